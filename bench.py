@@ -1,0 +1,224 @@
+#!/usr/bin/env python
+"""Throughput of hash-blocked TSDF fusion on one MI355X.
+
+Workload: a 300-frame, 640x480 orbit through a 4 m room with 20 random boxes and
+spheres (voxel 5 mm, truncation 2 cm, table of 2^20 slots, pool of 2^18 blocks),
+fused frame by frame through the C ABI (the plain per-frame path).
+
+One step = reset the volume, then fuse all frames of the trajectory into it.
+Depth frames are resident in HBM before timing starts.  The JSON line reports
+points fused per second over the timed steps, per-frame GPU latency
+percentiles, the HBM roofline fraction of the fusion kernel on algorithmic
+bytes, and the CPU oracle's throughput on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "depth points fused/s + p50/p99 frame latency, batched-served vs plain"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_2608_08287_amd", "csrc", "tsdf_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fuse_kernel_room_orbit_640x480_traffic.json")
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_sha() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def algorithmic_bytes(n_pix: int, touched_blocks: int, new_blocks: int, touched_voxels: int) -> int:
+    """Bytes one fused frame must move at least.
+
+    depth read (4 per pixel) + one 16-byte table entry per touched block + a new
+    block's entry write and key (16 + 8) + read and write of 4-byte TSDF and weight
+    per touched voxel (16)."""
+    return 4 * n_pix + 16 * touched_blocks + 24 * new_blocks + 16 * touched_voxels
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--frames", type=int, default=300)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="approximate CPU time for the oracle baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", choices=["fused", "two_pass", "fused_no_remap"], default="fused")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the volume is not sharded across GPUs", file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_2608_08287_amd import scenes as S
+    from paper_2608_08287_amd import tsdf as T
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    torch.cuda.set_device(0)
+    flags = {"fused": T.FUSE_DEFAULT, "two_pass": T.FUSE_TWO_PASS,
+             "fused_no_remap": T.FUSE_NO_XCD_REMAP}[args.mode]
+
+    # ---- inputs, resident in HBM ---------------------------------------------
+    t0 = time.time()
+    w = S.room_trajectory_workload(n_frames=300, frames=range(args.frames), device="cuda")
+    depth = [torch.from_numpy(d).cuda() for d in w.depth]
+    cams = [T.camera_struct(c) for c in w.cameras]
+    n_pix = w.depth[0].size
+    log(f"[bench] generated {len(depth)} frames in {time.time() - t0:.1f}s")
+
+    vol = T.Volume(w.voxel_size, w.trunc, w.table_capacity, w.pool_capacity)
+    L = T.lib()
+    stream = torch.cuda.current_stream()
+    sp = T.C.c_void_p(stream.cuda_stream)
+    h = vol.handle
+    ptrs = [T.C.c_void_p(d.data_ptr()) for d in depth]
+    cam_refs = [T.C.byref(c) for c in cams]
+
+    def fuse_all(events=None):
+        if L.tsdf_reset_volume(h, sp) != T.OK:
+            raise RuntimeError("reset failed")
+        for k in range(len(ptrs)):
+            if events is not None:
+                events[k].record(stream)
+            if L.tsdf_fuse_frame_ex(h, ptrs[k], cam_refs[k], flags, sp) != T.OK:
+                raise RuntimeError("fuse failed")
+        if events is not None:
+            events[len(ptrs)].record(stream)
+
+    # ---- correctness gate and algorithmic-byte accounting (untimed) ----------
+    vol.reset()
+    acc_bytes, acc = [], {"V": 0, "Bt": 0, "Bn": 0}
+    prev_blocks = 0
+    wv = vol.weight_view()
+    for k in range(len(ptrs)):
+        before = wv[:prev_blocks].clone()
+        vol.fuse(depth[k], cams[k], flags)
+        st = vol.stats()
+        nb = st.blocks_total
+        after = wv[:nb]
+        changed = after != torch.nn.functional.pad(before, (0, 0, 0, nb - prev_blocks))
+        V = int(changed.sum())
+        Bt = int(changed.any(dim=1).sum())
+        Bn = nb - prev_blocks
+        acc_bytes.append(algorithmic_bytes(n_pix, Bt, Bn, V))
+        acc["V"] += V
+        acc["Bt"] += Bt
+        acc["Bn"] += Bn
+        prev_blocks = nb
+    st = vol.stats()
+    if st.status != T.OK or st.pairs_dropped or st.lookup_misses:
+        print(f"correctness gate failed: {T.status_str(st.status)} dropped={st.pairs_dropped}",
+              file=sys.stderr)
+        return 1
+    points_per_step = st.points_valid
+    log(f"[bench] gate ok: {st.points_valid} points, {st.pairs} pairs, {st.blocks_total} blocks, "
+        f"max probe {st.max_probe}, load factor {st.blocks_total / w.table_capacity:.3f}")
+
+    # ---- warmup, then the timed steps ----------------------------------------
+    for _ in range(args.warmup):
+        fuse_all()
+    torch.cuda.synchronize()
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(len(ptrs) + 1)]
+              for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for s in range(args.steps):
+        fuse_all(events[s])
+    torch.cuda.synchronize()
+    t_end = time.perf_counter()
+    wall = t_end - t_start
+    frame_ms = np.array([[events[s][k].elapsed_time(events[s][k + 1]) for k in range(len(ptrs))]
+                         for s in range(args.steps)])
+    st = vol.stats()
+    if st.status != T.OK or st.pairs_dropped or st.points_valid != points_per_step:
+        print("timed run changed the result", file=sys.stderr)
+        return 1
+
+    value = points_per_step * args.steps / wall
+    mean_frame_ms = float(frame_ms.mean())
+    achieved = float(np.mean(acc_bytes)) / (mean_frame_ms * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        tr = json.load(open(TRAFFIC_FILE))
+        if tr.get("kernel_sha") == kernel_sha() and tr.get("mode") == args.mode:
+            traffic = tr.get("bytes_per_launch")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        n_cpu = 1
+        t_c0 = time.perf_counter()
+        ov = O.OracleVolume(w.voxel_size, w.trunc, w.pool_capacity)
+        pts = 0
+        k = 0
+        while k < len(w.depth) and (k < n_cpu or time.perf_counter() - t_c0 < args.cpu_seconds):
+            ov.fuse(w.depth[k], w.cameras[k])
+            k += 1
+        t_c = time.perf_counter() - t_c0
+        pts = ov.stats()["points_valid"]
+        cpu = {"value": pts / t_c, "unit": "points/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {k} of {len(w.depth)} frames fused sequentially into one volume "
+                         f"({pts} points, {t_c:.1f} s, one thread)"}
+        log(f"[bench] cpu oracle: {pts / t_c:.3e} points/s over {k} frames")
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"room orbit, {len(ptrs)} frames of 640x480, voxel 5 mm, truncation 2 cm, "
+                        f"table 2^20 slots, pool 2^18 blocks, plain per-frame path",
+            "path": "plain", "mode": args.mode, "frames_per_step": len(ptrs),
+            "points_per_step": points_per_step, "parallelism": "single GPU",
+        },
+        "p50_frame_ms": float(np.percentile(frame_ms, 50)),
+        "p95_frame_ms": float(np.percentile(frame_ms, 95)),
+        "p99_frame_ms": float(np.percentile(frame_ms, 99)),
+        "frame_samples": int(frame_ms.size),
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": "fuse_kernel<4, fused>" if args.mode != "two_pass" else "allocate+integrate",
+            "algorithmic_bytes_per_launch": float(np.mean(acc_bytes)),
+            "mean_launch_ms": mean_frame_ms,
+            "touched_voxels_per_frame": acc["V"] / len(ptrs),
+            "touched_blocks_per_frame": acc["Bt"] / len(ptrs),
+            "new_blocks_per_frame": acc["Bn"] / len(ptrs),
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,196 @@
+/*
+ * tsdf.h -- C ABI of libtsdf.so: hash-blocked TSDF fusion on one AMD Instinct
+ * MI355X (gfx950).
+ *
+ * The operation is the two-stage fusion kernel of "What Irregularity Costs"
+ * (Section 2): an irregular *allocate* stage walks every depth point's truncation
+ * band, maps each touched voxel to its 8^3 block, and makes sure the block exists
+ * in an open-addressed, linear-probe hash table (16-byte entries keyed by the
+ * packed 64-bit block coordinate of Section 2.1, inserted by compare-exchange
+ * with the two-step publication of Section 2.3); a regular *integrate* stage
+ * walks the same band and adds truncated signed distances and unit weights into a
+ * flat structure-of-arrays voxel pool that stores sums, so that means are
+ * recovered only at extraction (Section 2.2).
+ *
+ * Conventions for every call:
+ *  - Every call returns a tsdf_status.  No call aborts, prints or throws.
+ *  - Arguments that are invalid are detected on the host; the call then returns
+ *    TSDF_ERR_INVALID_ARGUMENT and enqueues nothing.
+ *  - Device memory is owned by the caller: the volume arena, depth frames and
+ *    extraction outputs are device pointers the caller allocated (with
+ *    hipMalloc, or a framework's allocator) and keeps alive while work that uses
+ *    them may still run.  The library owns only the small host handle made by
+ *    tsdf_create_volume and allocates no device memory at any time.
+ *  - `hip_stream` is a hipStream_t (NULL = the null stream).  All device work is
+ *    enqueued on it in call order; only tsdf_query_status and
+ *    tsdf_extract_blocks wait on it.  One volume must not be used from two
+ *    streams at once.
+ *  - Capacity problems met on the device (a full pool, a full table, voxel
+ *    coordinates beyond the 21-bit key range) never lose data silently: they are
+ *    counted, latched as sticky status bits in the volume, and reported by the
+ *    next tsdf_query_status.
+ */
+#ifndef TSDF_H_
+#define TSDF_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum tsdf_status {
+  TSDF_OK = 0,
+  TSDF_ERR_INVALID_ARGUMENT = 1,
+  TSDF_ERR_BUFFER_TOO_SMALL = 2,  /* extraction output smaller than the block count */
+  TSDF_ERR_POOL_EXHAUSTED = 3,    /* a new block found the pool full (sticky) */
+  TSDF_ERR_TABLE_FULL = 4,        /* a key found neither itself nor a free slot (sticky) */
+  TSDF_ERR_COORD_RANGE = 5,       /* a sample's voxel lies outside the key range (sticky) */
+  TSDF_ERR_INTERNAL = 6,          /* an invariant broke on the device (sticky) */
+  TSDF_ERR_HIP = 7                /* a HIP runtime call failed */
+} tsdf_status;
+
+/* Sticky status bits, as returned in tsdf_stats.status_bits. */
+#define TSDF_FLAG_POOL_EXHAUSTED 0x1u
+#define TSDF_FLAG_TABLE_FULL 0x2u
+#define TSDF_FLAG_COORD_RANGE 0x4u
+#define TSDF_FLAG_INTERNAL 0x8u
+
+/* Block and table geometry (Section 2.1). */
+#define TSDF_BLOCK_EDGE 8u
+#define TSDF_BLOCK_VOXELS 512u
+#define TSDF_EMPTY_KEY 0xFFFFFFFFFFFFFFFFull /* never a packed key: those use 63 bits */
+#define TSDF_MAX_POOL_BLOCKS ((1u << 22) - 1u) /* keeps voxel indices below 2^31 */
+#define TSDF_MAX_BAND_HALF 8 /* round(trunc / voxel_size) must lie in [1, 8] */
+
+typedef struct tsdf_volume_params {
+  float voxel_size;        /* voxel edge in metres, finite and > 0 */
+  float trunc;             /* truncation distance tau in metres, finite; the band
+                              walk takes 2K+1 samples, K = round(trunc/voxel_size),
+                              and K must lie in [1, TSDF_MAX_BAND_HALF] */
+  uint32_t table_capacity; /* hash-table slots C >= 1 (any value, not only powers
+                              of two); 0 selects the paper's sizing, the next power
+                              of two >= 2 * pool_capacity (Section 2.1) */
+  uint32_t pool_capacity;  /* voxel blocks P, 1 .. TSDF_MAX_POOL_BLOCKS */
+} tsdf_volume_params;
+
+typedef struct tsdf_camera {
+  uint32_t width, height;  /* depth image size; width * height <= 2^31 */
+  float fx, fy, cx, cy;    /* pinhole intrinsics in pixels, finite, fx, fy != 0;
+                              pixel (x, y) looks along ((x - cx)/fx, (y - cy)/fy, 1) */
+  float pose[12];          /* camera->world [R | t], row-major 3x4, finite
+                              (R = pose[0..2], pose[4..6], pose[8..10]) */
+} tsdf_camera;
+
+/* Cumulative counters since tsdf_create_volume / tsdf_reset_volume. */
+typedef struct tsdf_stats {
+  uint64_t points_valid;       /* pixels with finite depth > 0 that were fused */
+  uint64_t pairs;              /* (point, voxel) contributions that passed the walk */
+  uint64_t pairs_dropped;      /* contributions lost to a full pool or table */
+  uint64_t coord_out_of_range; /* band samples whose voxel cannot be keyed */
+  uint32_t blocks_total;       /* allocated pool blocks, <= pool_capacity */
+  uint32_t keys_pool_overflow; /* distinct keys that found the pool full */
+  uint32_t table_full_events;  /* failed insertions into a full table (one per
+                                  workgroup and key, so a key can count twice) */
+  uint32_t max_probe;          /* longest probe distance met (slots past home) */
+  uint32_t lookup_misses;      /* two-pass mode: integrate found no key */
+  uint32_t status_bits;        /* TSDF_FLAG_* */
+  uint32_t frames;             /* frames fused */
+  uint32_t reserved;
+} tsdf_stats;
+
+/* Byte offsets of the regions carved from the caller's arena; all 256-aligned.
+ *   counters   : 8192 bytes of device counters (internal format)
+ *   table      : table_capacity entries of 16 bytes: {uint64 key; int32 block;
+ *                uint32 pad}, key TSDF_EMPTY_KEY when free; block >= 0 is a pool
+ *                index, -1 = being published, -2 = the pool was full
+ *   block_keys : pool_capacity uint64, the key of each allocated pool block
+ *   tsdf       : pool_capacity * 512 float, the sum of truncated signed distances
+ *   weight     : pool_capacity * 512 float, the number of contributions
+ * Voxel (lx, ly, lz) of pool block b lives at index b * 512 + (lz * 8 + ly) * 8 + lx
+ * of both arrays (x fastest). */
+typedef struct tsdf_layout {
+  uint64_t counters, table, block_keys, tsdf, weight, total_bytes;
+  uint32_t table_capacity, pool_capacity;
+} tsdf_layout;
+
+typedef struct tsdf_volume tsdf_volume;
+
+/* Arena bytes the volume needs; 0 if `params` is invalid. */
+size_t tsdf_volume_bytes(const tsdf_volume_params* params);
+
+/* Region offsets for `params` (see tsdf_layout). */
+tsdf_status tsdf_volume_layout(const tsdf_volume_params* params, tsdf_layout* out);
+
+/* Make a volume over the caller's device arena (>= tsdf_volume_bytes bytes,
+ * 256-byte aligned) and enqueue its initialisation on `hip_stream`: empty table,
+ * zero pool, zero counters.  *out receives a host handle. */
+tsdf_status tsdf_create_volume(const tsdf_volume_params* params, void* dev_arena,
+                               size_t arena_bytes, void* hip_stream, tsdf_volume** out);
+
+/* Free the host handle.  The arena is the caller's and is not touched. */
+tsdf_status tsdf_destroy_volume(tsdf_volume* vol);
+
+/* Enqueue an empty table, zero counters and zeroed pool blocks (only the
+ * blocks that were handed out are cleared; the rest are still zero). */
+tsdf_status tsdf_reset_volume(tsdf_volume* vol, void* hip_stream);
+
+/* Fuse one depth frame (Section 2.2: allocate then integrate).  `depth_dev` is
+ * height x width float32 metres, row-major, camera-frame z; pixels that are not
+ * finite or not > 0 are not points.  Asynchronous: returns once enqueued. */
+tsdf_status tsdf_fuse_frame(tsdf_volume* vol, const float* depth_dev, const tsdf_camera* cam,
+                            void* hip_stream);
+
+/* As tsdf_fuse_frame with a choice of kernel structure:
+ *   TSDF_FUSE_DEFAULT   one fused launch (allocate and integrate per workgroup)
+ *   TSDF_FUSE_TWO_PASS  two launches, allocate over all points then integrate
+ *                       over all points, as in Section 2.2
+ *   TSDF_FUSE_ALLOCATE_ONLY / TSDF_FUSE_INTEGRATE_ONLY  one stage of TWO_PASS
+ *                       (for stage timing; integrate-only assumes the frame's
+ *                       blocks were allocated before)
+ *   | TSDF_FUSE_NO_XCD_REMAP  dispatch tiles in plain row-major order instead of
+ *                       giving each XCD a contiguous band of the image
+ * Results are identical for every choice (up to float summation order). */
+#define TSDF_FUSE_DEFAULT 0u
+#define TSDF_FUSE_TWO_PASS 1u
+#define TSDF_FUSE_ALLOCATE_ONLY 2u
+#define TSDF_FUSE_INTEGRATE_ONLY 3u
+#define TSDF_FUSE_MODE_MASK 3u
+#define TSDF_FUSE_NO_XCD_REMAP 0x100u
+tsdf_status tsdf_fuse_frame_ex(tsdf_volume* vol, const float* depth_dev, const tsdf_camera* cam,
+                               uint32_t flags, void* hip_stream);
+
+/* Wait for `hip_stream`, read the counters and return the most severe sticky
+ * condition (INTERNAL > TABLE_FULL > POOL_EXHAUSTED > COORD_RANGE), or TSDF_OK.
+ * `out` may be NULL. */
+tsdf_status tsdf_query_status(tsdf_volume* vol, void* hip_stream, tsdf_stats* out);
+
+/* Wait for `hip_stream` to learn the block count n, then, if n <= max_blocks,
+ * enqueue the extraction of every allocated block in pool order:
+ *   keys_dev[i]          packed key of pool block i          (n uint64)
+ *   tsdf_dev[i*512 + l]  mean TSDF = sum / weight, 0 where the weight is 0
+ *   weight_dev[i*512+l]  weight                              (n * 512 float)
+ * Any output pointer may be NULL to skip it.  *n_blocks_out = n always.
+ * Returns TSDF_ERR_BUFFER_TOO_SMALL (nothing enqueued) if n > max_blocks.  The
+ * outputs are complete once `hip_stream` has drained. */
+tsdf_status tsdf_extract_blocks(tsdf_volume* vol, void* hip_stream, uint32_t max_blocks,
+                                uint64_t* keys_dev, float* tsdf_dev, float* weight_dev,
+                                uint32_t* n_blocks_out);
+
+/* Allocate pool blocks for `n` block coordinates (device array of n rows of
+ * int32 bx, by, bz, each in [-2^20, 2^20)) through the same insertion protocol
+ * as fusion, as if a frame had touched them.  Used to pre-fill a table to a
+ * chosen load factor.  Coordinates out of range are counted as
+ * coord_out_of_range and skipped. */
+tsdf_status tsdf_insert_blocks(tsdf_volume* vol, const int32_t* block_coords_dev, uint32_t n,
+                               void* hip_stream);
+
+/* Static text for a status code. */
+const char* tsdf_status_str(tsdf_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TSDF_H_ */

@@ -1,0 +1,39 @@
+"""Build ``libtsdf.so`` (HIP for gfx950) in-tree with hipcc.
+
+Compile flags that the kernels rely on:
+  -ffp-contract=off     the band walk must round every float32 operation
+                        separately (no FMA) so voxel choices are exact;
+  -munsafe-fp-atomics   float atomic adds become the hardware instruction
+                        instead of a compare-exchange loop (the pool lives in
+                        ordinary device memory, where that instruction is exact);
+  -Xclang -target-feature -Xclang -packed-fp32-ops
+                        no packed fp32 math is generated.
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+OUT = os.path.join(HERE, "libtsdf.so")
+SOURCES = [os.path.join(CSRC, "tsdf_api.cpp"), os.path.join(CSRC, "tsdf_kernels.hip")]
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+FLAGS = ["-x", "hip", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+         "-ffp-contract=off", "-munsafe-fp-atomics",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-Wall", "-Wno-unused-function", f"-I{os.path.join(ROOT, 'include')}"]
+
+
+def build(verbose: bool = False, extra=()) -> str:
+    cmd = [HIPCC, *FLAGS, *extra, *SOURCES, "-o", OUT + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(OUT + ".tmp", OUT)
+    return OUT
+
+
+if __name__ == "__main__":
+    build(verbose="-v" in sys.argv)

@@ -1,0 +1,288 @@
+// Host half of libtsdf.so: argument checking, arena carving, launches and
+// status read-back for the C ABI declared in include/tsdf.h.
+//
+// Every entry point validates on the host and returns before enqueuing anything
+// if an argument is wrong.  No entry point allocates device memory; the only
+// host allocation is the volume handle.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "../../include/tsdf.h"
+#include "tsdf_internal.h"
+
+struct tsdf_volume {
+  tsdf_volume_params params;
+  tsdf_layout layout;
+  tsdf::VolumeDev dev;
+  uint32_t frames;
+};
+
+namespace {
+
+constexpr uint64_t kAlign = 256;
+
+uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool finite(float x) { return std::isfinite(x); }
+
+uint32_t next_pow2_at_least(uint64_t x) {
+  uint64_t p = 1;
+  while (p < x) p <<= 1;
+  return p > 0xFFFFFFFFull ? 0u : (uint32_t)p;
+}
+
+int band_half(const tsdf_volume_params& p) {
+  return (int)std::llround((double)p.trunc / (double)p.voxel_size);
+}
+
+// Fills `out` for valid params; returns false otherwise.
+bool make_layout(const tsdf_volume_params* p, tsdf_layout* out) {
+  if (!p) return false;
+  if (!finite(p->voxel_size) || !(p->voxel_size > 0.0f)) return false;
+  if (!finite(p->trunc) || !(p->trunc > 0.0f)) return false;
+  const int K = band_half(*p);
+  if (K < 1 || K > TSDF_MAX_BAND_HALF) return false;
+  if (p->pool_capacity < 1 || p->pool_capacity > TSDF_MAX_POOL_BLOCKS) return false;
+  uint32_t C = p->table_capacity;
+  if (C == 0) C = next_pow2_at_least(2ull * p->pool_capacity);
+  if (C == 0) return false;
+  tsdf_layout L;
+  std::memset(&L, 0, sizeof(L));
+  uint64_t off = 0;
+  L.counters = off;
+  off = align_up(off + tsdf::kCountersBytes);
+  L.table = off;
+  off = align_up(off + (uint64_t)C * sizeof(tsdf::TableEntry));
+  L.block_keys = off;
+  off = align_up(off + (uint64_t)p->pool_capacity * 8ull);
+  L.tsdf = off;
+  off = align_up(off + (uint64_t)p->pool_capacity * TSDF_BLOCK_VOXELS * 4ull);
+  L.weight = off;
+  off = align_up(off + (uint64_t)p->pool_capacity * TSDF_BLOCK_VOXELS * 4ull);
+  L.total_bytes = off;
+  L.table_capacity = C;
+  L.pool_capacity = p->pool_capacity;
+  *out = L;
+  return true;
+}
+
+hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+tsdf_status hip_status(hipError_t e) { return e == hipSuccess ? TSDF_OK : TSDF_ERR_HIP; }
+
+tsdf_status init_table_and_counters(tsdf_volume* v, hipStream_t s) {
+  const tsdf_layout& L = v->layout;
+  hipError_t e = tsdf::launch_fill_u32(v->dev.table, 0xFFFFFFFFu,
+                                        (size_t)L.table_capacity * (sizeof(tsdf::TableEntry) / 4), s);
+  if (e == hipSuccess) e = tsdf::launch_fill_u32(v->dev.ctr, 0u, tsdf::kCountersBytes / 4, s);
+  return hip_status(e);
+}
+
+bool valid_camera(const tsdf_camera* c) {
+  if (!c) return false;
+  if ((uint64_t)c->width * (uint64_t)c->height > (1ull << 31)) return false;
+  if (!finite(c->fx) || !finite(c->fy) || !finite(c->cx) || !finite(c->cy)) return false;
+  if (c->fx == 0.0f || c->fy == 0.0f) return false;
+  for (int i = 0; i < 12; ++i)
+    if (!finite(c->pose[i])) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t tsdf_volume_bytes(const tsdf_volume_params* params) {
+  tsdf_layout L;
+  return make_layout(params, &L) ? (size_t)L.total_bytes : 0;
+}
+
+tsdf_status tsdf_volume_layout(const tsdf_volume_params* params, tsdf_layout* out) {
+  if (!out) return TSDF_ERR_INVALID_ARGUMENT;
+  return make_layout(params, out) ? TSDF_OK : TSDF_ERR_INVALID_ARGUMENT;
+}
+
+tsdf_status tsdf_create_volume(const tsdf_volume_params* params, void* dev_arena,
+                               size_t arena_bytes, void* hip_stream, tsdf_volume** out) {
+  if (!out) return TSDF_ERR_INVALID_ARGUMENT;
+  *out = nullptr;
+  tsdf_layout L;
+  if (!make_layout(params, &L)) return TSDF_ERR_INVALID_ARGUMENT;
+  if (!dev_arena || ((uintptr_t)dev_arena % kAlign) != 0) return TSDF_ERR_INVALID_ARGUMENT;
+  if (arena_bytes < L.total_bytes) return TSDF_ERR_BUFFER_TOO_SMALL;
+  tsdf_volume* v = static_cast<tsdf_volume*>(std::malloc(sizeof(tsdf_volume)));
+  if (!v) return TSDF_ERR_INTERNAL;
+  v->params = *params;
+  v->layout = L;
+  v->frames = 0;
+  char* base = static_cast<char*>(dev_arena);
+  v->dev.ctr = reinterpret_cast<tsdf::DevCounters*>(base + L.counters);
+  v->dev.table = reinterpret_cast<tsdf::TableEntry*>(base + L.table);
+  v->dev.block_keys = reinterpret_cast<unsigned long long*>(base + L.block_keys);
+  v->dev.tsdf = reinterpret_cast<float*>(base + L.tsdf);
+  v->dev.weight = reinterpret_cast<float*>(base + L.weight);
+  v->dev.table_capacity = L.table_capacity;
+  v->dev.pool_capacity = L.pool_capacity;
+  hipStream_t s = as_stream(hip_stream);
+  tsdf_status st = init_table_and_counters(v, s);
+  const size_t pool_words = (size_t)L.pool_capacity * TSDF_BLOCK_VOXELS;
+  if (st == TSDF_OK) st = hip_status(tsdf::launch_fill_u32(v->dev.tsdf, 0u, pool_words, s));
+  if (st == TSDF_OK) st = hip_status(tsdf::launch_fill_u32(v->dev.weight, 0u, pool_words, s));
+  if (st == TSDF_OK)
+    st = hip_status(tsdf::launch_fill_u32(v->dev.block_keys, 0xFFFFFFFFu,
+                                          (size_t)L.pool_capacity * 2, s));
+  if (st != TSDF_OK) {
+    std::free(v);
+    return st;
+  }
+  *out = v;
+  return TSDF_OK;
+}
+
+tsdf_status tsdf_destroy_volume(tsdf_volume* vol) {
+  if (!vol) return TSDF_ERR_INVALID_ARGUMENT;
+  std::free(vol);
+  return TSDF_OK;
+}
+
+tsdf_status tsdf_reset_volume(tsdf_volume* vol, void* hip_stream) {
+  if (!vol) return TSDF_ERR_INVALID_ARGUMENT;
+  hipStream_t s = as_stream(hip_stream);
+  // the used-block clear reads the bump counter, so it runs before the counters
+  // are zeroed (same stream, in order)
+  tsdf_status st = hip_status(tsdf::launch_reset_used(vol->dev, s));
+  if (st == TSDF_OK) st = init_table_and_counters(vol, s);
+  if (st == TSDF_OK) vol->frames = 0;
+  return st;
+}
+
+tsdf_status tsdf_fuse_frame_ex(tsdf_volume* vol, const float* depth_dev, const tsdf_camera* cam,
+                               uint32_t flags, void* hip_stream) {
+  if (!vol || !valid_camera(cam)) return TSDF_ERR_INVALID_ARGUMENT;
+  if ((flags & ~(TSDF_FUSE_MODE_MASK | TSDF_FUSE_NO_XCD_REMAP)) != 0)
+    return TSDF_ERR_INVALID_ARGUMENT;
+  const uint64_t n_pix = (uint64_t)cam->width * cam->height;
+  if (n_pix > 0 && !depth_dev) return TSDF_ERR_INVALID_ARGUMENT;
+  tsdf::FrameDev f;
+  f.depth = depth_dev;
+  f.width = cam->width;
+  f.height = cam->height;
+  f.cx = cam->cx;
+  f.cy = cam->cy;
+  f.ifx = 1.0f / cam->fx;
+  f.ify = 1.0f / cam->fy;
+  for (int r = 0; r < 3; ++r) {
+    for (int c = 0; c < 3; ++c) f.R[3 * r + c] = cam->pose[4 * r + c];
+    f.t[r] = cam->pose[4 * r + 3];
+  }
+  f.v = vol->params.voxel_size;
+  f.iv = 1.0f / vol->params.voxel_size;
+  f.trunc = vol->params.trunc;
+  f.K = band_half(vol->params);
+  const bool remap = (flags & TSDF_FUSE_NO_XCD_REMAP) == 0;
+  hipStream_t s = as_stream(hip_stream);
+  hipError_t e = hipSuccess;
+  if (n_pix > 0) {
+    switch (flags & TSDF_FUSE_MODE_MASK) {
+      case TSDF_FUSE_DEFAULT:
+        e = tsdf::launch_fuse(vol->dev, f, tsdf::FuseMode::kFused, remap, s);
+        break;
+      case TSDF_FUSE_TWO_PASS:
+        e = tsdf::launch_fuse(vol->dev, f, tsdf::FuseMode::kAllocate, remap, s);
+        if (e == hipSuccess) e = tsdf::launch_fuse(vol->dev, f, tsdf::FuseMode::kIntegrate, remap, s);
+        break;
+      case TSDF_FUSE_ALLOCATE_ONLY:
+        e = tsdf::launch_fuse(vol->dev, f, tsdf::FuseMode::kAllocate, remap, s);
+        break;
+      case TSDF_FUSE_INTEGRATE_ONLY:
+        e = tsdf::launch_fuse(vol->dev, f, tsdf::FuseMode::kIntegrate, remap, s);
+        break;
+    }
+  }
+  if (e != hipSuccess) return TSDF_ERR_HIP;
+  if ((flags & TSDF_FUSE_MODE_MASK) != TSDF_FUSE_ALLOCATE_ONLY) vol->frames++;
+  return TSDF_OK;
+}
+
+tsdf_status tsdf_fuse_frame(tsdf_volume* vol, const float* depth_dev, const tsdf_camera* cam,
+                            void* hip_stream) {
+  return tsdf_fuse_frame_ex(vol, depth_dev, cam, TSDF_FUSE_DEFAULT, hip_stream);
+}
+
+tsdf_status tsdf_query_status(tsdf_volume* vol, void* hip_stream, tsdf_stats* out) {
+  if (!vol) return TSDF_ERR_INVALID_ARGUMENT;
+  hipStream_t s = as_stream(hip_stream);
+  tsdf::DevCounters c;
+  if (hipMemcpyAsync(&c, vol->dev.ctr, sizeof(c), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return TSDF_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return TSDF_ERR_HIP;
+  uint32_t bits = c.status_bits;
+  if (c.coord_out_of_range) bits |= TSDF_FLAG_COORD_RANGE;
+  if (out) {
+    std::memset(out, 0, sizeof(*out));
+    for (unsigned i = 0; i < tsdf::kCounterShards; ++i) {
+      out->points_valid += c.points_valid[i];
+      out->pairs += c.pairs[i];
+    }
+    out->pairs_dropped = c.pairs_dropped;
+    out->coord_out_of_range = c.coord_out_of_range;
+    out->blocks_total = c.block_count < vol->layout.pool_capacity ? c.block_count
+                                                                  : vol->layout.pool_capacity;
+    out->keys_pool_overflow = c.keys_pool_overflow;
+    out->table_full_events = c.table_full_events;
+    out->max_probe = c.max_probe;
+    out->lookup_misses = c.lookup_misses;
+    out->status_bits = bits;
+    out->frames = vol->frames;
+  }
+  if (bits & TSDF_FLAG_INTERNAL) return TSDF_ERR_INTERNAL;
+  if (bits & TSDF_FLAG_TABLE_FULL) return TSDF_ERR_TABLE_FULL;
+  if (bits & TSDF_FLAG_POOL_EXHAUSTED) return TSDF_ERR_POOL_EXHAUSTED;
+  if (bits & TSDF_FLAG_COORD_RANGE) return TSDF_ERR_COORD_RANGE;
+  return TSDF_OK;
+}
+
+tsdf_status tsdf_extract_blocks(tsdf_volume* vol, void* hip_stream, uint32_t max_blocks,
+                                uint64_t* keys_dev, float* tsdf_dev, float* weight_dev,
+                                uint32_t* n_blocks_out) {
+  if (!vol || !n_blocks_out) return TSDF_ERR_INVALID_ARGUMENT;
+  hipStream_t s = as_stream(hip_stream);
+  unsigned count = 0;
+  if (hipMemcpyAsync(&count, &vol->dev.ctr->block_count, sizeof(count), hipMemcpyDeviceToHost,
+                     s) != hipSuccess)
+    return TSDF_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return TSDF_ERR_HIP;
+  const uint32_t n = count < vol->layout.pool_capacity ? count : vol->layout.pool_capacity;
+  *n_blocks_out = n;
+  if (n > max_blocks) return TSDF_ERR_BUFFER_TOO_SMALL;
+  return hip_status(tsdf::launch_extract(vol->dev, n, reinterpret_cast<unsigned long long*>(keys_dev),
+                                         tsdf_dev, weight_dev, s));
+}
+
+tsdf_status tsdf_insert_blocks(tsdf_volume* vol, const int32_t* block_coords_dev, uint32_t n,
+                               void* hip_stream) {
+  if (!vol || (n > 0 && !block_coords_dev)) return TSDF_ERR_INVALID_ARGUMENT;
+  return hip_status(tsdf::launch_insert_blocks(vol->dev, block_coords_dev, n, as_stream(hip_stream)));
+}
+
+const char* tsdf_status_str(tsdf_status status) {
+  switch (status) {
+    case TSDF_OK: return "ok";
+    case TSDF_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case TSDF_ERR_BUFFER_TOO_SMALL: return "buffer too small";
+    case TSDF_ERR_POOL_EXHAUSTED: return "voxel pool exhausted";
+    case TSDF_ERR_TABLE_FULL: return "hash table full";
+    case TSDF_ERR_COORD_RANGE: return "voxel coordinate outside the key range";
+    case TSDF_ERR_INTERNAL: return "internal invariant violated";
+    case TSDF_ERR_HIP: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,81 @@
+// Internal declarations shared by the host half (tsdf_api.cpp) and the device
+// half (tsdf_kernels.hip) of libtsdf.so.  Not installed, not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tsdf {
+
+// One hash-table slot (Section 2.1): 64-bit packed key, 32-bit pool index,
+// 4 bytes of padding -> 16 bytes, read with one 128-bit load.
+struct alignas(16) TableEntry {
+  unsigned long long key;
+  int block;
+  unsigned pad;
+};
+static_assert(sizeof(TableEntry) == 16, "16-byte entries");
+
+constexpr int kBlockPublishing = -1;  // key claimed, pool index not yet stored
+constexpr int kBlockPoolFull = -2;    // key claimed, the pool had no block left
+constexpr int kBlockTableFull = -3;   // (never stored) resolution failed: table full
+constexpr unsigned long long kEmptyKey = ~0ull;
+
+// Device counters.  The 512-byte header holds the allocation state and the loss
+// counters on separate 128-byte lines; the per-frame traffic counters, which
+// every wave adds to, are spread over kCounterShards lines' worth of slots so
+// that no single address takes one atomic per wave of the whole grid.
+constexpr unsigned kCounterShards = 256;
+struct DevCounters {
+  // line 0: allocation
+  unsigned block_count;         // pool bump allocator (may run past the capacity)
+  unsigned status_bits;         // sticky TSDF_FLAG_*
+  unsigned keys_pool_overflow;
+  unsigned table_full_events;
+  unsigned max_probe;
+  unsigned lookup_misses;
+  unsigned pad0[26];
+  // line 1: losses
+  unsigned long long pairs_dropped;
+  unsigned long long coord_out_of_range;
+  unsigned long long pad1[14];
+  unsigned long long pad2[32];
+  // sharded traffic counters (summed on the host)
+  unsigned long long points_valid[kCounterShards];
+  unsigned long long pairs[kCounterShards];
+};
+static_assert(sizeof(DevCounters) == 512 + 2 * 8 * kCounterShards, "counter layout");
+constexpr size_t kCountersBytes = 8192;
+static_assert(sizeof(DevCounters) <= kCountersBytes, "counters fit their region");
+
+struct VolumeDev {
+  DevCounters* ctr;
+  TableEntry* table;
+  unsigned long long* block_keys;
+  float* tsdf;
+  float* weight;
+  unsigned table_capacity;
+  unsigned pool_capacity;
+};
+
+struct FrameDev {
+  const float* depth;
+  unsigned width, height;
+  float cx, cy, ifx, ify;  // 1/fx, 1/fy rounded once to float32
+  float R[9];              // camera->world rotation, row-major
+  float t[3];
+  float v, iv, trunc;      // voxel edge, 1/v (float32), truncation
+  int K;                   // band half-width in samples
+};
+
+enum class FuseMode : int { kFused = 0, kAllocate = 1, kIntegrate = 2 };
+
+hipError_t launch_fill_u32(void* ptr, unsigned value, size_t n_words, hipStream_t s);
+hipError_t launch_reset_used(VolumeDev vol, hipStream_t s);
+hipError_t launch_fuse(VolumeDev vol, const FrameDev& fr, FuseMode mode, bool xcd_remap,
+                       hipStream_t s);
+hipError_t launch_insert_blocks(VolumeDev vol, const int* coords, unsigned n, hipStream_t s);
+hipError_t launch_extract(VolumeDev vol, unsigned n_blocks, unsigned long long* keys,
+                          float* tsdf, float* weight, hipStream_t s);
+
+}  // namespace tsdf

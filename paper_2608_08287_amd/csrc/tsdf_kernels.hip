@@ -1,0 +1,612 @@
+// Device half of libtsdf.so: hash-blocked TSDF fusion kernels for gfx950.
+//
+// One workgroup of 256 lanes (4 wave64) owns a 16x16 pixel tile and runs three
+// phases separated by workgroup barriers:
+//
+//   1. walk   -- each lane walks its pixel's truncation band (2K+1 samples) and
+//                keeps, per sample, the voxel's in-block index and its truncated
+//                signed distance in registers.  The block keys of the tile are
+//                deduplicated into an LDS key set: per sample, a wave64 ballot
+//                loop elects one leader per distinct key, and only leaders touch
+//                the set.
+//   2. resolve -- each distinct key of the tile is resolved once against the
+//                global open-addressed table (Section 2.3's insert protocol):
+//                probe linearly from the home slot, plain first read of the
+//                entry, agent-scope compare-exchange on an empty slot, pool index
+//                from a bump counter (one atomic per wave), publication of the
+//                index with an agent-scope store.  The probe is unbounded up to a
+//                full cyclic scan and written as a converged step loop (every busy
+//                lane takes exactly one step per iteration and "waiting for a
+//                publication" means "look again next iteration"), so a waiter
+//                never spins while a publisher in its own wave is masked off.
+//   3. integrate -- each lane adds its contributions into the flat SoA pool with
+//                agent-scope float atomics, reading pool indices from LDS.
+//
+// A workgroup only ever accumulates into blocks whose indices it resolved itself,
+// so one launch needs no grid-wide barrier.  The two-pass structure of Section
+// 2.2 (allocate over all points, then integrate over all points) is the same
+// code with phase 3 switched off, or with phase 2 restricted to lookups.
+//
+// All walk arithmetic is float32 +, -, *, floor and comparisons in a fixed order
+// and this file must be compiled with -ffp-contract=off so that no FMA changes a
+// voxel choice.
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/tsdf.h"
+#include "tsdf_internal.h"
+
+namespace tsdf {
+namespace {
+
+constexpr int kTileW = 16;
+constexpr int kTileH = 16;
+constexpr int kThreads = kTileW * kTileH;  // 256 = 4 x wave64
+constexpr int kWave = 64;
+constexpr unsigned kSetCap = 1024;          // LDS key-set slots per workgroup
+constexpr unsigned kSetNone = 0x7FFu;       // "no LDS slot" (set full)
+// A publication is one store after the winner's compare-exchange, so a wait is a
+// handful of steps.  A wait this long means the invariant broke: report it as
+// INTERNAL instead of spinning forever.
+constexpr unsigned kMaxWaitSteps = 1u << 20;
+
+// ---------------------------------------------------------------------------
+// Keys and hashing
+// ---------------------------------------------------------------------------
+
+// Section 2.1: three 21-bit axes biased by 2^20, x in the top field.
+__device__ __forceinline__ unsigned long long pack_key(int bx, int by, int bz) {
+  return ((unsigned long long)(unsigned)(bx + (1 << 20)) << 42) |
+         ((unsigned long long)(unsigned)(by + (1 << 20)) << 21) |
+         (unsigned long long)(unsigned)(bz + (1 << 20));
+}
+
+// MurmurHash3 fmix64, then Lemire's multiply-shift range reduction of its high
+// word onto [0, C).  C need not be a power of two.
+__device__ __forceinline__ unsigned home_slot(unsigned long long k, unsigned C) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdull;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ull;
+  k ^= k >> 33;
+  return __umulhi((unsigned)(k >> 32), C);
+}
+
+// Slot of a key in the LDS set: Fibonacci hashing of the whole key.
+__device__ __forceinline__ unsigned set_home(unsigned long long k) {
+  return (unsigned)((k * 0x9E3779B97F4A7C15ull) >> 54) & (kSetCap - 1);
+}
+
+// ---------------------------------------------------------------------------
+// Wave helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ unsigned rank_in(unsigned long long mask) {
+  return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
+
+__device__ __forceinline__ unsigned long long readlane64(unsigned long long v, int l) {
+  const unsigned lo = __builtin_amdgcn_readlane((int)(unsigned)v, l);
+  const unsigned hi = __builtin_amdgcn_readlane((int)(unsigned)(v >> 32), l);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// Sum over the wave of a small non-negative per-lane count (< 32), by bit slices.
+__device__ __forceinline__ unsigned wave_sum_small(unsigned v) {
+  unsigned s = 0;
+#pragma unroll
+  for (int b = 0; b < 5; ++b) s += (unsigned)__popcll(__ballot((v >> b) & 1u)) << b;
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// Atomics.  Agent scope: workgroups on every XCD see one another's claims.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ unsigned long long cas_key(unsigned long long* p,
+                                                      unsigned long long expected,
+                                                      unsigned long long desired) {
+  __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+  return expected;  // the value seen in memory
+}
+
+__device__ __forceinline__ unsigned add_u32(unsigned* p, unsigned v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void add_u64(unsigned long long* p, unsigned long long v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void add_f32(float* p, float v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void set_flag(DevCounters* c, unsigned f) {
+  __hip_atomic_fetch_or(&c->status_bits, f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------------------
+// Section 2.3: find or insert one key.  Converged step loop over the busy lanes.
+// Returns the pool index, kBlockPoolFull, kBlockTableFull, or (lookup only)
+// kBlockTableFull for a key that is absent.
+// ---------------------------------------------------------------------------
+
+template <bool kInsert>
+__device__ int resolve_key(const VolumeDev& vol, unsigned long long want, bool active,
+                           unsigned& probes_out, bool& missing_out) {
+  const unsigned C = vol.table_capacity;
+  unsigned slot = active ? home_slot(want, C) : 0u;
+  unsigned probes = 0, waits = 0;
+  bool waiting = false, busy = active, missing = false, broken = false;
+  int result = kBlockTableFull;
+  while (busy) {
+    TableEntry* e = vol.table + slot;
+    bool won = false, advance = false;
+    if (waiting) {
+      // only while waiting is the index read with an atomic (coherent) load
+      const int b = __hip_atomic_load(&e->block, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (b != kBlockPublishing) {
+        result = b;
+        busy = false;
+      } else if (++waits >= kMaxWaitSteps) {
+        broken = true;
+        busy = false;
+      }
+    } else {
+      // plain, cacheable first read: a stale key costs one more step, a stale
+      // index only enters the wait
+      const TableEntry en = *e;
+      if (en.key == want) {
+        if (en.block != kBlockPublishing) {
+          result = en.block;
+          busy = false;
+        } else {
+          waiting = true;
+        }
+      } else if (en.key == kEmptyKey) {
+        if (kInsert) {
+          const unsigned long long prev = cas_key(&e->key, kEmptyKey, want);
+          if (prev == kEmptyKey) won = true;
+          else if (prev == want) waiting = true;
+          else advance = true;  // another key took the slot: keep probing
+        } else {
+          missing = true;  // lookup only: an empty slot ends the chain
+          busy = false;
+        }
+      } else {
+        advance = true;
+      }
+    }
+    if (advance) {
+      if (++probes >= C) {  // a full cyclic scan: the table is full
+        result = kBlockTableFull;
+        busy = false;
+      } else {
+        slot = (slot + 1 == C) ? 0u : slot + 1;
+      }
+    }
+    // winners take consecutive pool indices with one atomic per wave
+    const unsigned long long wmask = __ballot(won);
+    if (wmask) {
+      const int leader = __ffsll((long long)wmask) - 1;
+      unsigned base = 0;
+      if ((int)lane_id() == leader) base = add_u32(&vol.ctr->block_count, (unsigned)__popcll(wmask));
+      base = (unsigned)__builtin_amdgcn_readlane((int)base, leader);
+      if (won) {
+        const unsigned idx = base + rank_in(wmask);
+        int pub;
+        if (idx < vol.pool_capacity) {
+          vol.block_keys[idx] = want;  // read only after the launch: no fence needed
+          pub = (int)idx;
+        } else {
+          pub = kBlockPoolFull;
+          add_u32(&vol.ctr->keys_pool_overflow, 1u);
+          set_flag(vol.ctr, TSDF_FLAG_POOL_EXHAUSTED);
+        }
+        __hip_atomic_store(&e->block, pub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        result = pub;
+        busy = false;
+      }
+    }
+  }
+  // a pool index is used as an address only if it lies inside the pool
+  if (active && (broken || result >= (int)vol.pool_capacity || result < kBlockTableFull)) {
+    set_flag(vol.ctr, TSDF_FLAG_INTERNAL);
+    result = kBlockTableFull;
+    missing = true;  // counted as a loss, not as a full table
+  } else if (active && result == kBlockTableFull && !missing) {
+    add_u32(&vol.ctr->table_full_events, 1u);
+    set_flag(vol.ctr, TSDF_FLAG_TABLE_FULL);
+  }
+  probes_out = probes;
+  missing_out = missing;
+  return result;
+}
+
+// ---------------------------------------------------------------------------
+// The band walk of one sample (shared by every phase that needs a voxel).
+// ---------------------------------------------------------------------------
+
+struct Sample {
+  int vx, vy, vz;
+  float val;
+  bool in_range;  // the voxel can be keyed
+  bool keep;      // passes the occlusion test (meaningful when in_range)
+};
+
+__device__ __forceinline__ Sample walk_sample(const FrameDev& f, float d, float a, float b,
+                                              int k_minus_K) {
+  Sample s;
+  const float z = d + (float)k_minus_K * f.v;
+  const float xc = a * z, yc = b * z, zc = z;
+  float w[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    float acc = f.R[3 * r + 0] * xc;
+    acc = acc + f.R[3 * r + 1] * yc;
+    acc = acc + f.R[3 * r + 2] * zc;
+    w[r] = acc + f.t[r];
+  }
+  const float q0 = w[0] * f.iv, q1 = w[1] * f.iv, q2 = w[2] * f.iv;
+  s.in_range = (z > 0.0f) && (__builtin_fabsf(q0) < 8388608.0f) &&
+               (__builtin_fabsf(q1) < 8388608.0f) && (__builtin_fabsf(q2) < 8388608.0f);
+  s.vx = s.in_range ? (int)__builtin_floorf(q0) : 0;
+  s.vy = s.in_range ? (int)__builtin_floorf(q1) : 0;
+  s.vz = s.in_range ? (int)__builtin_floorf(q2) : 0;
+  const float c0 = ((float)s.vx + 0.5f) * f.v;
+  const float c1 = ((float)s.vy + 0.5f) * f.v;
+  const float c2 = ((float)s.vz + 0.5f) * f.v;
+  float zcv = f.R[2] * (c0 - f.t[0]);
+  zcv = zcv + f.R[5] * (c1 - f.t[1]);
+  zcv = zcv + f.R[8] * (c2 - f.t[2]);
+  const float sdf = d - zcv;
+  s.keep = (zcv > 0.0f) && !(sdf < -f.trunc);
+  s.val = sdf < f.trunc ? sdf : f.trunc;
+  return s;
+}
+
+// Per-sample state carried from phase 1 to phase 3 in one register:
+// bit 31 valid pair, bits 9..19 LDS slot (kSetNone when the set overflowed),
+// bits 0..8 in-block voxel index.
+constexpr unsigned kPairValid = 1u << 31;
+
+__device__ __forceinline__ unsigned tile_of_group(unsigned g, unsigned n_tiles, bool remap) {
+  if (!remap) return g;
+  // Workgroups are dealt round-robin to the 8 XCDs.  Give XCD j the j-th
+  // contiguous run of tiles so that neighbouring tiles, which share blocks and
+  // table entries, meet in the same L2.
+  const unsigned q = n_tiles >> 3, r = n_tiles & 7u;
+  const unsigned xcd = g & 7u, local = g >> 3;
+  return xcd * q + (xcd < r ? xcd : r) + local;
+}
+
+template <int K, FuseMode kMode>
+__global__ __launch_bounds__(kThreads) void fuse_kernel(VolumeDev vol, FrameDev f,
+                                                        unsigned tiles_x, unsigned n_tiles,
+                                                        int remap) {
+  constexpr int NS = 2 * K + 1;
+  constexpr bool kInsert = kMode != FuseMode::kIntegrate;
+  constexpr bool kAccumulate = kMode != FuseMode::kAllocate;
+
+  __shared__ unsigned long long s_keys[kSetCap];
+  __shared__ int s_block[kSetCap];
+  __shared__ unsigned short s_list[kSetCap];
+  __shared__ unsigned s_n;
+  __shared__ unsigned s_probe_max;
+
+  const unsigned tid = threadIdx.x;
+  for (unsigned i = tid; i < kSetCap; i += kThreads) s_keys[i] = kEmptyKey;
+  if (tid == 0) {
+    s_n = 0;
+    s_probe_max = 0;
+  }
+
+  const unsigned tile = tile_of_group(blockIdx.x, n_tiles, remap != 0);
+  const unsigned px = (tile % tiles_x) * kTileW + (tid % kTileW);
+  const unsigned py = (tile / tiles_x) * kTileH + (tid / kTileW);
+  const bool inside = px < f.width && py < f.height;
+  const float d = inside ? f.depth[(size_t)py * f.width + px] : 0.0f;
+  const bool point = inside && __builtin_isfinite(d) && d > 0.0f;
+  const float a = ((float)px - f.cx) * f.ifx;
+  const float b = ((float)py - f.cy) * f.ify;
+  __syncthreads();
+
+  // ---- phase 1: walk, per-point dedupe, per-wave key dedupe into LDS -------
+  unsigned st[NS];
+  float val[NS];
+  int hx[NS], hy[NS], hz[NS];
+  bool hv[NS];
+  unsigned n_pairs = 0, n_oor = 0;
+  unsigned long long prev_key = kEmptyKey;
+  unsigned prev_slot = kSetNone;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const Sample smp = walk_sample(f, d, a, b, s - K);
+    const bool z_ok = point && (d + (float)(s - K) * f.v > 0.0f);
+    if (z_ok && !smp.in_range) ++n_oor;
+    const bool ok = point && smp.in_range;
+    // a voxel counts once per point: compare with this point's earlier samples
+    bool dup = false;
+#pragma unroll
+    for (int j = 0; j < s; ++j)
+      dup |= hv[j] && hx[j] == smp.vx && hy[j] == smp.vy && hz[j] == smp.vz;
+    hv[s] = ok;
+    hx[s] = smp.vx;
+    hy[s] = smp.vy;
+    hz[s] = smp.vz;
+    const bool pair = ok && !dup && smp.keep;
+    n_pairs += pair ? 1u : 0u;
+    const unsigned long long key = pack_key(smp.vx >> 3, smp.vy >> 3, smp.vz >> 3);
+    const unsigned loc = (unsigned)((((smp.vz & 7) * 8) + (smp.vy & 7)) * 8 + (smp.vx & 7));
+    val[s] = smp.val;
+    // consecutive samples of a point mostly share a block: reuse its slot
+    const bool need = pair && key != prev_key;
+    unsigned slot = prev_slot;
+    unsigned long long pending = __ballot(need);
+    while (pending) {
+      const int leader = __ffsll((long long)pending) - 1;
+      const unsigned long long lk = readlane64(key, leader);
+      const bool same = need && key == lk;
+      pending &= ~__ballot(same);
+      unsigned ls = kSetNone;
+      if ((int)lane_id() == leader) {
+        unsigned h = set_home(lk);
+        for (unsigned i = 0; i < kSetCap; ++i) {
+          const unsigned long long old = atomicCAS(&s_keys[h], kEmptyKey, lk);
+          if (old == kEmptyKey) {
+            s_list[atomicAdd(&s_n, 1u)] = (unsigned short)h;
+            ls = h;
+            break;
+          }
+          if (old == lk) {
+            ls = h;
+            break;
+          }
+          h = (h + 1) & (kSetCap - 1);
+        }
+      }
+      ls = (unsigned)__builtin_amdgcn_readlane((int)ls, leader);
+      if (same) slot = ls;
+    }
+    if (pair) {
+      prev_key = key;
+      prev_slot = slot;
+    }
+    st[s] = pair ? (kPairValid | (slot << 9) | loc) : 0u;
+  }
+  __syncthreads();
+
+  // ---- phase 2: resolve each distinct key of the tile once ----------------
+  const unsigned n_keys = s_n;
+  unsigned my_probe_max = 0;
+  unsigned my_missing = 0;
+  for (unsigned base = 0; base < n_keys; base += kThreads) {
+    const unsigned j = base + tid;
+    const bool act = j < n_keys;
+    const unsigned h = act ? s_list[j] : 0u;
+    const unsigned long long key = act ? s_keys[h] : kEmptyKey;
+    unsigned probes = 0;
+    bool missing = false;
+    const int blk = resolve_key<kInsert>(vol, key, act, probes, missing);
+    if (act) {
+      s_block[h] = blk;
+      my_probe_max = probes > my_probe_max ? probes : my_probe_max;
+      my_missing += missing ? 1u : 0u;
+    }
+  }
+  if (my_probe_max) atomicMax(&s_probe_max, my_probe_max);
+  __syncthreads();
+
+  // ---- phase 3: integrate --------------------------------------------------
+  unsigned n_drop = 0;
+  if (kAccumulate) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const unsigned w = st[s];
+      if (w & kPairValid) {
+        const unsigned slot = (w >> 9) & 0x7FFu;
+        int blk;
+        if (slot != kSetNone) {
+          blk = s_block[slot];
+        } else {
+          // the tile had more distinct blocks than the LDS set holds: resolve
+          // this pair's key directly (same protocol, same result)
+          const Sample smp = walk_sample(f, d, a, b, s - K);
+          unsigned probes = 0;
+          bool missing = false;
+          blk = resolve_key<kInsert>(vol, pack_key(smp.vx >> 3, smp.vy >> 3, smp.vz >> 3), true,
+                                     probes, missing);
+          my_missing += missing ? 1u : 0u;
+        }
+        if (blk >= 0) {
+          const size_t i = (size_t)blk * TSDF_BLOCK_VOXELS + (w & 511u);
+          add_f32(vol.tsdf + i, val[s]);
+          add_f32(vol.weight + i, 1.0f);
+        } else {
+          ++n_drop;
+        }
+      }
+    }
+  }
+
+  // ---- counters: one atomic per wave, spread over shards -------------------
+  const unsigned wave = tid / kWave;
+  const bool leader = lane_id() == 0;
+  if (kAccumulate) {
+    const unsigned n_pts = (unsigned)__popcll(__ballot(point));
+    const unsigned pw = wave_sum_small(n_pairs);
+    const unsigned sh = (blockIdx.x * 4u + wave) & (kCounterShards - 1);
+    if (leader && n_pts) add_u64(&vol.ctr->points_valid[sh], n_pts);
+    if (leader && pw) add_u64(&vol.ctr->pairs[sh], pw);
+    if (__ballot(n_drop)) {
+      const unsigned dw = wave_sum_small(n_drop);
+      if (leader) add_u64(&vol.ctr->pairs_dropped, dw);
+    }
+    if (__ballot(n_oor)) {
+      const unsigned ow = wave_sum_small(n_oor);
+      if (leader) add_u64(&vol.ctr->coord_out_of_range, ow);
+    }
+  }
+  if (__ballot(my_missing)) {
+    const unsigned mw = wave_sum_small(my_missing);
+    if (leader) add_u32(&vol.ctr->lookup_misses, mw);
+  }
+  if (tid == 0 && s_probe_max) {
+    // a plain read filters almost every update; the atomic keeps the maximum exact
+    if (s_probe_max > *(volatile unsigned*)&vol.ctr->max_probe)
+      __hip_atomic_fetch_max(&vol.ctr->max_probe, s_probe_max, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__global__ __launch_bounds__(256) void insert_blocks_kernel(VolumeDev vol, const int* coords,
+                                                            unsigned n) {
+  const unsigned i = blockIdx.x * 256u + threadIdx.x;
+  bool act = i < n;
+  int bx = 0, by = 0, bz = 0;
+  if (act) {
+    bx = coords[3 * (size_t)i];
+    by = coords[3 * (size_t)i + 1];
+    bz = coords[3 * (size_t)i + 2];
+  }
+  const bool in_range = bx >= -(1 << 20) && bx < (1 << 20) && by >= -(1 << 20) &&
+                        by < (1 << 20) && bz >= -(1 << 20) && bz < (1 << 20);
+  if (act && !in_range) add_u64(&vol.ctr->coord_out_of_range, 1ull);
+  act = act && in_range;
+  unsigned probes = 0;
+  bool missing = false;
+  resolve_key<true>(vol, pack_key(bx, by, bz), act, probes, missing);
+  if (act && probes > *(volatile unsigned*)&vol.ctr->max_probe)
+    __hip_atomic_fetch_max(&vol.ctr->max_probe, probes, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(256) void fill_u32_kernel(unsigned* p, unsigned value, size_t n) {
+  const size_t stride = (size_t)gridDim.x * 256u;
+  const size_t n4 = n / 4;
+  uint4* p4 = reinterpret_cast<uint4*>(p);
+  const uint4 v4 = make_uint4(value, value, value, value);
+  for (size_t i = blockIdx.x * 256u + threadIdx.x; i < n4; i += stride) p4[i] = v4;
+  for (size_t i = n4 * 4 + blockIdx.x * 256u + threadIdx.x; i < n; i += stride) p[i] = value;
+}
+
+// Zero the pool blocks handed out since the last reset (the others are zero).
+__global__ __launch_bounds__(256) void reset_used_kernel(VolumeDev vol) {
+  unsigned used = *(volatile unsigned*)&vol.ctr->block_count;
+  used = used < vol.pool_capacity ? used : vol.pool_capacity;
+  const size_t n4 = (size_t)used * (TSDF_BLOCK_VOXELS / 4);
+  const size_t stride = (size_t)gridDim.x * 256u;
+  float4* t4 = reinterpret_cast<float4*>(vol.tsdf);
+  float4* w4 = reinterpret_cast<float4*>(vol.weight);
+  const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (size_t i = blockIdx.x * 256u + threadIdx.x; i < n4; i += stride) {
+    t4[i] = z;
+    w4[i] = z;
+  }
+}
+
+__global__ __launch_bounds__(256) void extract_kernel(VolumeDev vol, unsigned n_blocks,
+                                                      unsigned long long* keys, float* tsdf,
+                                                      float* weight) {
+  const size_t n4 = (size_t)n_blocks * (TSDF_BLOCK_VOXELS / 4);
+  const size_t stride = (size_t)gridDim.x * 256u;
+  const float4* t4 = reinterpret_cast<const float4*>(vol.tsdf);
+  const float4* w4 = reinterpret_cast<const float4*>(vol.weight);
+  for (size_t i = blockIdx.x * 256u + threadIdx.x; i < n4; i += stride) {
+    const float4 t = t4[i], w = w4[i];
+    if (tsdf) {
+      float4 m;
+      m.x = w.x > 0.f ? t.x / w.x : 0.f;
+      m.y = w.y > 0.f ? t.y / w.y : 0.f;
+      m.z = w.z > 0.f ? t.z / w.z : 0.f;
+      m.w = w.w > 0.f ? t.w / w.w : 0.f;
+      reinterpret_cast<float4*>(tsdf)[i] = m;
+    }
+    if (weight) reinterpret_cast<float4*>(weight)[i] = w;
+  }
+  if (keys)
+    for (size_t i = blockIdx.x * 256u + threadIdx.x; i < n_blocks; i += stride)
+      keys[i] = vol.block_keys[i];
+}
+
+unsigned grid_for(size_t work, unsigned cap) {
+  const size_t g = (work + 255) / 256;
+  return (unsigned)(g < 1 ? 1 : (g > cap ? cap : g));
+}
+
+template <int K>
+hipError_t launch_fuse_k(VolumeDev vol, const FrameDev& f, FuseMode mode, bool remap,
+                         hipStream_t s) {
+  const unsigned tx = (f.width + kTileW - 1) / kTileW;
+  const unsigned ty = (f.height + kTileH - 1) / kTileH;
+  const unsigned n_tiles = tx * ty;
+  if (n_tiles == 0) return hipSuccess;
+  const dim3 grid(n_tiles), block(kThreads);
+  switch (mode) {
+    case FuseMode::kFused:
+      hipLaunchKernelGGL((fuse_kernel<K, FuseMode::kFused>), grid, block, 0, s, vol, f, tx, n_tiles,
+                         (int)remap);
+      break;
+    case FuseMode::kAllocate:
+      hipLaunchKernelGGL((fuse_kernel<K, FuseMode::kAllocate>), grid, block, 0, s, vol, f, tx,
+                         n_tiles, (int)remap);
+      break;
+    case FuseMode::kIntegrate:
+      hipLaunchKernelGGL((fuse_kernel<K, FuseMode::kIntegrate>), grid, block, 0, s, vol, f, tx,
+                         n_tiles, (int)remap);
+      break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_fill_u32(void* ptr, unsigned value, size_t n_words, hipStream_t s) {
+  if (n_words == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(n_words / 4 + 1, 8192)), dim3(256), 0, s,
+                     static_cast<unsigned*>(ptr), value, n_words);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_used(VolumeDev vol, hipStream_t s) {
+  hipLaunchKernelGGL(reset_used_kernel,
+                     dim3(grid_for((size_t)vol.pool_capacity * (TSDF_BLOCK_VOXELS / 4), 8192)),
+                     dim3(256), 0, s, vol);
+  return hipGetLastError();
+}
+
+hipError_t launch_fuse(VolumeDev vol, const FrameDev& f, FuseMode mode, bool remap,
+                       hipStream_t s) {
+  switch (f.K) {
+    case 1: return launch_fuse_k<1>(vol, f, mode, remap, s);
+    case 2: return launch_fuse_k<2>(vol, f, mode, remap, s);
+    case 3: return launch_fuse_k<3>(vol, f, mode, remap, s);
+    case 4: return launch_fuse_k<4>(vol, f, mode, remap, s);
+    case 5: return launch_fuse_k<5>(vol, f, mode, remap, s);
+    case 6: return launch_fuse_k<6>(vol, f, mode, remap, s);
+    case 7: return launch_fuse_k<7>(vol, f, mode, remap, s);
+    case 8: return launch_fuse_k<8>(vol, f, mode, remap, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_insert_blocks(VolumeDev vol, const int* coords, unsigned n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(insert_blocks_kernel, dim3((n + 255) / 256), dim3(256), 0, s, vol, coords, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_extract(VolumeDev vol, unsigned n_blocks, unsigned long long* keys,
+                          float* tsdf, float* weight, hipStream_t s) {
+  if (n_blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(extract_kernel, dim3(grid_for((size_t)n_blocks * 128, 8192)), dim3(256), 0,
+                     s, vol, n_blocks, keys, tsdf, weight);
+  return hipGetLastError();
+}
+
+}  // namespace tsdf

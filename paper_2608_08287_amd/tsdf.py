@@ -1,0 +1,275 @@
+"""Python binding of ``libtsdf.so`` (ctypes).  Argument marshalling only.
+
+Every step of fusion runs in the HIP kernels behind the C ABI of
+``include/tsdf.h``; PyTorch supplies device memory (a ``torch.uint8`` arena per
+volume, depth frames, extraction outputs) and the ``hipStream_t`` to enqueue on.
+There is no CPU fallback: if the library is not built, or no GPU is present,
+the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtsdf.so")
+
+# tsdf_status
+OK, ERR_INVALID_ARGUMENT, ERR_BUFFER_TOO_SMALL, ERR_POOL_EXHAUSTED, ERR_TABLE_FULL, \
+    ERR_COORD_RANGE, ERR_INTERNAL, ERR_HIP = range(8)
+FLAG_POOL_EXHAUSTED, FLAG_TABLE_FULL, FLAG_COORD_RANGE, FLAG_INTERNAL = 1, 2, 4, 8
+FUSE_DEFAULT, FUSE_TWO_PASS, FUSE_ALLOCATE_ONLY, FUSE_INTEGRATE_ONLY = 0, 1, 2, 3
+FUSE_NO_XCD_REMAP = 0x100
+BLOCK_VOXELS = 512
+EMPTY_KEY = 0xFFFFFFFFFFFFFFFF
+
+EXPORTED_SYMBOLS = (
+    "tsdf_volume_bytes", "tsdf_volume_layout", "tsdf_create_volume", "tsdf_destroy_volume",
+    "tsdf_reset_volume", "tsdf_fuse_frame", "tsdf_fuse_frame_ex", "tsdf_query_status",
+    "tsdf_extract_blocks", "tsdf_insert_blocks", "tsdf_status_str",
+)
+
+
+class VolumeParams(C.Structure):
+    _fields_ = [("voxel_size", C.c_float), ("trunc", C.c_float),
+                ("table_capacity", C.c_uint32), ("pool_capacity", C.c_uint32)]
+
+
+class CameraC(C.Structure):
+    _fields_ = [("width", C.c_uint32), ("height", C.c_uint32), ("fx", C.c_float),
+                ("fy", C.c_float), ("cx", C.c_float), ("cy", C.c_float),
+                ("pose", C.c_float * 12)]
+
+
+class StatsC(C.Structure):
+    _fields_ = [("points_valid", C.c_uint64), ("pairs", C.c_uint64),
+                ("pairs_dropped", C.c_uint64), ("coord_out_of_range", C.c_uint64),
+                ("blocks_total", C.c_uint32), ("keys_pool_overflow", C.c_uint32),
+                ("table_full_events", C.c_uint32), ("max_probe", C.c_uint32),
+                ("lookup_misses", C.c_uint32), ("status_bits", C.c_uint32),
+                ("frames", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class LayoutC(C.Structure):
+    _fields_ = [("counters", C.c_uint64), ("table", C.c_uint64), ("block_keys", C.c_uint64),
+                ("tsdf", C.c_uint64), ("weight", C.c_uint64), ("total_bytes", C.c_uint64),
+                ("table_capacity", C.c_uint32), ("pool_capacity", C.c_uint32)]
+
+
+class TsdfError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {status_str(status)} ({status})")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libtsdf.so (after torch, so both share one HIP runtime)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                               "or python paper_2608_08287_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        P, U32, I = C.c_void_p, C.c_uint32, C.c_int
+        L.tsdf_volume_bytes.restype = C.c_size_t
+        L.tsdf_volume_bytes.argtypes = [C.POINTER(VolumeParams)]
+        L.tsdf_volume_layout.restype = I
+        L.tsdf_volume_layout.argtypes = [C.POINTER(VolumeParams), C.POINTER(LayoutC)]
+        L.tsdf_create_volume.restype = I
+        L.tsdf_create_volume.argtypes = [C.POINTER(VolumeParams), P, C.c_size_t, P, C.POINTER(P)]
+        L.tsdf_destroy_volume.restype = I
+        L.tsdf_destroy_volume.argtypes = [P]
+        L.tsdf_reset_volume.restype = I
+        L.tsdf_reset_volume.argtypes = [P, P]
+        L.tsdf_fuse_frame.restype = I
+        L.tsdf_fuse_frame.argtypes = [P, P, C.POINTER(CameraC), P]
+        L.tsdf_fuse_frame_ex.restype = I
+        L.tsdf_fuse_frame_ex.argtypes = [P, P, C.POINTER(CameraC), U32, P]
+        L.tsdf_query_status.restype = I
+        L.tsdf_query_status.argtypes = [P, P, C.POINTER(StatsC)]
+        L.tsdf_extract_blocks.restype = I
+        L.tsdf_extract_blocks.argtypes = [P, P, U32, P, P, P, C.POINTER(U32)]
+        L.tsdf_insert_blocks.restype = I
+        L.tsdf_insert_blocks.argtypes = [P, P, U32, P]
+        L.tsdf_status_str.restype = C.c_char_p
+        L.tsdf_status_str.argtypes = [I]
+        _lib = L
+    return _lib
+
+
+def status_str(status: int) -> str:
+    return lib().tsdf_status_str(status).decode()
+
+
+def volume_params(voxel_size: float, trunc: float, table_capacity: int,
+                  pool_capacity: int) -> VolumeParams:
+    return VolumeParams(voxel_size, trunc, table_capacity, pool_capacity)
+
+
+def volume_bytes(p: VolumeParams) -> int:
+    return int(lib().tsdf_volume_bytes(C.byref(p)))
+
+
+def layout(p: VolumeParams) -> LayoutC:
+    out = LayoutC()
+    st = lib().tsdf_volume_layout(C.byref(p), C.byref(out))
+    if st != OK:
+        raise TsdfError(st, "tsdf_volume_layout")
+    return out
+
+
+def camera_struct(cam) -> CameraC:
+    """``cam``: anything with width, height, fx, fy, cx, cy and a 3x4 pose."""
+    pose = np.ascontiguousarray(np.asarray(cam.pose, dtype=np.float32).reshape(12))
+    return CameraC(int(cam.width), int(cam.height), float(cam.fx), float(cam.fy), float(cam.cx),
+                   float(cam.cy), (C.c_float * 12)(*pose.tolist()))
+
+
+def _stream_ptr(stream: Optional[torch.cuda.Stream]) -> C.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+@dataclass
+class Stats:
+    points_valid: int
+    pairs: int
+    pairs_dropped: int
+    coord_out_of_range: int
+    blocks_total: int
+    keys_pool_overflow: int
+    table_full_events: int
+    max_probe: int
+    lookup_misses: int
+    status_bits: int
+    frames: int
+    status: int
+
+
+@dataclass
+class Extracted:
+    keys: torch.Tensor     # (n,) int64 holding the uint64 packed keys, pool order
+    tsdf: torch.Tensor     # (n, 512) float32 mean TSDF (0 where weight 0)
+    weight: torch.Tensor   # (n, 512) float32
+
+
+class Volume:
+    """One resident TSDF volume in a device arena owned by this object."""
+
+    def __init__(self, voxel_size: float, trunc: float, table_capacity: int, pool_capacity: int,
+                 device: str | torch.device = "cuda", stream: Optional[torch.cuda.Stream] = None):
+        self.params = volume_params(voxel_size, trunc, table_capacity, pool_capacity)
+        nbytes = volume_bytes(self.params)
+        if nbytes == 0:
+            raise TsdfError(ERR_INVALID_ARGUMENT, "volume parameters")
+        self.layout = layout(self.params)
+        self.arena = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self._h = C.c_void_p()
+        st = lib().tsdf_create_volume(C.byref(self.params), C.c_void_p(self.arena.data_ptr()),
+                                      nbytes, _stream_ptr(stream), C.byref(self._h))
+        if st != OK:
+            raise TsdfError(st, "tsdf_create_volume")
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) and self._h.value:
+            lib().tsdf_destroy_volume(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self) -> C.c_void_p:
+        return self._h
+
+    def reset(self, stream=None) -> None:
+        st = lib().tsdf_reset_volume(self._h, _stream_ptr(stream))
+        if st != OK:
+            raise TsdfError(st, "tsdf_reset_volume")
+
+    def fuse(self, depth: torch.Tensor, cam, flags: int = FUSE_DEFAULT, stream=None) -> None:
+        """Enqueue the fusion of one (H, W) float32 device depth frame."""
+        if depth.dtype != torch.float32 or not depth.is_cuda or not depth.is_contiguous():
+            raise TypeError("depth must be a contiguous float32 device tensor")
+        c = cam if isinstance(cam, CameraC) else camera_struct(cam)
+        if depth.numel() != c.width * c.height:
+            raise ValueError("depth size does not match the camera")
+        st = lib().tsdf_fuse_frame_ex(self._h, C.c_void_p(depth.data_ptr()), C.byref(c), flags,
+                                      _stream_ptr(stream))
+        if st != OK:
+            raise TsdfError(st, "tsdf_fuse_frame")
+
+    def insert_blocks(self, coords: torch.Tensor, stream=None) -> None:
+        """Allocate blocks for (n, 3) int32 device block coordinates."""
+        if coords.dtype != torch.int32 or not coords.is_cuda or not coords.is_contiguous():
+            raise TypeError("coords must be a contiguous int32 device tensor")
+        n = coords.numel() // 3
+        st = lib().tsdf_insert_blocks(self._h, C.c_void_p(coords.data_ptr()), n, _stream_ptr(stream))
+        if st != OK:
+            raise TsdfError(st, "tsdf_insert_blocks")
+
+    def stats(self, stream=None) -> Stats:
+        s = StatsC()
+        st = lib().tsdf_query_status(self._h, _stream_ptr(stream), C.byref(s))
+        if st == ERR_HIP or st == ERR_INVALID_ARGUMENT:
+            raise TsdfError(st, "tsdf_query_status")
+        return Stats(s.points_valid, s.pairs, s.pairs_dropped, s.coord_out_of_range, s.blocks_total,
+                     s.keys_pool_overflow, s.table_full_events, s.max_probe, s.lookup_misses,
+                     s.status_bits, s.frames, st)
+
+    def extract(self, stream=None) -> Extracted:
+        n = C.c_uint32(0)
+        L = lib()
+        st = L.tsdf_extract_blocks(self._h, _stream_ptr(stream), 0, None, None, None, C.byref(n))
+        if st not in (OK, ERR_BUFFER_TOO_SMALL):
+            raise TsdfError(st, "tsdf_extract_blocks")
+        nb = n.value
+        dev = self.arena.device
+        keys = torch.empty(nb, dtype=torch.int64, device=dev)
+        tsdf = torch.empty((nb, BLOCK_VOXELS), dtype=torch.float32, device=dev)
+        weight = torch.empty((nb, BLOCK_VOXELS), dtype=torch.float32, device=dev)
+        st = L.tsdf_extract_blocks(self._h, _stream_ptr(stream), nb, C.c_void_p(keys.data_ptr()),
+                                   C.c_void_p(tsdf.data_ptr()), C.c_void_p(weight.data_ptr()),
+                                   C.byref(n))
+        if st != OK:
+            raise TsdfError(st, "tsdf_extract_blocks")
+        return Extracted(keys, tsdf, weight)
+
+    # Zero-copy views of the carved regions (for invariant checks and consumers).
+    def table_view(self) -> torch.Tensor:
+        """(C, 2) int64 view of the table: column 0 key bits, column 1 (block | pad<<32)."""
+        L = self.layout
+        t = self.arena[L.table:L.table + 16 * L.table_capacity]
+        return t.view(torch.int64).view(L.table_capacity, 2)
+
+    def tsdf_sum_view(self) -> torch.Tensor:
+        L = self.layout
+        return self.arena[L.tsdf:L.tsdf + 2048 * L.pool_capacity].view(torch.float32).view(
+            L.pool_capacity, BLOCK_VOXELS)
+
+    def weight_view(self) -> torch.Tensor:
+        L = self.layout
+        return self.arena[L.weight:L.weight + 2048 * L.pool_capacity].view(torch.float32).view(
+            L.pool_capacity, BLOCK_VOXELS)
+
+    def block_keys_view(self) -> torch.Tensor:
+        L = self.layout
+        return self.arena[L.block_keys:L.block_keys + 8 * L.pool_capacity].view(torch.int64)
+
+
+def fuse_frames(vol: Volume, depths: Sequence[torch.Tensor], cams: Sequence, flags: int = FUSE_DEFAULT,
+                stream=None) -> None:
+    structs = [c if isinstance(c, CameraC) else camera_struct(c) for c in cams]
+    for d, c in zip(depths, structs):
+        vol.fuse(d, c, flags, stream)

@@ -1,0 +1,109 @@
+"""Helpers shared by the GPU parity tests: run a workload through the C ABI and
+compare with the oracle (keys and weights exact, TSDF means within a tolerance,
+table and pool invariants)."""
+from __future__ import annotations
+
+import dataclasses
+import sys
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from oracle import oracle as O
+from paper_2608_08287_amd import tsdf as T
+
+# TSDF means: float32 sums on the GPU in a racy order against float64 sums in the
+# oracle.  A mean of n contributions, each |x| <= tau <= 0.04 m, carries at most
+# about n * 2^-24 * tau of float32 rounding: 1e-5 holds up to n ~ 4000.
+TSDF_ATOL = 1e-5
+EMPTY = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+@dataclasses.dataclass
+class GpuResult:
+    keys: np.ndarray     # uint64, ascending
+    means: np.ndarray    # (n, 512) float32
+    weights: np.ndarray  # (n, 512) float32
+    stats: T.Stats
+    vol: Optional[T.Volume] = None
+
+
+def run_gpu(voxel_size, trunc, table_capacity, pool_capacity, depths: Sequence[np.ndarray], cams,
+            prefill_blocks=None, flags=T.FUSE_DEFAULT, keep_volume=False,
+            vol: Optional[T.Volume] = None) -> GpuResult:
+    if vol is None:
+        vol = T.Volume(voxel_size, trunc, table_capacity, pool_capacity)
+    if prefill_blocks is not None:
+        vol.insert_blocks(torch.from_numpy(np.ascontiguousarray(prefill_blocks, dtype=np.int32)).cuda())
+    dev = [torch.from_numpy(np.ascontiguousarray(d, dtype=np.float32)).cuda() for d in depths]
+    for d, c in zip(dev, cams):
+        vol.fuse(d, c, flags)
+    st = vol.stats()
+    ex = vol.extract()
+    torch.cuda.synchronize()
+    keys = ex.keys.cpu().numpy().view(np.uint64)
+    order = np.argsort(keys, kind="stable")
+    res = GpuResult(keys[order], ex.tsdf.cpu().numpy()[order], ex.weight.cpu().numpy()[order], st)
+    if keep_volume:
+        res.vol = vol
+    return res
+
+
+def run_workload(w, flags=T.FUSE_DEFAULT, keep_volume=False, **kw) -> GpuResult:
+    return run_gpu(w.voxel_size, w.trunc, w.table_capacity, w.pool_capacity, w.depth, w.cameras,
+                   w.prefill_blocks, flags, keep_volume, **kw)
+
+
+def assert_parity(g: GpuResult, o: O.OracleResult, atol=TSDF_ATOL) -> None:
+    assert g.keys.size == o.keys.size, (g.keys.size, o.keys.size)
+    assert np.array_equal(g.keys, o.keys), "block key sets differ"
+    assert np.array_equal(g.weights, o.weights.astype(np.float32)), "weights differ"
+    err = np.abs(g.means.astype(np.float64) - o.means)
+    assert float(err.max(initial=0.0)) <= atol, float(err.max())
+    assert g.stats.points_valid == o.stats["points_valid"]
+    assert g.stats.pairs == o.stats["pairs"]
+    assert g.stats.pairs_dropped == o.stats["pairs_dropped"]
+    assert g.stats.coord_out_of_range == o.stats["coord_out_of_range"]
+    assert g.stats.blocks_total == o.stats["blocks"]
+    assert g.stats.keys_pool_overflow == o.stats["pool_overflow_keys"]
+
+
+def table_arrays(vol: T.Volume):
+    t = vol.table_view().cpu().numpy()
+    keys = t[:, 0].view(np.uint64).copy()
+    blocks = (t[:, 1] & 0xFFFFFFFF).astype(np.uint32).view(np.int32)
+    return keys, blocks
+
+
+def assert_table_invariants(vol: T.Volume, expect_keys: np.ndarray, n_blocks: int) -> None:
+    """The GPU table against the sequential linear-probe model.
+
+    expect_keys: every key that must be in the table (allocated or pool-full).
+    """
+    keys, blocks = table_arrays(vol)
+    C = keys.size
+    occ = np.nonzero(keys != EMPTY)[0]
+    tk = keys[occ]
+    assert np.unique(tk).size == tk.size, "duplicate keys in the table"
+    assert np.array_equal(np.sort(tk), np.sort(expect_keys)), "table key set differs"
+    tb = blocks[occ]
+    assert np.all((tb >= 0) | (tb == -2)), "unpublished or corrupt entry"
+    alloc = np.sort(tb[tb >= 0])
+    assert np.array_equal(alloc, np.arange(n_blocks)), "pool indices are not a permutation"
+    bk = vol.block_keys_view()[:max(n_blocks, 0)].cpu().numpy().view(np.uint64)
+    assert np.array_equal(bk[tb[tb >= 0]], tk[tb >= 0]), "block_keys does not match the table"
+    model = O.probe_model(tk, C)  # any insertion order gives the same layout
+    assert np.array_equal(model.occupied, occ), "occupied slots differ from the probe model"
+    homes = np.array([O.home_slot(int(k), C) for k in tk], dtype=np.int64)
+    disp = (occ.astype(np.int64) - homes) % C
+    assert int(disp.sum()) == int(model.disp_of.sum()), "total displacement differs"
+    # no empty slot between a key's home and its slot
+    empty = keys == EMPTY
+    cum = np.concatenate([[0], np.cumsum(np.concatenate([empty, empty]).astype(np.int64))])
+    starts, ends = homes, homes + disp
+    assert np.all(cum[ends] - cum[starts] == 0), "empty slot inside a probe path"

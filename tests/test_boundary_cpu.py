@@ -1,0 +1,98 @@
+"""The C ABI without a GPU: the library loads, exports every declared symbol, and
+its host-side argument checks reject bad input before anything is enqueued."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2608_08287_amd import tsdf as T
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "tsdf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tsdf_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = T.lib()
+    declared = _declared_functions()
+    assert set(declared) == set(T.EXPORTED_SYMBOLS)
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def test_volume_bytes_and_layout():
+    p = T.volume_params(0.01, 0.04, 8192, 4096)
+    L = T.layout(p)
+    assert L.table_capacity == 8192 and L.pool_capacity == 4096
+    assert L.counters == 0
+    for off in (L.table, L.block_keys, L.tsdf, L.weight, L.total_bytes):
+        assert off % 256 == 0
+    assert L.block_keys - L.table >= 8192 * 16
+    assert L.tsdf - L.block_keys >= 4096 * 8
+    assert L.weight - L.tsdf == 4096 * 512 * 4
+    assert L.total_bytes - L.weight == 4096 * 512 * 4
+    assert T.volume_bytes(p) == L.total_bytes
+    # table 0 -> next power of two >= 2 * pool (the paper's sizing)
+    assert T.layout(T.volume_params(0.01, 0.04, 0, 4096)).table_capacity == 8192
+    assert T.layout(T.volume_params(0.01, 0.04, 0, 3000)).table_capacity == 8192
+    assert T.layout(T.volume_params(0.01, 0.04, 0, 1)).table_capacity == 2
+    # non-power-of-two tables are allowed
+    assert T.layout(T.volume_params(0.005, 0.02, 123457, 1 << 18)).table_capacity == 123457
+    # the configuration with a 2^20-slot table and a 2^18-block pool
+    big = T.layout(T.volume_params(0.005, 0.02, 1 << 20, 1 << 18))
+    assert big.total_bytes > 2 * (1 << 18) * 2048
+
+
+@pytest.mark.parametrize("vs,tr,C_,P", [
+    (0.0, 0.04, 8192, 4096), (-0.01, 0.04, 8192, 4096), (float("nan"), 0.04, 8192, 4096),
+    (float("inf"), 0.04, 8192, 4096), (0.01, 0.0, 8192, 4096), (0.01, 0.001, 8192, 4096),
+    (0.01, 0.2, 8192, 4096), (0.01, float("nan"), 8192, 4096), (0.01, 0.04, 8192, 0),
+    (0.01, 0.04, 8192, 1 << 22), (0.01, 0.04, 0, 0x7FFFFFFF),
+])
+def test_invalid_volume_params(vs, tr, C_, P):
+    p = T.volume_params(vs, tr, C_, P)
+    assert T.volume_bytes(p) == 0
+    out = T.LayoutC()
+    assert T.lib().tsdf_volume_layout(C.byref(p), C.byref(out)) == T.ERR_INVALID_ARGUMENT
+    h = C.c_void_p()
+    assert T.lib().tsdf_create_volume(C.byref(p), C.c_void_p(256), 1 << 40, None,
+                                      C.byref(h)) == T.ERR_INVALID_ARGUMENT
+    assert not h.value
+
+
+def test_create_rejects_bad_arena_before_any_device_work():
+    L = T.lib()
+    p = T.volume_params(0.01, 0.04, 8192, 4096)
+    h = C.c_void_p()
+    assert L.tsdf_create_volume(C.byref(p), None, 1 << 30, None, C.byref(h)) == T.ERR_INVALID_ARGUMENT
+    assert L.tsdf_create_volume(C.byref(p), C.c_void_p(4096 + 8), 1 << 30, None,
+                                C.byref(h)) == T.ERR_INVALID_ARGUMENT
+    assert L.tsdf_create_volume(C.byref(p), C.c_void_p(4096), 1024, None,
+                                C.byref(h)) == T.ERR_BUFFER_TOO_SMALL
+    assert L.tsdf_create_volume(C.byref(p), C.c_void_p(4096), 1 << 30, None, None) == \
+        T.ERR_INVALID_ARGUMENT
+
+
+def test_null_handles_are_rejected():
+    L = T.lib()
+    cam = T.CameraC(4, 4, 1.0, 1.0, 2.0, 2.0, (C.c_float * 12)(1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0))
+    st = T.StatsC()
+    n = C.c_uint32()
+    assert L.tsdf_destroy_volume(None) == T.ERR_INVALID_ARGUMENT
+    assert L.tsdf_reset_volume(None, None) == T.ERR_INVALID_ARGUMENT
+    assert L.tsdf_fuse_frame(None, C.c_void_p(256), C.byref(cam), None) == T.ERR_INVALID_ARGUMENT
+    assert L.tsdf_fuse_frame_ex(None, C.c_void_p(256), C.byref(cam), 0, None) == T.ERR_INVALID_ARGUMENT
+    assert L.tsdf_query_status(None, None, C.byref(st)) == T.ERR_INVALID_ARGUMENT
+    assert L.tsdf_extract_blocks(None, None, 0, None, None, None, C.byref(n)) == T.ERR_INVALID_ARGUMENT
+    assert L.tsdf_insert_blocks(None, C.c_void_p(256), 1, None) == T.ERR_INVALID_ARGUMENT
+
+
+def test_status_strings():
+    for s in range(8):
+        assert T.status_str(s) and T.status_str(s) != "unknown status"
+    assert T.status_str(99) == "unknown status"

@@ -1,0 +1,282 @@
+"""GPU parity: the HIP path through the C ABI against the sequential CPU oracle.
+
+Block keys and per-voxel weights must match exactly, TSDF means within 1e-5;
+table and pool invariants are checked against the linear-probe model.  Every
+case prints its name before touching the GPU.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2608_08287_amd import scenes as S
+from paper_2608_08287_amd import tsdf as T
+
+from parity import (EMPTY, assert_parity, assert_table_invariants, log, run_gpu, run_workload,
+                    table_arrays)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible: the HIP path has no CPU fallback")
+    T.lib()
+
+
+def _name(request):
+    log(f"[gpu] {request.node.name}")
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    _name(request)
+    yield
+    torch.cuda.synchronize()
+
+
+# ---------------------------------------------------------------------------
+# The single-frame plane + sphere workload (160x120, 1 cm voxels)
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def single():
+    w = S.single_frame_workload()
+    return w, O.fuse_workload(w)
+
+
+@pytest.mark.parametrize("flags", [T.FUSE_DEFAULT, T.FUSE_TWO_PASS, T.FUSE_NO_XCD_REMAP,
+                                   T.FUSE_TWO_PASS | T.FUSE_NO_XCD_REMAP])
+def test_single_frame_parity(single, flags):
+    w, o = single
+    g = run_workload(w, flags=flags, keep_volume=True)
+    assert_parity(g, o)
+    assert g.stats.status == T.OK and g.stats.lookup_misses == 0
+    assert_table_invariants(g.vol, o.keys, o.keys.size)
+
+
+def test_single_frame_repeatable(single):
+    w, o = single
+    for _ in range(3):
+        assert_parity(run_workload(w), o)
+
+
+def test_reset_then_refuse_is_identical(single):
+    w, o = single
+    g = run_workload(w, keep_volume=True)
+    g.vol.reset()
+    g2 = run_gpu(w.voxel_size, w.trunc, w.table_capacity, w.pool_capacity, w.depth, w.cameras,
+                 vol=g.vol)
+    assert_parity(g2, o)
+    assert g2.stats.frames == 1
+
+
+def test_separate_stages_match_fused(single):
+    w, o = single
+    vol = T.Volume(w.voxel_size, w.trunc, w.table_capacity, w.pool_capacity)
+    d = torch.from_numpy(w.depth[0]).cuda()
+    vol.fuse(d, w.cameras[0], T.FUSE_ALLOCATE_ONLY)
+    st = vol.stats()
+    assert st.blocks_total == o.keys.size and st.pairs == 0 and st.frames == 0
+    vol.fuse(d, w.cameras[0], T.FUSE_INTEGRATE_ONLY)
+    g = run_gpu(w.voxel_size, w.trunc, w.table_capacity, w.pool_capacity, [], [], vol=vol)
+    assert_parity(g, o)
+
+
+def test_extract_buffer_too_small(single):
+    w, o = single
+    import ctypes as C
+    vol = T.Volume(w.voxel_size, w.trunc, w.table_capacity, w.pool_capacity)
+    vol.fuse(torch.from_numpy(w.depth[0]).cuda(), w.cameras[0])
+    n = C.c_uint32(0)
+    keys = torch.empty(10, dtype=torch.int64, device="cuda")
+    st = T.lib().tsdf_extract_blocks(vol.handle, C.c_void_p(torch.cuda.current_stream().cuda_stream),
+                                     10, C.c_void_p(keys.data_ptr()), None, None, C.byref(n))
+    assert st == T.ERR_BUFFER_TOO_SMALL and n.value == o.keys.size
+
+
+# ---------------------------------------------------------------------------
+# Closed forms and tiny inputs (ragged tiles, random poses, invalid pixels)
+# ---------------------------------------------------------------------------
+
+def _rot(a, b, c):
+    ca, sa, cb, sb, cc, sc = math.cos(a), math.sin(a), math.cos(b), math.sin(b), math.cos(c), math.sin(c)
+    return (np.array([[ca, -sa, 0], [sa, ca, 0], [0, 0, 1]]) @ np.array([[cb, 0, sb], [0, 1, 0], [-sb, 0, cb]])
+            @ np.array([[1, 0, 0], [0, cc, -sc], [0, sc, cc]]))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_tiny_random_frames(seed):
+    rng = np.random.default_rng(100 + seed)
+    W, H = [(13, 9), (1, 1), (17, 33), (16, 16), (31, 2), (40, 23)][seed]
+    pose = np.concatenate([_rot(*rng.uniform(-2, 2, 3)), rng.uniform(-1, 1, (3, 1))], 1).astype(np.float32)
+    cam = S.Camera(W, H, float(rng.uniform(5, 30)), float(rng.uniform(5, 30)), W / 2 - 0.3, H / 2 + 0.1, pose)
+    depth = rng.uniform(0.2, 1.5, (H, W)).astype(np.float32)
+    depth[rng.random((H, W)) < 0.15] = 0.0
+    depth[rng.random((H, W)) < 0.05] = np.nan
+    depth[rng.random((H, W)) < 0.05] = -0.5
+    v, tau = [(0.01, 0.04), (0.02, 0.06), (0.005, 0.02), (0.03, 0.03), (0.01, 0.08), (0.004, 0.016)][seed]
+    o = O.fuse_frames(v, tau, 1 << 14, [depth], [cam])
+    g = run_gpu(v, tau, 1 << 15, 1 << 14, [depth], [cam], keep_volume=True)
+    assert_parity(g, o)
+    assert_table_invariants(g.vol, o.keys, o.keys.size)
+
+
+@pytest.mark.parametrize("angles", [(0.0, 0.0, 0.0), (0.5, 0.3, -0.2), (-2.0, 1.1, 0.7)])
+def test_fronto_parallel_plane(angles):
+    R = _rot(*angles)
+    pose = np.concatenate([R, np.array([[0.3], [-0.2], [1.1]])], 1).astype(np.float32)
+    cam = S.Camera(97, 61, 80.0, 75.0, 48.0, 30.5, pose)
+    depth = np.full((61, 97), np.float32(1.003), dtype=np.float32)
+    o = O.fuse_frames(0.01, 0.04, 1 << 14, [depth], [cam])
+    g = run_gpu(0.01, 0.04, 1 << 15, 1 << 14, [depth], [cam])
+    assert_parity(g, o)
+
+
+def test_empty_and_invalid_frames():
+    cam = S.Camera(64, 48, 50.0, 50.0, 32.0, 24.0, S.IDENTITY_POSE)
+    frames = [np.zeros((48, 64), np.float32), np.full((48, 64), np.nan, np.float32),
+              np.full((48, 64), -1.0, np.float32), np.full((48, 64), np.inf, np.float32)]
+    g = run_gpu(0.01, 0.04, 1024, 512, frames, [cam] * 4)
+    assert g.keys.size == 0 and g.stats.points_valid == 0 and g.stats.pairs == 0
+    assert g.stats.status == T.OK and g.stats.frames == 4
+    # a zero-sized frame is a valid no-op
+    g0 = run_gpu(0.01, 0.04, 1024, 512, [np.zeros((0, 5), np.float32)],
+                 [S.Camera(5, 0, 50.0, 50.0, 2.0, 0.0, S.IDENTITY_POSE)])
+    assert g0.keys.size == 0 and g0.stats.frames == 1
+
+
+def test_coordinates_out_of_range_are_reported():
+    cam, depth = S.plane_sphere_frame()
+    pose = cam.pose.copy()
+    pose[0, 3] = 1.0e5
+    cam2 = S.Camera(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy, pose)
+    o = O.fuse_frames(0.01, 0.04, 4096, [depth], [cam2])
+    g = run_gpu(0.01, 0.04, 8192, 4096, [depth], [cam2])
+    assert_parity(g, o)
+    assert g.stats.status == T.ERR_COORD_RANGE and g.stats.coord_out_of_range == 9 * 19200
+
+
+def test_large_frame_1280x720():
+    scene = S.room_scene(1)
+    cam = S.orbit_camera(17, 300, width=1280, height=720)
+    depth = S.render_depth(cam, scene, lambda z: 0.002 * z * z, 7)
+    o = O.fuse_frames(0.005, 0.02, 1 << 18, [depth], [cam])
+    g = run_gpu(0.005, 0.02, 1 << 20, 1 << 18, [depth], [cam])
+    assert_parity(g, o)
+
+
+# ---------------------------------------------------------------------------
+# The room trajectory at its full frame and volume sizes (sampled frames)
+# ---------------------------------------------------------------------------
+
+ROOM_FRAMES = [0, 1, 2, 150, 299]
+
+
+@pytest.fixture(scope="module")
+def room():
+    w = S.room_trajectory_workload(frames=ROOM_FRAMES)
+    return w, O.fuse_workload(w)
+
+
+def test_room_trajectory_sampled_frames(room):
+    w, o = room
+    g = run_workload(w, keep_volume=True)
+    assert_parity(g, o)
+    assert g.stats.status == T.OK
+    assert_table_invariants(g.vol, o.keys, o.keys.size)
+
+
+@pytest.mark.parametrize("alpha", [0.25, 0.5, 0.75, 0.9])
+def test_room_load_factor_sweep(room, alpha):
+    w, o = room
+    C = int(math.ceil(o.keys.size / alpha))
+    g = run_gpu(w.voxel_size, w.trunc, C, w.pool_capacity, w.depth, w.cameras, keep_volume=True)
+    assert_parity(g, o)
+    assert_table_invariants(g.vol, o.keys, o.keys.size)
+    log(f"  alpha={alpha} C={C} max_probe={g.stats.max_probe}")
+
+
+# ---------------------------------------------------------------------------
+# Contention and overflow stress: plane at 0.5 m, table pre-filled to LF 0.95
+# ---------------------------------------------------------------------------
+
+STRESS_FRAMES = [0, 1]
+
+
+@pytest.fixture(scope="module")
+def stress_full():
+    """Oracle with an unbounded pool: every key's true weights."""
+    w = S.plane_stress_workload("plain", frames=STRESS_FRAMES)
+    return w, O.fuse_workload(w)
+
+
+def test_stress_plain_contention(stress_full):
+    w, o = stress_full
+    g = run_workload(w)
+    assert_parity(g, o)
+
+
+def test_stress_A_prefilled_to_095_drops_nothing(stress_full):
+    w = S.plane_stress_workload("A", frames=STRESS_FRAMES)
+    o = O.fuse_workload(w)
+    assert o.stats["pairs_dropped"] == 0 and o.stats["pool_overflow_keys"] == 0
+    g = run_workload(w, keep_volume=True)
+    assert_parity(g, o)
+    assert g.stats.pairs_dropped == 0 and g.stats.status == T.OK
+    assert_table_invariants(g.vol, o.keys, o.keys.size)
+    log(f"  max_probe={g.stats.max_probe}")
+
+
+def _pre_keys(coords):
+    return np.array([O.pack_key(*map(int, c)) for c in coords], dtype=np.uint64)
+
+
+def _check_subset(g, full, allocated_scene_keys):
+    """Kept scene keys carry their full weights; everything else was dropped."""
+    idx = np.searchsorted(full.keys, allocated_scene_keys)
+    assert np.array_equal(full.keys[idx], allocated_scene_keys)
+    gi = np.searchsorted(g.keys, allocated_scene_keys)
+    assert np.array_equal(g.weights[gi], full.weights[idx].astype(np.float32))
+    assert float(np.abs(g.means[gi] - full.means[idx]).max(initial=0.0)) <= 1e-5
+    kept_pairs = int(full.weights[idx].sum())
+    assert g.stats.pairs == full.stats["pairs"]
+    assert g.stats.pairs_dropped == full.stats["pairs"] - kept_pairs
+
+
+def test_stress_B_pool_exhaustion_is_exact(stress_full):
+    w_full, full = stress_full
+    w = S.plane_stress_workload("B", frames=STRESS_FRAMES)
+    pre = _pre_keys(w.prefill_blocks)
+    n_scene = full.keys.size
+    g = run_workload(w, keep_volume=True)
+    assert g.stats.status == T.ERR_POOL_EXHAUSTED
+    assert g.stats.blocks_total == w.pool_capacity
+    assert g.stats.keys_pool_overflow == n_scene - 100
+    table_keys, blocks = table_arrays(g.vol)
+    occ = table_keys != EMPTY
+    alloc_keys = table_keys[occ & (blocks >= 0)]
+    scene_alloc = np.setdiff1d(alloc_keys, pre)
+    assert scene_alloc.size == 100
+    assert np.array_equal(np.sort(g.keys), np.sort(alloc_keys))
+    _check_subset(g, full, np.sort(scene_alloc))
+    assert_table_invariants(g.vol, np.union1d(pre, full.keys), w.pool_capacity)
+
+
+def test_stress_C_table_full_is_reported(stress_full):
+    w_full, full = stress_full
+    w = S.plane_stress_workload("C", frames=STRESS_FRAMES[:1])
+    full1 = O.fuse_frames(w.voxel_size, w.trunc, 1 << 20, w.depth, w.cameras)
+    pre = _pre_keys(w.prefill_blocks)
+    g = run_workload(w, keep_volume=True)
+    assert g.stats.status == T.ERR_TABLE_FULL
+    table_keys, blocks = table_arrays(g.vol)
+    assert np.count_nonzero(table_keys == EMPTY) == 0
+    scene_in = np.setdiff1d(table_keys, pre)
+    assert scene_in.size == 50
+    assert g.stats.blocks_total == pre.size + 50
+    _check_subset(g, full1, np.sort(scene_in))
+    assert g.stats.table_full_events >= full1.keys.size - 50
