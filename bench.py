@@ -60,6 +60,9 @@ def main() -> int:
                     help="approximate CPU time for the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", choices=["fused", "two_pass", "fused_no_remap"], default="fused")
+    ap.add_argument("--profile-copy-bytes", type=int, default=0,
+                    help="after the run, copy this many bytes device-to-device three times "
+                         "(a kernel of known traffic for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -180,6 +183,14 @@ def main() -> int:
                "sample": f"first {k} of {len(w.depth)} frames fused sequentially into one volume "
                          f"({pts} points, {t_c:.1f} s, one thread)"}
         log(f"[bench] cpu oracle: {pts / t_c:.3e} points/s over {k} frames")
+
+    if args.profile_copy_bytes:
+        src = torch.empty(args.profile_copy_bytes, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     out = {
         "metric": METRIC,

@@ -6,9 +6,10 @@
 //   1. walk   -- each lane walks its pixel's truncation band (2K+1 samples) and
 //                keeps, per sample, the voxel's in-block index and its truncated
 //                signed distance in registers.  The block keys of the tile are
-//                deduplicated into an LDS key set: per sample, a wave64 ballot
-//                loop elects one leader per distinct key, and only leaders touch
-//                the set.
+//                deduplicated into an LDS key set (open addressing, 64-bit LDS
+//                compare-exchange); a lane inserts a key only when it differs
+//                from its previous sample's, and lanes of one wave that race for
+//                a slot are serialised by the LDS itself.
 //   2. resolve -- each distinct key of the tile is resolved once against the
 //                global open-addressed table (Section 2.3's insert protocol):
 //                probe linearly from the home slot, plain first read of the
@@ -19,8 +20,14 @@
 //                lane takes exactly one step per iteration and "waiting for a
 //                publication" means "look again next iteration"), so a waiter
 //                never spins while a publisher in its own wave is masked off.
-//   3. integrate -- each lane adds its contributions into the flat SoA pool with
-//                agent-scope float atomics, reading pool indices from LDS.
+//   3. integrate -- the tile's contributions are first summed in LDS, kAccBlocks
+//                blocks at a time, in a dense 512-voxel accumulator per block;
+//                each pass then flushes its touched voxels into the flat SoA pool
+//                with agent-scope float atomics, 64 consecutive voxels of one block
+//                per wave instruction.  A voxel thus receives one atomic per
+//                workgroup instead of one per contribution, and each instruction
+//                hits two 128-byte lines with distinct addresses: the pool's
+//                read-modify-write traffic is line-coalesced instead of scattered.
 //
 // A workgroup only ever accumulates into blocks whose indices it resolved itself,
 // so one launch needs no grid-wide barrier.  The two-pass structure of Section
@@ -45,6 +52,9 @@ constexpr int kThreads = kTileW * kTileH;  // 256 = 4 x wave64
 constexpr int kWave = 64;
 constexpr unsigned kSetCap = 1024;          // LDS key-set slots per workgroup
 constexpr unsigned kSetNone = 0x7FFu;       // "no LDS slot" (set full)
+constexpr unsigned kAccBlocks = 8;          // blocks aggregated in LDS per pass
+constexpr int kProbeAhead = 4;              // table slots read per probe step
+constexpr unsigned kAccSlots = kAccBlocks * TSDF_BLOCK_VOXELS;
 // A publication is one store after the winner's compare-exchange, so a wait is a
 // handful of steps.  A wait this long means the invariant broke: report it as
 // INTERNAL instead of spinning forever.
@@ -102,6 +112,22 @@ __device__ __forceinline__ unsigned wave_sum_small(unsigned v) {
   return s;
 }
 
+// Sum over the wave of any per-lane count; every lane receives the total.
+__device__ __forceinline__ unsigned wave_sum(unsigned v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += (unsigned)__shfl_xor((int)v, off, kWave);
+  return v;
+}
+
+__device__ __forceinline__ unsigned wave_max(unsigned v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned o = (unsigned)__shfl_xor((int)v, off, kWave);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
 // ---------------------------------------------------------------------------
 // Atomics.  Agent scope: workgroups on every XCD see one another's claims.
 // ---------------------------------------------------------------------------
@@ -140,13 +166,13 @@ template <bool kInsert>
 __device__ int resolve_key(const VolumeDev& vol, unsigned long long want, bool active,
                            unsigned& probes_out, bool& missing_out) {
   const unsigned C = vol.table_capacity;
-  unsigned slot = active ? home_slot(want, C) : 0u;
+  unsigned slot = active ? home_slot(want, C) : 0u;  // the slot at distance `probes`
   unsigned probes = 0, waits = 0;
   bool waiting = false, busy = active, missing = false, broken = false;
   int result = kBlockTableFull;
   while (busy) {
+    bool won = false;
     TableEntry* e = vol.table + slot;
-    bool won = false, advance = false;
     if (waiting) {
       // only while waiting is the index read with an atomic (coherent) load
       const int b = __hip_atomic_load(&e->block, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -158,36 +184,71 @@ __device__ int resolve_key(const VolumeDev& vol, unsigned long long want, bool a
         busy = false;
       }
     } else {
-      // plain, cacheable first read: a stale key costs one more step, a stale
-      // index only enters the wait
-      const TableEntry en = *e;
-      if (en.key == want) {
-        if (en.block != kBlockPublishing) {
-          result = en.block;
-          busy = false;
-        } else {
-          waiting = true;
+      // Read kProbeAhead consecutive slots with plain, cacheable loads issued
+      // together (one memory latency per step instead of one per slot), then
+      // examine them in probe order.  A stale key costs one more step; a stale
+      // index only enters the wait.
+      unsigned sl[kProbeAhead];
+      TableEntry en[kProbeAhead];
+#pragma unroll
+      for (int i = 0; i < kProbeAhead; ++i) {
+        sl[i] = (i == 0) ? slot : ((sl[i - 1] + 1 == C) ? 0u : sl[i - 1] + 1);
+        en[i] = vol.table[sl[i]];
+      }
+      // the first candidate in probe order (compile-time indices only, so the
+      // read-ahead stays in registers)
+      int at = -1;
+      bool is_key = false;
+      unsigned at_slot = 0;
+      int at_block = 0;
+#pragma unroll
+      for (int i = kProbeAhead - 1; i >= 0; --i) {
+        const bool cand = (probes + (unsigned)i < C) &&
+                          (en[i].key == want || en[i].key == kEmptyKey);
+        if (cand) {
+          at = i;
+          is_key = en[i].key == want;
+          at_slot = sl[i];
+          at_block = en[i].block;
         }
-      } else if (en.key == kEmptyKey) {
-        if (kInsert) {
+      }
+      if (at < 0) {
+        // none of them: move on (a full cyclic scan means the table is full)
+        probes += kProbeAhead;
+        slot = (sl[kProbeAhead - 1] + 1 == C) ? 0u : sl[kProbeAhead - 1] + 1;
+        if (probes >= C) {
+          result = kBlockTableFull;
+          busy = false;
+        }
+      } else {
+        probes += (unsigned)at;
+        slot = at_slot;
+        e = vol.table + slot;
+        if (is_key) {
+          if (at_block != kBlockPublishing) {
+            result = at_block;
+            busy = false;
+          } else {
+            waiting = true;
+          }
+        } else if (kInsert) {
           const unsigned long long prev = cas_key(&e->key, kEmptyKey, want);
-          if (prev == kEmptyKey) won = true;
-          else if (prev == want) waiting = true;
-          else advance = true;  // another key took the slot: keep probing
+          if (prev == kEmptyKey) {
+            won = true;
+          } else if (prev == want) {
+            waiting = true;
+          } else {  // another key took the slot: keep probing after it
+            ++probes;
+            slot = (slot + 1 == C) ? 0u : slot + 1;
+            if (probes >= C) {
+              result = kBlockTableFull;
+              busy = false;
+            }
+          }
         } else {
           missing = true;  // lookup only: an empty slot ends the chain
           busy = false;
         }
-      } else {
-        advance = true;
-      }
-    }
-    if (advance) {
-      if (++probes >= C) {  // a full cyclic scan: the table is full
-        result = kBlockTableFull;
-        busy = false;
-      } else {
-        slot = (slot + 1 == C) ? 0u : slot + 1;
       }
     }
     // winners take consecutive pool indices with one atomic per wave
@@ -271,8 +332,8 @@ __device__ __forceinline__ Sample walk_sample(const FrameDev& f, float d, float 
 }
 
 // Per-sample state carried from phase 1 to phase 3 in one register:
-// bit 31 valid pair, bits 9..19 LDS slot (kSetNone when the set overflowed),
-// bits 0..8 in-block voxel index.
+// bit 31 valid pair, bits 9..19 LDS slot (kSetNone when the set overflowed;
+// replaced by the dense block id in phase 3), bits 0..8 in-block voxel index.
 constexpr unsigned kPairValid = 1u << 31;
 
 __device__ __forceinline__ unsigned tile_of_group(unsigned g, unsigned n_tiles, bool remap) {
@@ -293,18 +354,28 @@ __global__ __launch_bounds__(kThreads) void fuse_kernel(VolumeDev vol, FrameDev 
   constexpr bool kInsert = kMode != FuseMode::kIntegrate;
   constexpr bool kAccumulate = kMode != FuseMode::kAllocate;
 
-  __shared__ unsigned long long s_keys[kSetCap];
-  __shared__ int s_block[kSetCap];
-  __shared__ unsigned short s_list[kSetCap];
-  __shared__ unsigned s_n;
-  __shared__ unsigned s_probe_max;
+  // The key set is dead once phase 2 has read it; its space is reused by the
+  // phase-3 accumulator.
+  union SharedSet {
+    struct {
+      unsigned long long keys[kSetCap];
+      unsigned n;  // distinct keys in the set
+    } set;
+    struct {
+      float sum[kAccSlots];
+      float cnt[kAccSlots];
+    } acc;
+  };
+  __shared__ SharedSet sh;
+  __shared__ int s_blockd[kSetCap];            // pool index per dense block id
+  __shared__ unsigned short s_dense[kSetCap];  // dense block id per set slot
+  __shared__ unsigned short s_list[kSetCap];   // set slot per dense block id
+  unsigned long long* const s_keys = sh.set.keys;
+  unsigned* const s_n = &sh.set.n;
 
   const unsigned tid = threadIdx.x;
   for (unsigned i = tid; i < kSetCap; i += kThreads) s_keys[i] = kEmptyKey;
-  if (tid == 0) {
-    s_n = 0;
-    s_probe_max = 0;
-  }
+  if (tid == 0) *s_n = 0;
 
   const unsigned tile = tile_of_group(blockIdx.x, n_tiles, remap != 0);
   const unsigned px = (tile % tiles_x) * kTileW + (tid % kTileW);
@@ -347,31 +418,25 @@ __global__ __launch_bounds__(kThreads) void fuse_kernel(VolumeDev vol, FrameDev 
     // consecutive samples of a point mostly share a block: reuse its slot
     const bool need = pair && key != prev_key;
     unsigned slot = prev_slot;
-    unsigned long long pending = __ballot(need);
-    while (pending) {
-      const int leader = __ffsll((long long)pending) - 1;
-      const unsigned long long lk = readlane64(key, leader);
-      const bool same = need && key == lk;
-      pending &= ~__ballot(same);
-      unsigned ls = kSetNone;
-      if ((int)lane_id() == leader) {
-        unsigned h = set_home(lk);
-        for (unsigned i = 0; i < kSetCap; ++i) {
-          const unsigned long long old = atomicCAS(&s_keys[h], kEmptyKey, lk);
-          if (old == kEmptyKey) {
-            s_list[atomicAdd(&s_n, 1u)] = (unsigned short)h;
-            ls = h;
-            break;
-          }
-          if (old == lk) {
-            ls = h;
-            break;
-          }
-          h = (h + 1) & (kSetCap - 1);
+    if (need) {
+      // every lane inserts its own key; the LDS serialises lanes of one wave that
+      // aim at the same slot, so exactly one of them claims it and the others
+      // find the key there
+      unsigned h = set_home(key);
+      slot = kSetNone;
+      for (unsigned i = 0; i < kSetCap; ++i) {
+        const unsigned long long old = atomicCAS(&s_keys[h], kEmptyKey, key);
+        if (old == kEmptyKey) {
+          s_list[atomicAdd(s_n, 1u)] = (unsigned short)h;
+          slot = h;
+          break;
         }
+        if (old == key) {
+          slot = h;
+          break;
+        }
+        h = (h + 1) & (kSetCap - 1);
       }
-      ls = (unsigned)__builtin_amdgcn_readlane((int)ls, leader);
-      if (same) slot = ls;
     }
     if (pair) {
       prev_key = key;
@@ -382,7 +447,7 @@ __global__ __launch_bounds__(kThreads) void fuse_kernel(VolumeDev vol, FrameDev 
   __syncthreads();
 
   // ---- phase 2: resolve each distinct key of the tile once ----------------
-  const unsigned n_keys = s_n;
+  const unsigned n_keys = *s_n;
   unsigned my_probe_max = 0;
   unsigned my_missing = 0;
   for (unsigned base = 0; base < n_keys; base += kThreads) {
@@ -394,35 +459,34 @@ __global__ __launch_bounds__(kThreads) void fuse_kernel(VolumeDev vol, FrameDev 
     bool missing = false;
     const int blk = resolve_key<kInsert>(vol, key, act, probes, missing);
     if (act) {
-      s_block[h] = blk;
+      s_blockd[j] = blk;
+      s_dense[h] = (unsigned short)j;
       my_probe_max = probes > my_probe_max ? probes : my_probe_max;
       my_missing += missing ? 1u : 0u;
     }
   }
-  if (my_probe_max) atomicMax(&s_probe_max, my_probe_max);
   __syncthreads();
 
   // ---- phase 3: integrate --------------------------------------------------
   unsigned n_drop = 0;
   if (kAccumulate) {
+    // LDS slot -> dense block id; pairs beyond the LDS set go straight to HBM
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const unsigned w = st[s];
-      if (w & kPairValid) {
-        const unsigned slot = (w >> 9) & 0x7FFu;
-        int blk;
-        if (slot != kSetNone) {
-          blk = s_block[slot];
-        } else {
-          // the tile had more distinct blocks than the LDS set holds: resolve
-          // this pair's key directly (same protocol, same result)
-          const Sample smp = walk_sample(f, d, a, b, s - K);
-          unsigned probes = 0;
-          bool missing = false;
-          blk = resolve_key<kInsert>(vol, pack_key(smp.vx >> 3, smp.vy >> 3, smp.vz >> 3), true,
-                                     probes, missing);
-          my_missing += missing ? 1u : 0u;
-        }
+      if (!(w & kPairValid)) continue;
+      const unsigned slot = (w >> 9) & 0x7FFu;
+      if (slot != kSetNone) {
+        st[s] = kPairValid | ((unsigned)s_dense[slot] << 9) | (w & 511u);
+      } else {
+        // the tile had more distinct blocks than the LDS set holds: resolve
+        // this pair's key directly (same protocol, same result)
+        const Sample smp = walk_sample(f, d, a, b, s - K);
+        unsigned probes = 0;
+        bool missing = false;
+        const int blk = resolve_key<kInsert>(vol, pack_key(smp.vx >> 3, smp.vy >> 3, smp.vz >> 3),
+                                             true, probes, missing);
+        my_missing += missing ? 1u : 0u;
         if (blk >= 0) {
           const size_t i = (size_t)blk * TSDF_BLOCK_VOXELS + (w & 511u);
           add_f32(vol.tsdf + i, val[s]);
@@ -430,7 +494,47 @@ __global__ __launch_bounds__(kThreads) void fuse_kernel(VolumeDev vol, FrameDev 
         } else {
           ++n_drop;
         }
+        st[s] = 0u;
       }
+    }
+    for (unsigned i = tid; i < kAccSlots; i += kThreads) {
+      sh.acc.sum[i] = 0.0f;
+      sh.acc.cnt[i] = 0.0f;
+    }
+    __syncthreads();
+    for (unsigned lo = 0; lo < n_keys; lo += kAccBlocks) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const unsigned w = st[s];
+        const unsigned db = ((w >> 9) & 0x7FFu) - lo;
+        if ((w & kPairValid) && db < kAccBlocks) {
+          const unsigned i = db * TSDF_BLOCK_VOXELS + (w & 511u);
+          __hip_atomic_fetch_add(&sh.acc.sum[i], val[s], __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+          __hip_atomic_fetch_add(&sh.acc.cnt[i], 1.0f, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (unsigned c = 0; c < kAccSlots / kThreads; ++c) {
+        const unsigned slot = c * kThreads + tid;
+        const unsigned db = slot / TSDF_BLOCK_VOXELS;
+        const float cn = sh.acc.cnt[slot];
+        if (cn != 0.0f) {
+          const int blk = s_blockd[lo + db];
+          if (blk >= 0) {
+            const size_t i = (size_t)blk * TSDF_BLOCK_VOXELS + (slot % TSDF_BLOCK_VOXELS);
+            add_f32(vol.tsdf + i, sh.acc.sum[slot]);
+            add_f32(vol.weight + i, cn);
+          } else {
+            n_drop += (unsigned)cn;
+          }
+          sh.acc.sum[slot] = 0.0f;
+          sh.acc.cnt[slot] = 0.0f;
+        }
+      }
+      __syncthreads();
     }
   }
 
@@ -444,7 +548,7 @@ __global__ __launch_bounds__(kThreads) void fuse_kernel(VolumeDev vol, FrameDev 
     if (leader && n_pts) add_u64(&vol.ctr->points_valid[sh], n_pts);
     if (leader && pw) add_u64(&vol.ctr->pairs[sh], pw);
     if (__ballot(n_drop)) {
-      const unsigned dw = wave_sum_small(n_drop);
+      const unsigned dw = wave_sum(n_drop);
       if (leader) add_u64(&vol.ctr->pairs_dropped, dw);
     }
     if (__ballot(n_oor)) {
@@ -456,11 +560,11 @@ __global__ __launch_bounds__(kThreads) void fuse_kernel(VolumeDev vol, FrameDev 
     const unsigned mw = wave_sum_small(my_missing);
     if (leader) add_u32(&vol.ctr->lookup_misses, mw);
   }
-  if (tid == 0 && s_probe_max) {
+  if (__ballot(my_probe_max)) {
+    const unsigned pm = wave_max(my_probe_max);
     // a plain read filters almost every update; the atomic keeps the maximum exact
-    if (s_probe_max > *(volatile unsigned*)&vol.ctr->max_probe)
-      __hip_atomic_fetch_max(&vol.ctr->max_probe, s_probe_max, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
+    if (leader && pm > *(volatile unsigned*)&vol.ctr->max_probe)
+      __hip_atomic_fetch_max(&vol.ctr->max_probe, pm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
