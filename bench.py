@@ -59,7 +59,7 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="approximate CPU time for the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", choices=["fused", "two_pass", "fused_no_remap"], default="fused")
+    ap.add_argument("--mode", choices=["fused", "two_pass", "fused_xcd_remap"], default="fused")
     ap.add_argument("--profile-copy-bytes", type=int, default=0,
                     help="after the run, copy this many bytes device-to-device three times "
                          "(a kernel of known traffic for scaling hardware byte counters)")
@@ -79,7 +79,7 @@ def main() -> int:
         return 1
     torch.cuda.set_device(0)
     flags = {"fused": T.FUSE_DEFAULT, "two_pass": T.FUSE_TWO_PASS,
-             "fused_no_remap": T.FUSE_NO_XCD_REMAP}[args.mode]
+             "fused_xcd_remap": T.FUSE_XCD_REMAP}[args.mode]
 
     # ---- inputs, resident in HBM ---------------------------------------------
     t0 = time.time()
@@ -114,11 +114,11 @@ def main() -> int:
     prev_blocks = 0
     wv = vol.weight_view()
     for k in range(len(ptrs)):
-        before = wv[:prev_blocks].clone()
+        before = wv[:prev_blocks].reshape(prev_blocks, 512).clone()
         vol.fuse(depth[k], cams[k], flags)
         st = vol.stats()
         nb = st.blocks_total
-        after = wv[:nb]
+        after = wv[:nb].reshape(nb, 512)
         changed = after != torch.nn.functional.pad(before, (0, 0, 0, nb - prev_blocks))
         V = int(changed.sum())
         Bt = int(changed.any(dim=1).sum())

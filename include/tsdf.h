@@ -106,12 +106,16 @@ typedef struct tsdf_stats {
  *                uint32 pad}, key TSDF_EMPTY_KEY when free; block >= 0 is a pool
  *                index, -1 = being published, -2 = the pool was full
  *   block_keys : pool_capacity uint64, the key of each allocated pool block
- *   tsdf       : pool_capacity * 512 float, the sum of truncated signed distances
- *   weight     : pool_capacity * 512 float, the number of contributions
- * Voxel (lx, ly, lz) of pool block b lives at index b * 512 + (lz * 8 + ly) * 8 + lx
- * of both arrays (x fastest). */
+ *   voxels     : pool_capacity * 1024 float, the voxel pool.  Voxel (lx, ly, lz)
+ *                of block b has in-block index loc = (lz * 8 + ly) * 8 + lx
+ *                (x fastest) and lies in x-row r = loc / 8; each row is one
+ *                64-byte segment holding its 8 TSDF sums then its 8 weights:
+ *                  TSDF sum : voxels[b * 1024 + r * 16 + lx]
+ *                  weight   : voxels[b * 1024 + r * 16 + 8 + lx]
+ *                Weights count contributions; TSDF values are sums (the mean is
+ *                sum / weight).  tsdf_extract_blocks returns plain arrays. */
 typedef struct tsdf_layout {
-  uint64_t counters, table, block_keys, tsdf, weight, total_bytes;
+  uint64_t counters, table, block_keys, voxels, total_bytes;
   uint32_t table_capacity, pool_capacity;
 } tsdf_layout;
 
@@ -149,15 +153,15 @@ tsdf_status tsdf_fuse_frame(tsdf_volume* vol, const float* depth_dev, const tsdf
  *   TSDF_FUSE_ALLOCATE_ONLY / TSDF_FUSE_INTEGRATE_ONLY  one stage of TWO_PASS
  *                       (for stage timing; integrate-only assumes the frame's
  *                       blocks were allocated before)
- *   | TSDF_FUSE_NO_XCD_REMAP  dispatch tiles in plain row-major order instead of
- *                       giving each XCD a contiguous band of the image
+ *   | TSDF_FUSE_XCD_REMAP  give each of the 8 XCDs a contiguous band of tiles
+ *                       instead of the hardware's round-robin of row-major tiles
  * Results are identical for every choice (up to float summation order). */
 #define TSDF_FUSE_DEFAULT 0u
 #define TSDF_FUSE_TWO_PASS 1u
 #define TSDF_FUSE_ALLOCATE_ONLY 2u
 #define TSDF_FUSE_INTEGRATE_ONLY 3u
 #define TSDF_FUSE_MODE_MASK 3u
-#define TSDF_FUSE_NO_XCD_REMAP 0x100u
+#define TSDF_FUSE_XCD_REMAP 0x100u
 tsdf_status tsdf_fuse_frame_ex(tsdf_volume* vol, const float* depth_dev, const tsdf_camera* cam,
                                uint32_t flags, void* hip_stream);
 

@@ -61,10 +61,8 @@ bool make_layout(const tsdf_volume_params* p, tsdf_layout* out) {
   off = align_up(off + (uint64_t)C * sizeof(tsdf::TableEntry));
   L.block_keys = off;
   off = align_up(off + (uint64_t)p->pool_capacity * 8ull);
-  L.tsdf = off;
-  off = align_up(off + (uint64_t)p->pool_capacity * TSDF_BLOCK_VOXELS * 4ull);
-  L.weight = off;
-  off = align_up(off + (uint64_t)p->pool_capacity * TSDF_BLOCK_VOXELS * 4ull);
+  L.voxels = off;
+  off = align_up(off + (uint64_t)p->pool_capacity * tsdf::kBlockFloats * 4ull);
   L.total_bytes = off;
   L.table_capacity = C;
   L.pool_capacity = p->pool_capacity;
@@ -125,15 +123,13 @@ tsdf_status tsdf_create_volume(const tsdf_volume_params* params, void* dev_arena
   v->dev.ctr = reinterpret_cast<tsdf::DevCounters*>(base + L.counters);
   v->dev.table = reinterpret_cast<tsdf::TableEntry*>(base + L.table);
   v->dev.block_keys = reinterpret_cast<unsigned long long*>(base + L.block_keys);
-  v->dev.tsdf = reinterpret_cast<float*>(base + L.tsdf);
-  v->dev.weight = reinterpret_cast<float*>(base + L.weight);
+  v->dev.voxels = reinterpret_cast<float*>(base + L.voxels);
   v->dev.table_capacity = L.table_capacity;
   v->dev.pool_capacity = L.pool_capacity;
   hipStream_t s = as_stream(hip_stream);
   tsdf_status st = init_table_and_counters(v, s);
-  const size_t pool_words = (size_t)L.pool_capacity * TSDF_BLOCK_VOXELS;
-  if (st == TSDF_OK) st = hip_status(tsdf::launch_fill_u32(v->dev.tsdf, 0u, pool_words, s));
-  if (st == TSDF_OK) st = hip_status(tsdf::launch_fill_u32(v->dev.weight, 0u, pool_words, s));
+  const size_t pool_words = (size_t)L.pool_capacity * tsdf::kBlockFloats;
+  if (st == TSDF_OK) st = hip_status(tsdf::launch_fill_u32(v->dev.voxels, 0u, pool_words, s));
   if (st == TSDF_OK)
     st = hip_status(tsdf::launch_fill_u32(v->dev.block_keys, 0xFFFFFFFFu,
                                           (size_t)L.pool_capacity * 2, s));
@@ -165,7 +161,7 @@ tsdf_status tsdf_reset_volume(tsdf_volume* vol, void* hip_stream) {
 tsdf_status tsdf_fuse_frame_ex(tsdf_volume* vol, const float* depth_dev, const tsdf_camera* cam,
                                uint32_t flags, void* hip_stream) {
   if (!vol || !valid_camera(cam)) return TSDF_ERR_INVALID_ARGUMENT;
-  if ((flags & ~(TSDF_FUSE_MODE_MASK | TSDF_FUSE_NO_XCD_REMAP)) != 0)
+  if ((flags & ~(TSDF_FUSE_MODE_MASK | TSDF_FUSE_XCD_REMAP)) != 0)
     return TSDF_ERR_INVALID_ARGUMENT;
   const uint64_t n_pix = (uint64_t)cam->width * cam->height;
   if (n_pix > 0 && !depth_dev) return TSDF_ERR_INVALID_ARGUMENT;
@@ -185,7 +181,7 @@ tsdf_status tsdf_fuse_frame_ex(tsdf_volume* vol, const float* depth_dev, const t
   f.iv = 1.0f / vol->params.voxel_size;
   f.trunc = vol->params.trunc;
   f.K = band_half(vol->params);
-  const bool remap = (flags & TSDF_FUSE_NO_XCD_REMAP) == 0;
+  const bool remap = (flags & TSDF_FUSE_XCD_REMAP) != 0;
   hipStream_t s = as_stream(hip_stream);
   hipError_t e = hipSuccess;
   if (n_pix > 0) {

@@ -48,12 +48,23 @@ static_assert(sizeof(DevCounters) == 512 + 2 * 8 * kCounterShards, "counter layo
 constexpr size_t kCountersBytes = 8192;
 static_assert(sizeof(DevCounters) <= kCountersBytes, "counters fit their region");
 
+// Voxel pool layout: block b owns 1024 floats at b * kBlockFloats.  Each x-row
+// of 8 voxels (row r = lz * 8 + ly) is one 64-byte segment holding the 8 TSDF
+// sums then the 8 weights, so that one memory-side atomic request carries both
+// accumulators of a row.
+constexpr unsigned kBlockFloats = 1024;
+__host__ __device__ constexpr unsigned pool_tsdf_index(unsigned loc) {
+  return (loc >> 3) * 16u + (loc & 7u);
+}
+__host__ __device__ constexpr unsigned pool_weight_index(unsigned loc) {
+  return (loc >> 3) * 16u + 8u + (loc & 7u);
+}
+
 struct VolumeDev {
   DevCounters* ctr;
   TableEntry* table;
   unsigned long long* block_keys;
-  float* tsdf;
-  float* weight;
+  float* voxels;  // pool_capacity * kBlockFloats
   unsigned table_capacity;
   unsigned pool_capacity;
 };

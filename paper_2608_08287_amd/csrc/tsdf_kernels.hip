@@ -21,13 +21,15 @@
 //                publication" means "look again next iteration"), so a waiter
 //                never spins while a publisher in its own wave is masked off.
 //   3. integrate -- the tile's contributions are first summed in LDS, kAccBlocks
-//                blocks at a time, in a dense 512-voxel accumulator per block;
-//                each pass then flushes its touched voxels into the flat SoA pool
-//                with agent-scope float atomics, 64 consecutive voxels of one block
-//                per wave instruction.  A voxel thus receives one atomic per
-//                workgroup instead of one per contribution, and each instruction
-//                hits two 128-byte lines with distinct addresses: the pool's
-//                read-modify-write traffic is line-coalesced instead of scattered.
+//                blocks at a time, in a dense accumulator laid out exactly like a
+//                pool block; each pass then flushes it with agent-scope float
+//                atomics, four 8-voxel rows per wave instruction.  Device-scope
+//                float atomics on gfx950 are performed beyond L2 at about 20 G
+//                requests/s, one request per touched 64-byte segment per
+//                instruction whatever its lane count, so the cost is the number of
+//                (tile, row) pairs: a voxel gets one update per tile, not one per
+//                contribution, and the row's TSDF sums and weights share a
+//                segment (see the pool layout in tsdf_internal.h).
 //
 // A workgroup only ever accumulates into blocks whose indices it resolved itself,
 // so one launch needs no grid-wide barrier.  The two-pass structure of Section
@@ -54,7 +56,7 @@ constexpr unsigned kSetCap = 1024;          // LDS key-set slots per workgroup
 constexpr unsigned kSetNone = 0x7FFu;       // "no LDS slot" (set full)
 constexpr unsigned kAccBlocks = 8;          // blocks aggregated in LDS per pass
 constexpr int kProbeAhead = 4;              // table slots read per probe step
-constexpr unsigned kAccSlots = kAccBlocks * TSDF_BLOCK_VOXELS;
+constexpr unsigned kAccSlots = kAccBlocks * kBlockFloats;  // sums and counts
 // A publication is one store after the winner's compare-exchange, so a wait is a
 // handful of steps.  A wait this long means the invariant broke: report it as
 // INTERNAL instead of spinning forever.
@@ -361,10 +363,7 @@ __global__ __launch_bounds__(kThreads) void fuse_kernel(VolumeDev vol, FrameDev 
       unsigned long long keys[kSetCap];
       unsigned n;  // distinct keys in the set
     } set;
-    struct {
-      float sum[kAccSlots];
-      float cnt[kAccSlots];
-    } acc;
+    float acc[kAccSlots];  // kAccBlocks blocks in the pool's own layout
   };
   __shared__ SharedSet sh;
   __shared__ int s_blockd[kSetCap];            // pool index per dense block id
@@ -488,19 +487,16 @@ __global__ __launch_bounds__(kThreads) void fuse_kernel(VolumeDev vol, FrameDev 
                                              true, probes, missing);
         my_missing += missing ? 1u : 0u;
         if (blk >= 0) {
-          const size_t i = (size_t)blk * TSDF_BLOCK_VOXELS + (w & 511u);
-          add_f32(vol.tsdf + i, val[s]);
-          add_f32(vol.weight + i, 1.0f);
+          float* bp = vol.voxels + (size_t)blk * kBlockFloats;
+          add_f32(bp + pool_tsdf_index(w & 511u), val[s]);
+          add_f32(bp + pool_weight_index(w & 511u), 1.0f);
         } else {
           ++n_drop;
         }
         st[s] = 0u;
       }
     }
-    for (unsigned i = tid; i < kAccSlots; i += kThreads) {
-      sh.acc.sum[i] = 0.0f;
-      sh.acc.cnt[i] = 0.0f;
-    }
+    for (unsigned i = tid; i < kAccSlots; i += kThreads) sh.acc[i] = 0.0f;
     __syncthreads();
     for (unsigned lo = 0; lo < n_keys; lo += kAccBlocks) {
 #pragma unroll
@@ -508,31 +504,42 @@ __global__ __launch_bounds__(kThreads) void fuse_kernel(VolumeDev vol, FrameDev 
         const unsigned w = st[s];
         const unsigned db = ((w >> 9) & 0x7FFu) - lo;
         if ((w & kPairValid) && db < kAccBlocks) {
-          const unsigned i = db * TSDF_BLOCK_VOXELS + (w & 511u);
-          __hip_atomic_fetch_add(&sh.acc.sum[i], val[s], __ATOMIC_RELAXED,
+          float* ab = &sh.acc[db * kBlockFloats];
+          __hip_atomic_fetch_add(ab + pool_tsdf_index(w & 511u), val[s], __ATOMIC_RELAXED,
                                  __HIP_MEMORY_SCOPE_WORKGROUP);
-          __hip_atomic_fetch_add(&sh.acc.cnt[i], 1.0f, __ATOMIC_RELAXED,
+          __hip_atomic_fetch_add(ab + pool_weight_index(w & 511u), 1.0f, __ATOMIC_RELAXED,
                                  __HIP_MEMORY_SCOPE_WORKGROUP);
         }
       }
       __syncthreads();
+      // flush: per block, each thread owns floats tid + 256q (q = 0..3) of the
+      // block's 1024; a wave instruction covers 64 consecutive floats = 4 rows,
+      // one 64-byte memory-side atomic request per touched row.  All LDS reads
+      // of a block are issued before any atomic or clearing write, so the
+      // flush pays one LDS latency per block rather than one per float.
+      for (unsigned bb = 0; bb < kAccBlocks && lo + bb < n_keys; ++bb) {
+        const int blk = s_blockd[lo + bb];  // uniform across the workgroup
+        float* ab = &sh.acc[bb * kBlockFloats];
+        float v[4], cn[4];
 #pragma unroll
-      for (unsigned c = 0; c < kAccSlots / kThreads; ++c) {
-        const unsigned slot = c * kThreads + tid;
-        const unsigned db = slot / TSDF_BLOCK_VOXELS;
-        const float cn = sh.acc.cnt[slot];
-        if (cn != 0.0f) {
-          const int blk = s_blockd[lo + db];
-          if (blk >= 0) {
-            const size_t i = (size_t)blk * TSDF_BLOCK_VOXELS + (slot % TSDF_BLOCK_VOXELS);
-            add_f32(vol.tsdf + i, sh.acc.sum[slot]);
-            add_f32(vol.weight + i, cn);
-          } else {
-            n_drop += (unsigned)cn;
-          }
-          sh.acc.sum[slot] = 0.0f;
-          sh.acc.cnt[slot] = 0.0f;
+        for (int q = 0; q < 4; ++q) {
+          const unsigned i = q * kThreads + tid;
+          v[q] = ab[i];
+          cn[q] = ab[(i & ~15u) + 8u + (i & 7u)];  // this voxel's count
         }
+        if (blk >= 0) {
+          float* bp = vol.voxels + (size_t)blk * kBlockFloats;
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (cn[q] != 0.0f) add_f32(bp + q * kThreads + tid, v[q]);
+        } else if (tid & 8u) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) n_drop += (unsigned)cn[q];
+        }
+        // every lane of a wave has read its rows before any lane clears them
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (cn[q] != 0.0f) ab[q * kThreads + tid] = 0.0f;
       }
       __syncthreads();
     }
@@ -603,35 +610,40 @@ __global__ __launch_bounds__(256) void fill_u32_kernel(unsigned* p, unsigned val
 __global__ __launch_bounds__(256) void reset_used_kernel(VolumeDev vol) {
   unsigned used = *(volatile unsigned*)&vol.ctr->block_count;
   used = used < vol.pool_capacity ? used : vol.pool_capacity;
-  const size_t n4 = (size_t)used * (TSDF_BLOCK_VOXELS / 4);
+  const size_t n4 = (size_t)used * (kBlockFloats / 4);
   const size_t stride = (size_t)gridDim.x * 256u;
-  float4* t4 = reinterpret_cast<float4*>(vol.tsdf);
-  float4* w4 = reinterpret_cast<float4*>(vol.weight);
+  float4* v4 = reinterpret_cast<float4*>(vol.voxels);
   const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-  for (size_t i = blockIdx.x * 256u + threadIdx.x; i < n4; i += stride) {
-    t4[i] = z;
-    w4[i] = z;
-  }
+  for (size_t i = blockIdx.x * 256u + threadIdx.x; i < n4; i += stride) v4[i] = z;
 }
 
+// One thread per x-row of 8 voxels: read the row's 64-byte segment, write the
+// 8 means and 8 weights in flat x-fastest order.
 __global__ __launch_bounds__(256) void extract_kernel(VolumeDev vol, unsigned n_blocks,
                                                       unsigned long long* keys, float* tsdf,
                                                       float* weight) {
-  const size_t n4 = (size_t)n_blocks * (TSDF_BLOCK_VOXELS / 4);
+  const size_t n_rows = (size_t)n_blocks * (TSDF_BLOCK_VOXELS / 8);
   const size_t stride = (size_t)gridDim.x * 256u;
-  const float4* t4 = reinterpret_cast<const float4*>(vol.tsdf);
-  const float4* w4 = reinterpret_cast<const float4*>(vol.weight);
-  for (size_t i = blockIdx.x * 256u + threadIdx.x; i < n4; i += stride) {
-    const float4 t = t4[i], w = w4[i];
+  const float4* v4 = reinterpret_cast<const float4*>(vol.voxels);
+  for (size_t r = blockIdx.x * 256u + threadIdx.x; r < n_rows; r += stride) {
+    const float4 s0 = v4[4 * r], s1 = v4[4 * r + 1], w0 = v4[4 * r + 2], w1 = v4[4 * r + 3];
     if (tsdf) {
-      float4 m;
-      m.x = w.x > 0.f ? t.x / w.x : 0.f;
-      m.y = w.y > 0.f ? t.y / w.y : 0.f;
-      m.z = w.z > 0.f ? t.z / w.z : 0.f;
-      m.w = w.w > 0.f ? t.w / w.w : 0.f;
-      reinterpret_cast<float4*>(tsdf)[i] = m;
+      float4 m0, m1;
+      m0.x = w0.x > 0.f ? s0.x / w0.x : 0.f;
+      m0.y = w0.y > 0.f ? s0.y / w0.y : 0.f;
+      m0.z = w0.z > 0.f ? s0.z / w0.z : 0.f;
+      m0.w = w0.w > 0.f ? s0.w / w0.w : 0.f;
+      m1.x = w1.x > 0.f ? s1.x / w1.x : 0.f;
+      m1.y = w1.y > 0.f ? s1.y / w1.y : 0.f;
+      m1.z = w1.z > 0.f ? s1.z / w1.z : 0.f;
+      m1.w = w1.w > 0.f ? s1.w / w1.w : 0.f;
+      reinterpret_cast<float4*>(tsdf)[2 * r] = m0;
+      reinterpret_cast<float4*>(tsdf)[2 * r + 1] = m1;
     }
-    if (weight) reinterpret_cast<float4*>(weight)[i] = w;
+    if (weight) {
+      reinterpret_cast<float4*>(weight)[2 * r] = w0;
+      reinterpret_cast<float4*>(weight)[2 * r + 1] = w1;
+    }
   }
   if (keys)
     for (size_t i = blockIdx.x * 256u + threadIdx.x; i < n_blocks; i += stride)
@@ -679,7 +691,7 @@ hipError_t launch_fill_u32(void* ptr, unsigned value, size_t n_words, hipStream_
 
 hipError_t launch_reset_used(VolumeDev vol, hipStream_t s) {
   hipLaunchKernelGGL(reset_used_kernel,
-                     dim3(grid_for((size_t)vol.pool_capacity * (TSDF_BLOCK_VOXELS / 4), 8192)),
+                     dim3(grid_for((size_t)vol.pool_capacity * (kBlockFloats / 4), 8192)),
                      dim3(256), 0, s, vol);
   return hipGetLastError();
 }
@@ -708,7 +720,7 @@ hipError_t launch_insert_blocks(VolumeDev vol, const int* coords, unsigned n, hi
 hipError_t launch_extract(VolumeDev vol, unsigned n_blocks, unsigned long long* keys,
                           float* tsdf, float* weight, hipStream_t s) {
   if (n_blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(extract_kernel, dim3(grid_for((size_t)n_blocks * 128, 8192)), dim3(256), 0,
+  hipLaunchKernelGGL(extract_kernel, dim3(grid_for((size_t)n_blocks * 64, 8192)), dim3(256), 0,
                      s, vol, n_blocks, keys, tsdf, weight);
   return hipGetLastError();
 }

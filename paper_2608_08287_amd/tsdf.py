@@ -24,7 +24,7 @@ OK, ERR_INVALID_ARGUMENT, ERR_BUFFER_TOO_SMALL, ERR_POOL_EXHAUSTED, ERR_TABLE_FU
     ERR_COORD_RANGE, ERR_INTERNAL, ERR_HIP = range(8)
 FLAG_POOL_EXHAUSTED, FLAG_TABLE_FULL, FLAG_COORD_RANGE, FLAG_INTERNAL = 1, 2, 4, 8
 FUSE_DEFAULT, FUSE_TWO_PASS, FUSE_ALLOCATE_ONLY, FUSE_INTEGRATE_ONLY = 0, 1, 2, 3
-FUSE_NO_XCD_REMAP = 0x100
+FUSE_XCD_REMAP = 0x100
 BLOCK_VOXELS = 512
 EMPTY_KEY = 0xFFFFFFFFFFFFFFFF
 
@@ -57,7 +57,7 @@ class StatsC(C.Structure):
 
 class LayoutC(C.Structure):
     _fields_ = [("counters", C.c_uint64), ("table", C.c_uint64), ("block_keys", C.c_uint64),
-                ("tsdf", C.c_uint64), ("weight", C.c_uint64), ("total_bytes", C.c_uint64),
+                ("voxels", C.c_uint64), ("total_bytes", C.c_uint64),
                 ("table_capacity", C.c_uint32), ("pool_capacity", C.c_uint32)]
 
 
@@ -253,15 +253,19 @@ class Volume:
         t = self.arena[L.table:L.table + 16 * L.table_capacity]
         return t.view(torch.int64).view(L.table_capacity, 2)
 
-    def tsdf_sum_view(self) -> torch.Tensor:
+    def pool_view(self) -> torch.Tensor:
+        """(P, 64, 2, 8) float32 view of the voxel pool: [block, x-row, (sum | weight), x]."""
         L = self.layout
-        return self.arena[L.tsdf:L.tsdf + 2048 * L.pool_capacity].view(torch.float32).view(
-            L.pool_capacity, BLOCK_VOXELS)
+        return self.arena[L.voxels:L.voxels + 4096 * L.pool_capacity].view(torch.float32).view(
+            L.pool_capacity, 64, 2, 8)
+
+    def tsdf_sum_view(self) -> torch.Tensor:
+        """(P, 64, 8) strided view of the TSDF sums (x-row major within a block)."""
+        return self.pool_view()[:, :, 0, :]
 
     def weight_view(self) -> torch.Tensor:
-        L = self.layout
-        return self.arena[L.weight:L.weight + 2048 * L.pool_capacity].view(torch.float32).view(
-            L.pool_capacity, BLOCK_VOXELS)
+        """(P, 64, 8) strided view of the weights (x-row major within a block)."""
+        return self.pool_view()[:, :, 1, :]
 
     def block_keys_view(self) -> torch.Tensor:
         L = self.layout

@@ -30,12 +30,11 @@ def test_volume_bytes_and_layout():
     L = T.layout(p)
     assert L.table_capacity == 8192 and L.pool_capacity == 4096
     assert L.counters == 0
-    for off in (L.table, L.block_keys, L.tsdf, L.weight, L.total_bytes):
+    for off in (L.table, L.block_keys, L.voxels, L.total_bytes):
         assert off % 256 == 0
     assert L.block_keys - L.table >= 8192 * 16
-    assert L.tsdf - L.block_keys >= 4096 * 8
-    assert L.weight - L.tsdf == 4096 * 512 * 4
-    assert L.total_bytes - L.weight == 4096 * 512 * 4
+    assert L.voxels - L.block_keys >= 4096 * 8
+    assert L.total_bytes - L.voxels == 4096 * 1024 * 4
     assert T.volume_bytes(p) == L.total_bytes
     # table 0 -> next power of two >= 2 * pool (the paper's sizing)
     assert T.layout(T.volume_params(0.01, 0.04, 0, 4096)).table_capacity == 8192
@@ -45,7 +44,7 @@ def test_volume_bytes_and_layout():
     assert T.layout(T.volume_params(0.005, 0.02, 123457, 1 << 18)).table_capacity == 123457
     # the configuration with a 2^20-slot table and a 2^18-block pool
     big = T.layout(T.volume_params(0.005, 0.02, 1 << 20, 1 << 18))
-    assert big.total_bytes > 2 * (1 << 18) * 2048
+    assert big.total_bytes > (1 << 18) * 4096
 
 
 @pytest.mark.parametrize("vs,tr,C_,P", [

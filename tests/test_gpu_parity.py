@@ -48,8 +48,8 @@ def single():
     return w, O.fuse_workload(w)
 
 
-@pytest.mark.parametrize("flags", [T.FUSE_DEFAULT, T.FUSE_TWO_PASS, T.FUSE_NO_XCD_REMAP,
-                                   T.FUSE_TWO_PASS | T.FUSE_NO_XCD_REMAP])
+@pytest.mark.parametrize("flags", [T.FUSE_DEFAULT, T.FUSE_TWO_PASS, T.FUSE_XCD_REMAP,
+                                   T.FUSE_TWO_PASS | T.FUSE_XCD_REMAP])
 def test_single_frame_parity(single, flags):
     w, o = single
     g = run_workload(w, flags=flags, keep_volume=True)
