@@ -2,14 +2,15 @@
 """Throughput of hash-blocked TSDF fusion on one MI355X.
 
 Workload: a 300-frame, 640x480 orbit through a 4 m room with 20 random boxes and
-spheres (voxel 5 mm, truncation 2 cm, table of 2^20 slots, pool of 2^18 blocks),
-fused frame by frame through the C ABI (the plain per-frame path).
+spheres (voxel 5 mm, truncation 2 cm, table of 2^20 slots, pool of 2^18 blocks).
 
 One step = reset the volume, then fuse all frames of the trajectory into it.
-Depth frames are resident in HBM before timing starts.  The JSON line reports
-points fused per second over the timed steps, per-frame GPU latency
-percentiles, the HBM roofline fraction of the fusion kernel on algorithmic
-bytes, and the CPU oracle's throughput on a bounded sample.
+Depth frames are resident in HBM before timing starts.  The headline `value` is
+the trajectory fused through tsdf_fuse_frames (16 frames per launch); the plain
+path (one tsdf_fuse_frame launch per frame) is timed beside it and supplies the
+per-frame latency percentiles.  Also reported: the HBM roofline fraction of the
+headline path's fusion kernel on algorithmic bytes, and the CPU oracle's
+throughput on a bounded sample.
 """
 from __future__ import annotations
 
@@ -28,7 +29,7 @@ if ROOT not in sys.path:
 
 METRIC = "depth points fused/s + p50/p99 frame latency, batched-served vs plain"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_2608_08287_amd", "csrc", "tsdf_kernels.hip")
+CSRC = os.path.join(ROOT, "paper_2608_08287_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fuse_kernel_room_orbit_640x480_traffic.json")
 
 
@@ -37,8 +38,13 @@ def log(msg: str) -> None:
 
 
 def kernel_sha() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the device sources (so stored counter readings go stale on any change)."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".h", ".hip")):
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
 
 
 def algorithmic_bytes(n_pix: int, touched_blocks: int, new_blocks: int, touched_voxels: int) -> int:
@@ -59,7 +65,12 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="approximate CPU time for the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", choices=["fused", "two_pass", "fused_xcd_remap"], default="fused")
+    ap.add_argument("--mode", choices=["fused", "two_pass", "fused_xcd_remap"], default="fused",
+                    help="kernel structure of the plain per-frame path")
+    ap.add_argument("--batch", type=int, default=16,
+                    help="frames per tsdf_fuse_frames call on the headline path")
+    ap.add_argument("--per-group", type=int, default=1,
+                    help="frames summed per workgroup on the headline path (1, 2 or 4)")
     ap.add_argument("--profile-copy-bytes", type=int, default=0,
                     help="after the run, copy this many bytes device-to-device three times "
                          "(a kernel of known traffic for scaling hardware byte counters)")
@@ -98,6 +109,7 @@ def main() -> int:
     cam_refs = [T.C.byref(c) for c in cams]
 
     def fuse_all(events=None):
+        """The plain path: one launch per frame."""
         if L.tsdf_reset_volume(h, sp) != T.OK:
             raise RuntimeError("reset failed")
         for k in range(len(ptrs)):
@@ -107,6 +119,26 @@ def main() -> int:
                 raise RuntimeError("fuse failed")
         if events is not None:
             events[len(ptrs)].record(stream)
+
+    fpl = max(1, min(args.batch, 16))  # frames per launch
+    chunks = [(i, min(fpl, len(ptrs) - i)) for i in range(0, len(ptrs), fpl)]
+    ptr_arr = (T.C.c_void_p * len(ptrs))(*[d.data_ptr() for d in depth])
+    cam_arr = (T.CameraC * len(cams))(*cams)
+    bflags = T.FUSE_BATCH(args.per_group)
+
+    def fuse_batched(events=None):
+        """The headline path: tsdf_fuse_frames, `fpl` frames per launch."""
+        if L.tsdf_reset_volume(h, sp) != T.OK:
+            raise RuntimeError("reset failed")
+        for j, (i0, n) in enumerate(chunks):
+            if events is not None:
+                events[j].record(stream)
+            p = T.C.cast(T.C.byref(ptr_arr, i0 * T.C.sizeof(T.C.c_void_p)), T.C.c_void_p)
+            c = T.C.cast(T.C.byref(cam_arr, i0 * T.C.sizeof(T.CameraC)), T.C.c_void_p)
+            if L.tsdf_fuse_frames(h, n, p, c, bflags, sp) != T.OK:
+                raise RuntimeError("fuse_frames failed")
+        if events is not None:
+            events[len(chunks)].record(stream)
 
     # ---- correctness gate and algorithmic-byte accounting (untimed) ----------
     vol.reset()
@@ -137,33 +169,43 @@ def main() -> int:
     log(f"[bench] gate ok: {st.points_valid} points, {st.pairs} pairs, {st.blocks_total} blocks, "
         f"max probe {st.max_probe}, load factor {st.blocks_total / w.table_capacity:.3f}")
 
-    # ---- warmup, then the timed steps ----------------------------------------
-    for _ in range(args.warmup):
-        fuse_all()
-    torch.cuda.synchronize()
-    events = [[torch.cuda.Event(enable_timing=True) for _ in range(len(ptrs) + 1)]
-              for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for s in range(args.steps):
-        fuse_all(events[s])
-    torch.cuda.synchronize()
-    t_end = time.perf_counter()
-    wall = t_end - t_start
-    frame_ms = np.array([[events[s][k].elapsed_time(events[s][k + 1]) for k in range(len(ptrs))]
-                         for s in range(args.steps)])
-    st = vol.stats()
-    if st.status != T.OK or st.pairs_dropped or st.points_valid != points_per_step:
-        print("timed run changed the result", file=sys.stderr)
-        return 1
+    # ---- warmup, then the timed steps: plain path, then the headline path ----
+    def timed(run, n_events):
+        for _ in range(args.warmup):
+            run()
+        torch.cuda.synchronize()
+        events = [[torch.cuda.Event(enable_timing=True) for _ in range(n_events + 1)]
+                  for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for s_ in range(args.steps):
+            run(events[s_])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_start
+        ms = np.array([[events[s_][k].elapsed_time(events[s_][k + 1]) for k in range(n_events)]
+                       for s_ in range(args.steps)])
+        st_ = vol.stats()
+        if st_.status != T.OK or st_.pairs_dropped or st_.points_valid != points_per_step:
+            raise RuntimeError("timed run changed the result")
+        return wall, ms
 
-    value = points_per_step * args.steps / wall
+    wall_p, frame_ms = timed(fuse_all, len(ptrs))
+    wall_b, launch_ms = timed(fuse_batched, len(chunks))
+    plain_value = points_per_step * args.steps / wall_p
+    value = points_per_step * args.steps / wall_b
+    wall = wall_b
+    # algorithmic bytes per launch of the headline path, against its mean launch time
+    launch_bytes = [float(sum(acc_bytes[i0:i0 + n])) for (i0, n) in chunks]
+    full = [j for j, (_, n) in enumerate(chunks) if n == fpl]
+    mean_launch_ms = float(launch_ms[:, full].mean())
+    bytes_per_launch = float(np.mean([launch_bytes[j] for j in full]))
+    achieved = bytes_per_launch / (mean_launch_ms * 1e-3) / 1e9
     mean_frame_ms = float(frame_ms.mean())
-    achieved = float(np.mean(acc_bytes)) / (mean_frame_ms * 1e-3) / 1e9
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         tr = json.load(open(TRAFFIC_FILE))
-        if tr.get("kernel_sha") == kernel_sha() and tr.get("mode") == args.mode:
+        if tr.get("kernel_sha") == kernel_sha() and tr.get("batch") == fpl and \
+                tr.get("per_group") == args.per_group:
             traffic = tr.get("bytes_per_launch")
 
     cpu = None
@@ -207,20 +249,36 @@ def main() -> int:
         "data": "synthetic",
         "config": {
             "workload": f"room orbit, {len(ptrs)} frames of 640x480, voxel 5 mm, truncation 2 cm, "
-                        f"table 2^20 slots, pool 2^18 blocks, plain per-frame path",
-            "path": "plain", "mode": args.mode, "frames_per_step": len(ptrs),
-            "points_per_step": points_per_step, "parallelism": "single GPU",
+                        f"table 2^20 slots, pool 2^18 blocks",
+            "path": f"batched: tsdf_fuse_frames, {fpl} frames per launch, "
+                    f"{args.per_group} frame(s) per workgroup",
+            "frames_per_step": len(ptrs), "points_per_step": points_per_step,
+            "parallelism": "single GPU",
         },
         "p50_frame_ms": float(np.percentile(frame_ms, 50)),
         "p95_frame_ms": float(np.percentile(frame_ms, 95)),
         "p99_frame_ms": float(np.percentile(frame_ms, 99)),
-        "frame_samples": int(frame_ms.size),
+        "frame_latency_path": "plain (one launch per frame)",
+        "plain": {
+            "value": plain_value, "unit": "points/s", "mode": args.mode,
+            "ms_per_step": wall_p / args.steps * 1e3, "mean_frame_ms": mean_frame_ms,
+            "p50_frame_ms": float(np.percentile(frame_ms, 50)),
+            "p99_frame_ms": float(np.percentile(frame_ms, 99)), "frame_samples": int(frame_ms.size),
+        },
+        "batched": {
+            "value": value, "unit": "points/s", "frames_per_launch": fpl,
+            "frames_per_workgroup": args.per_group,
+            "mean_launch_ms": mean_launch_ms,
+            "p50_launch_ms": float(np.percentile(launch_ms[:, full], 50)),
+            "p99_launch_ms": float(np.percentile(launch_ms[:, full], 99)),
+            "ms_per_frame": mean_launch_ms / fpl,
+        },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": "fuse_kernel<4, fused>" if args.mode != "two_pass" else "allocate+integrate",
-            "algorithmic_bytes_per_launch": float(np.mean(acc_bytes)),
-            "mean_launch_ms": mean_frame_ms,
+            "kernel": f"fuse_kernel<4, {args.per_group}, 16, fused>",
+            "algorithmic_bytes_per_launch": bytes_per_launch,
+            "mean_launch_ms": mean_launch_ms,
             "touched_voxels_per_frame": acc["V"] / len(ptrs),
             "touched_blocks_per_frame": acc["Bt"] / len(ptrs),
             "new_blocks_per_frame": acc["Bn"] / len(ptrs),

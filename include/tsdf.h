@@ -165,6 +165,25 @@ tsdf_status tsdf_fuse_frame(tsdf_volume* vol, const float* depth_dev, const tsdf
 tsdf_status tsdf_fuse_frame_ex(tsdf_volume* vol, const float* depth_dev, const tsdf_camera* cam,
                                uint32_t flags, void* hip_stream);
 
+/* Fuse `n_frames` depth frames into the volume, up to 16 frames per launch:
+ * the tiles of all frames of a launch share one grid, so one frame's start-up
+ * overlaps another's pool updates.  With TSDF_FUSE_BATCH(m), m >= 2, each
+ * workgroup also takes the same 16x16 pixel tile of 2 (m = 2, 3) or 4 (m >= 4)
+ * consecutive frames and sums their contributions in LDS before adding them to
+ * the pool, so frames of one trajectory that see the same surface share pool
+ * updates (4 becomes 2 when round(trunc/voxel_size) > 4).  The result is that
+ * of fusing the frames one by one with tsdf_fuse_frame, in any order (keys and
+ * weights identical, TSDF sums up to float summation order).
+ *   depth_devs  host array of n_frames device pointers (height x width float32)
+ *   cams        host array of n_frames cameras (sizes may differ)
+ *   flags       TSDF_FUSE_XCD_REMAP and/or TSDF_FUSE_BATCH(m), m in 0..15
+ * Asynchronous, like tsdf_fuse_frame. */
+#define TSDF_FUSE_BATCH_SHIFT 16
+#define TSDF_FUSE_BATCH_MASK (0xFu << TSDF_FUSE_BATCH_SHIFT)
+#define TSDF_FUSE_BATCH(m) (((uint32_t)(m) & 0xFu) << TSDF_FUSE_BATCH_SHIFT)
+tsdf_status tsdf_fuse_frames(tsdf_volume* vol, uint32_t n_frames, const float* const* depth_devs,
+                             const tsdf_camera* cams, uint32_t flags, void* hip_stream);
+
 /* Wait for `hip_stream`, read the counters and return the most severe sticky
  * condition (INTERNAL > TABLE_FULL > POOL_EXHAUSTED > COORD_RANGE), or TSDF_OK.
  * `out` may be NULL. */

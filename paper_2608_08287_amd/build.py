@@ -9,25 +9,43 @@ Compile flags that the kernels rely on:
   -Xclang -target-feature -Xclang -packed-fp32-ops
                         no packed fp32 math is generated.
 """
+import glob
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libtsdf.so")
-SOURCES = [os.path.join(CSRC, "tsdf_api.cpp"), os.path.join(CSRC, "tsdf_kernels.hip")]
+SOURCES = ([os.path.join(CSRC, "tsdf_api.cpp"), os.path.join(CSRC, "tsdf_kernels.hip")]
+           + sorted(glob.glob(os.path.join(CSRC, "tsdf_fuse_k*.hip"))))
+BUILD_DIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-FLAGS = ["-x", "hip", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+FLAGS = ["-x", "hip", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
          "-ffp-contract=off", "-munsafe-fp-atomics",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", f"-I{os.path.join(ROOT, 'include')}"]
 
 
-def build(verbose: bool = False, extra=()) -> str:
-    cmd = [HIPCC, *FLAGS, *extra, *SOURCES, "-o", OUT + ".tmp"]
+def build(verbose: bool = False, extra=(), jobs: int = 0) -> str:
+    """Compile every translation unit in parallel, then link libtsdf.so."""
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    jobs = jobs or min(16, os.cpu_count() or 4)
+
+    def compile_one(src):
+        obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
+        cmd = [HIPCC, *FLAGS, *extra, "-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        return obj
+
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(compile_one, SOURCES))
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", OUT + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -158,13 +158,9 @@ tsdf_status tsdf_reset_volume(tsdf_volume* vol, void* hip_stream) {
   return st;
 }
 
-tsdf_status tsdf_fuse_frame_ex(tsdf_volume* vol, const float* depth_dev, const tsdf_camera* cam,
-                               uint32_t flags, void* hip_stream) {
-  if (!vol || !valid_camera(cam)) return TSDF_ERR_INVALID_ARGUMENT;
-  if ((flags & ~(TSDF_FUSE_MODE_MASK | TSDF_FUSE_XCD_REMAP)) != 0)
-    return TSDF_ERR_INVALID_ARGUMENT;
-  const uint64_t n_pix = (uint64_t)cam->width * cam->height;
-  if (n_pix > 0 && !depth_dev) return TSDF_ERR_INVALID_ARGUMENT;
+namespace {
+
+tsdf::FrameDev frame_dev(const float* depth_dev, const tsdf_camera* cam) {
   tsdf::FrameDev f;
   f.depth = depth_dev;
   f.width = cam->width;
@@ -177,32 +173,89 @@ tsdf_status tsdf_fuse_frame_ex(tsdf_volume* vol, const float* depth_dev, const t
     for (int c = 0; c < 3; ++c) f.R[3 * r + c] = cam->pose[4 * r + c];
     f.t[r] = cam->pose[4 * r + 3];
   }
-  f.v = vol->params.voxel_size;
-  f.iv = 1.0f / vol->params.voxel_size;
-  f.trunc = vol->params.trunc;
-  f.K = band_half(vol->params);
+  return f;
+}
+
+tsdf::WalkParams walk_params(const tsdf_volume* vol) {
+  tsdf::WalkParams wp;
+  wp.v = vol->params.voxel_size;
+  wp.iv = 1.0f / vol->params.voxel_size;
+  wp.trunc = vol->params.trunc;
+  wp.K = band_half(vol->params);
+  return wp;
+}
+
+}  // namespace
+
+tsdf_status tsdf_fuse_frame_ex(tsdf_volume* vol, const float* depth_dev, const tsdf_camera* cam,
+                               uint32_t flags, void* hip_stream) {
+  if (!vol || !valid_camera(cam)) return TSDF_ERR_INVALID_ARGUMENT;
+  if ((flags & ~(TSDF_FUSE_MODE_MASK | TSDF_FUSE_XCD_REMAP)) != 0)
+    return TSDF_ERR_INVALID_ARGUMENT;
+  const uint64_t n_pix = (uint64_t)cam->width * cam->height;
+  if (n_pix > 0 && !depth_dev) return TSDF_ERR_INVALID_ARGUMENT;
+  const tsdf::FrameDev f = frame_dev(depth_dev, cam);
+  const tsdf::WalkParams wp = walk_params(vol);
   const bool remap = (flags & TSDF_FUSE_XCD_REMAP) != 0;
   hipStream_t s = as_stream(hip_stream);
   hipError_t e = hipSuccess;
   if (n_pix > 0) {
     switch (flags & TSDF_FUSE_MODE_MASK) {
       case TSDF_FUSE_DEFAULT:
-        e = tsdf::launch_fuse(vol->dev, f, tsdf::FuseMode::kFused, remap, s);
+        e = tsdf::launch_fuse(vol->dev, wp, &f, 1, 1, tsdf::FuseMode::kFused, remap, s);
         break;
       case TSDF_FUSE_TWO_PASS:
-        e = tsdf::launch_fuse(vol->dev, f, tsdf::FuseMode::kAllocate, remap, s);
-        if (e == hipSuccess) e = tsdf::launch_fuse(vol->dev, f, tsdf::FuseMode::kIntegrate, remap, s);
+        e = tsdf::launch_fuse(vol->dev, wp, &f, 1, 1, tsdf::FuseMode::kAllocate, remap, s);
+        if (e == hipSuccess)
+          e = tsdf::launch_fuse(vol->dev, wp, &f, 1, 1, tsdf::FuseMode::kIntegrate, remap, s);
         break;
       case TSDF_FUSE_ALLOCATE_ONLY:
-        e = tsdf::launch_fuse(vol->dev, f, tsdf::FuseMode::kAllocate, remap, s);
+        e = tsdf::launch_fuse(vol->dev, wp, &f, 1, 1, tsdf::FuseMode::kAllocate, remap, s);
         break;
       case TSDF_FUSE_INTEGRATE_ONLY:
-        e = tsdf::launch_fuse(vol->dev, f, tsdf::FuseMode::kIntegrate, remap, s);
+        e = tsdf::launch_fuse(vol->dev, wp, &f, 1, 1, tsdf::FuseMode::kIntegrate, remap, s);
         break;
     }
   }
   if (e != hipSuccess) return TSDF_ERR_HIP;
   if ((flags & TSDF_FUSE_MODE_MASK) != TSDF_FUSE_ALLOCATE_ONLY) vol->frames++;
+  return TSDF_OK;
+}
+
+tsdf_status tsdf_fuse_frames(tsdf_volume* vol, uint32_t n_frames, const float* const* depth_devs,
+                             const tsdf_camera* cams, uint32_t flags, void* hip_stream) {
+  if (!vol || (n_frames > 0 && (!depth_devs || !cams))) return TSDF_ERR_INVALID_ARGUMENT;
+  if ((flags & ~(TSDF_FUSE_XCD_REMAP | TSDF_FUSE_BATCH_MASK)) != 0) return TSDF_ERR_INVALID_ARGUMENT;
+  for (uint32_t i = 0; i < n_frames; ++i) {
+    if (!valid_camera(&cams[i])) return TSDF_ERR_INVALID_ARGUMENT;
+    if ((uint64_t)cams[i].width * cams[i].height > 0 && !depth_devs[i])
+      return TSDF_ERR_INVALID_ARGUMENT;
+  }
+  const tsdf::WalkParams wp = walk_params(vol);
+  // frames summed per workgroup: the TSDF_FUSE_BATCH(m) request, rounded down to
+  // 1, 2 or 4 and capped for wide bands
+  const uint32_t asked = (flags & TSDF_FUSE_BATCH_MASK) >> TSDF_FUSE_BATCH_SHIFT;
+  int per_group = asked >= 4 ? 4 : asked >= 2 ? 2 : 1;
+  const int cap = tsdf::max_frames_per_group(wp.K);
+  if (per_group > cap) per_group = cap;
+  const bool remap = (flags & TSDF_FUSE_XCD_REMAP) != 0;
+  hipStream_t s = as_stream(hip_stream);
+  tsdf::FrameDev batch[tsdf::kMaxBatchFrames];
+  uint32_t done = 0;
+  while (done < n_frames) {
+    const uint32_t left = n_frames - done;
+    const int n = left < (uint32_t)tsdf::kMaxBatchFrames ? (int)left : tsdf::kMaxBatchFrames;
+    uint64_t pix = 0;
+    for (int i = 0; i < n; ++i) {
+      batch[i] = frame_dev(depth_devs[done + i], &cams[done + i]);
+      pix += (uint64_t)cams[done + i].width * cams[done + i].height;
+    }
+    if (pix > 0 && tsdf::launch_fuse(vol->dev, wp, batch, n, n > 1 ? per_group : 1,
+                                     tsdf::FuseMode::kFused, remap, s) != hipSuccess)
+      return TSDF_ERR_HIP;
+    done += (uint32_t)n;
+    vol->frames += (uint32_t)n;
+  }
   return TSDF_OK;
 }
 

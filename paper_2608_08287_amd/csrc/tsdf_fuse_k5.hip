@@ -1,0 +1,11 @@
+// The fused kernel for a band of 11 samples (K = 5).
+#include "tsdf_device.h"
+
+namespace tsdf {
+
+hipError_t launch_fuse_band5(VolumeDev vol, const WalkParams& wp, const FrameDev* frames, int n,
+                             int frames_per_group, FuseMode mode, bool remap, hipStream_t s) {
+  return launch_fuse_k<5>(vol, wp, frames, n, frames_per_group, mode, remap, s);
+}
+
+}  // namespace tsdf

@@ -1,0 +1,11 @@
+// The fused kernel for a band of 13 samples (K = 6).
+#include "tsdf_device.h"
+
+namespace tsdf {
+
+hipError_t launch_fuse_band6(VolumeDev vol, const WalkParams& wp, const FrameDev* frames, int n,
+                             int frames_per_group, FuseMode mode, bool remap, hipStream_t s) {
+  return launch_fuse_k<6>(vol, wp, frames, n, frames_per_group, mode, remap, s);
+}
+
+}  // namespace tsdf

@@ -75,16 +75,42 @@ struct FrameDev {
   float cx, cy, ifx, ify;  // 1/fx, 1/fy rounded once to float32
   float R[9];              // camera->world rotation, row-major
   float t[3];
-  float v, iv, trunc;      // voxel edge, 1/v (float32), truncation
-  int K;                   // band half-width in samples
 };
+
+struct WalkParams {
+  float v, iv, trunc;  // voxel edge, 1/v (float32), truncation
+  int K;               // band half-width in samples
+};
+
+// Frames fused by one launch of tsdf_fuse_frames.
+constexpr int kMaxBatchFrames = 16;
 
 enum class FuseMode : int { kFused = 0, kAllocate = 1, kIntegrate = 2 };
 
 hipError_t launch_fill_u32(void* ptr, unsigned value, size_t n_words, hipStream_t s);
 hipError_t launch_reset_used(VolumeDev vol, hipStream_t s);
-hipError_t launch_fuse(VolumeDev vol, const FrameDev& fr, FuseMode mode, bool xcd_remap,
-                       hipStream_t s);
+// Fuse n_frames (1..kMaxBatchFrames) frames in one launch, frames_per_group of
+// them summed per workgroup (1, 2 or 4, at most max_frames_per_group(K)).
+hipError_t launch_fuse(VolumeDev vol, const WalkParams& wp, const FrameDev* frames, int n_frames,
+                       int frames_per_group, FuseMode mode, bool xcd_remap, hipStream_t s);
+int max_frames_per_group(int K);
+// one per band half-width K, each in its own translation unit
+hipError_t launch_fuse_band1(VolumeDev vol, const WalkParams& wp, const FrameDev* frames, int n,
+                             int frames_per_group, FuseMode mode, bool remap, hipStream_t s);
+hipError_t launch_fuse_band2(VolumeDev vol, const WalkParams& wp, const FrameDev* frames, int n,
+                             int frames_per_group, FuseMode mode, bool remap, hipStream_t s);
+hipError_t launch_fuse_band3(VolumeDev vol, const WalkParams& wp, const FrameDev* frames, int n,
+                             int frames_per_group, FuseMode mode, bool remap, hipStream_t s);
+hipError_t launch_fuse_band4(VolumeDev vol, const WalkParams& wp, const FrameDev* frames, int n,
+                             int frames_per_group, FuseMode mode, bool remap, hipStream_t s);
+hipError_t launch_fuse_band5(VolumeDev vol, const WalkParams& wp, const FrameDev* frames, int n,
+                             int frames_per_group, FuseMode mode, bool remap, hipStream_t s);
+hipError_t launch_fuse_band6(VolumeDev vol, const WalkParams& wp, const FrameDev* frames, int n,
+                             int frames_per_group, FuseMode mode, bool remap, hipStream_t s);
+hipError_t launch_fuse_band7(VolumeDev vol, const WalkParams& wp, const FrameDev* frames, int n,
+                             int frames_per_group, FuseMode mode, bool remap, hipStream_t s);
+hipError_t launch_fuse_band8(VolumeDev vol, const WalkParams& wp, const FrameDev* frames, int n,
+                             int frames_per_group, FuseMode mode, bool remap, hipStream_t s);
 hipError_t launch_insert_blocks(VolumeDev vol, const int* coords, unsigned n, hipStream_t s);
 hipError_t launch_extract(VolumeDev vol, unsigned n_blocks, unsigned long long* keys,
                           float* tsdf, float* weight, hipStream_t s);

@@ -1,579 +1,11 @@
-// Device half of libtsdf.so: hash-blocked TSDF fusion kernels for gfx950.
-//
-// One workgroup of 256 lanes (4 wave64) owns a 16x16 pixel tile and runs three
-// phases separated by workgroup barriers:
-//
-//   1. walk   -- each lane walks its pixel's truncation band (2K+1 samples) and
-//                keeps, per sample, the voxel's in-block index and its truncated
-//                signed distance in registers.  The block keys of the tile are
-//                deduplicated into an LDS key set (open addressing, 64-bit LDS
-//                compare-exchange); a lane inserts a key only when it differs
-//                from its previous sample's, and lanes of one wave that race for
-//                a slot are serialised by the LDS itself.
-//   2. resolve -- each distinct key of the tile is resolved once against the
-//                global open-addressed table (Section 2.3's insert protocol):
-//                probe linearly from the home slot, plain first read of the
-//                entry, agent-scope compare-exchange on an empty slot, pool index
-//                from a bump counter (one atomic per wave), publication of the
-//                index with an agent-scope store.  The probe is unbounded up to a
-//                full cyclic scan and written as a converged step loop (every busy
-//                lane takes exactly one step per iteration and "waiting for a
-//                publication" means "look again next iteration"), so a waiter
-//                never spins while a publisher in its own wave is masked off.
-//   3. integrate -- the tile's contributions are first summed in LDS, kAccBlocks
-//                blocks at a time, in a dense accumulator laid out exactly like a
-//                pool block; each pass then flushes it with agent-scope float
-//                atomics, four 8-voxel rows per wave instruction.  Device-scope
-//                float atomics on gfx950 are performed beyond L2 at about 20 G
-//                requests/s, one request per touched 64-byte segment per
-//                instruction whatever its lane count, so the cost is the number of
-//                (tile, row) pairs: a voxel gets one update per tile, not one per
-//                contribution, and the row's TSDF sums and weights share a
-//                segment (see the pool layout in tsdf_internal.h).
-//
-// A workgroup only ever accumulates into blocks whose indices it resolved itself,
-// so one launch needs no grid-wide barrier.  The two-pass structure of Section
-// 2.2 (allocate over all points, then integrate over all points) is the same
-// code with phase 3 switched off, or with phase 2 restricted to lookups.
-//
-// All walk arithmetic is float32 +, -, *, floor and comparisons in a fixed order
-// and this file must be compiled with -ffp-contract=off so that no FMA changes a
-// voxel choice.
+// Device half of libtsdf.so, part 1: the small kernels (table insert of given
+// blocks, fills, reset of used blocks, extraction) and the dispatch of the fused
+// kernel to its per-K translation units.
 
-#include <hip/hip_runtime.h>
-
-#include "../../include/tsdf.h"
-#include "tsdf_internal.h"
+#include "tsdf_device.h"
 
 namespace tsdf {
 namespace {
-
-constexpr int kTileW = 16;
-constexpr int kTileH = 16;
-constexpr int kThreads = kTileW * kTileH;  // 256 = 4 x wave64
-constexpr int kWave = 64;
-constexpr unsigned kSetCap = 1024;          // LDS key-set slots per workgroup
-constexpr unsigned kSetNone = 0x7FFu;       // "no LDS slot" (set full)
-constexpr unsigned kAccBlocks = 8;          // blocks aggregated in LDS per pass
-constexpr int kProbeAhead = 4;              // table slots read per probe step
-constexpr unsigned kAccSlots = kAccBlocks * kBlockFloats;  // sums and counts
-// A publication is one store after the winner's compare-exchange, so a wait is a
-// handful of steps.  A wait this long means the invariant broke: report it as
-// INTERNAL instead of spinning forever.
-constexpr unsigned kMaxWaitSteps = 1u << 20;
-
-// ---------------------------------------------------------------------------
-// Keys and hashing
-// ---------------------------------------------------------------------------
-
-// Section 2.1: three 21-bit axes biased by 2^20, x in the top field.
-__device__ __forceinline__ unsigned long long pack_key(int bx, int by, int bz) {
-  return ((unsigned long long)(unsigned)(bx + (1 << 20)) << 42) |
-         ((unsigned long long)(unsigned)(by + (1 << 20)) << 21) |
-         (unsigned long long)(unsigned)(bz + (1 << 20));
-}
-
-// MurmurHash3 fmix64, then Lemire's multiply-shift range reduction of its high
-// word onto [0, C).  C need not be a power of two.
-__device__ __forceinline__ unsigned home_slot(unsigned long long k, unsigned C) {
-  k ^= k >> 33;
-  k *= 0xff51afd7ed558ccdull;
-  k ^= k >> 33;
-  k *= 0xc4ceb9fe1a85ec53ull;
-  k ^= k >> 33;
-  return __umulhi((unsigned)(k >> 32), C);
-}
-
-// Slot of a key in the LDS set: Fibonacci hashing of the whole key.
-__device__ __forceinline__ unsigned set_home(unsigned long long k) {
-  return (unsigned)((k * 0x9E3779B97F4A7C15ull) >> 54) & (kSetCap - 1);
-}
-
-// ---------------------------------------------------------------------------
-// Wave helpers
-// ---------------------------------------------------------------------------
-
-__device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
-
-__device__ __forceinline__ unsigned rank_in(unsigned long long mask) {
-  return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
-                                   __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
-}
-
-__device__ __forceinline__ unsigned long long readlane64(unsigned long long v, int l) {
-  const unsigned lo = __builtin_amdgcn_readlane((int)(unsigned)v, l);
-  const unsigned hi = __builtin_amdgcn_readlane((int)(unsigned)(v >> 32), l);
-  return ((unsigned long long)hi << 32) | lo;
-}
-
-// Sum over the wave of a small non-negative per-lane count (< 32), by bit slices.
-__device__ __forceinline__ unsigned wave_sum_small(unsigned v) {
-  unsigned s = 0;
-#pragma unroll
-  for (int b = 0; b < 5; ++b) s += (unsigned)__popcll(__ballot((v >> b) & 1u)) << b;
-  return s;
-}
-
-// Sum over the wave of any per-lane count; every lane receives the total.
-__device__ __forceinline__ unsigned wave_sum(unsigned v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += (unsigned)__shfl_xor((int)v, off, kWave);
-  return v;
-}
-
-__device__ __forceinline__ unsigned wave_max(unsigned v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const unsigned o = (unsigned)__shfl_xor((int)v, off, kWave);
-    v = o > v ? o : v;
-  }
-  return v;
-}
-
-// ---------------------------------------------------------------------------
-// Atomics.  Agent scope: workgroups on every XCD see one another's claims.
-// ---------------------------------------------------------------------------
-
-__device__ __forceinline__ unsigned long long cas_key(unsigned long long* p,
-                                                      unsigned long long expected,
-                                                      unsigned long long desired) {
-  __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-  return expected;  // the value seen in memory
-}
-
-__device__ __forceinline__ unsigned add_u32(unsigned* p, unsigned v) {
-  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ void add_u64(unsigned long long* p, unsigned long long v) {
-  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ void add_f32(float* p, float v) {
-  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ void set_flag(DevCounters* c, unsigned f) {
-  __hip_atomic_fetch_or(&c->status_bits, f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// ---------------------------------------------------------------------------
-// Section 2.3: find or insert one key.  Converged step loop over the busy lanes.
-// Returns the pool index, kBlockPoolFull, kBlockTableFull, or (lookup only)
-// kBlockTableFull for a key that is absent.
-// ---------------------------------------------------------------------------
-
-template <bool kInsert>
-__device__ int resolve_key(const VolumeDev& vol, unsigned long long want, bool active,
-                           unsigned& probes_out, bool& missing_out) {
-  const unsigned C = vol.table_capacity;
-  unsigned slot = active ? home_slot(want, C) : 0u;  // the slot at distance `probes`
-  unsigned probes = 0, waits = 0;
-  bool waiting = false, busy = active, missing = false, broken = false;
-  int result = kBlockTableFull;
-  while (busy) {
-    bool won = false;
-    TableEntry* e = vol.table + slot;
-    if (waiting) {
-      // only while waiting is the index read with an atomic (coherent) load
-      const int b = __hip_atomic_load(&e->block, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (b != kBlockPublishing) {
-        result = b;
-        busy = false;
-      } else if (++waits >= kMaxWaitSteps) {
-        broken = true;
-        busy = false;
-      }
-    } else {
-      // Read kProbeAhead consecutive slots with plain, cacheable loads issued
-      // together (one memory latency per step instead of one per slot), then
-      // examine them in probe order.  A stale key costs one more step; a stale
-      // index only enters the wait.
-      unsigned sl[kProbeAhead];
-      TableEntry en[kProbeAhead];
-#pragma unroll
-      for (int i = 0; i < kProbeAhead; ++i) {
-        sl[i] = (i == 0) ? slot : ((sl[i - 1] + 1 == C) ? 0u : sl[i - 1] + 1);
-        en[i] = vol.table[sl[i]];
-      }
-      // the first candidate in probe order (compile-time indices only, so the
-      // read-ahead stays in registers)
-      int at = -1;
-      bool is_key = false;
-      unsigned at_slot = 0;
-      int at_block = 0;
-#pragma unroll
-      for (int i = kProbeAhead - 1; i >= 0; --i) {
-        const bool cand = (probes + (unsigned)i < C) &&
-                          (en[i].key == want || en[i].key == kEmptyKey);
-        if (cand) {
-          at = i;
-          is_key = en[i].key == want;
-          at_slot = sl[i];
-          at_block = en[i].block;
-        }
-      }
-      if (at < 0) {
-        // none of them: move on (a full cyclic scan means the table is full)
-        probes += kProbeAhead;
-        slot = (sl[kProbeAhead - 1] + 1 == C) ? 0u : sl[kProbeAhead - 1] + 1;
-        if (probes >= C) {
-          result = kBlockTableFull;
-          busy = false;
-        }
-      } else {
-        probes += (unsigned)at;
-        slot = at_slot;
-        e = vol.table + slot;
-        if (is_key) {
-          if (at_block != kBlockPublishing) {
-            result = at_block;
-            busy = false;
-          } else {
-            waiting = true;
-          }
-        } else if (kInsert) {
-          const unsigned long long prev = cas_key(&e->key, kEmptyKey, want);
-          if (prev == kEmptyKey) {
-            won = true;
-          } else if (prev == want) {
-            waiting = true;
-          } else {  // another key took the slot: keep probing after it
-            ++probes;
-            slot = (slot + 1 == C) ? 0u : slot + 1;
-            if (probes >= C) {
-              result = kBlockTableFull;
-              busy = false;
-            }
-          }
-        } else {
-          missing = true;  // lookup only: an empty slot ends the chain
-          busy = false;
-        }
-      }
-    }
-    // winners take consecutive pool indices with one atomic per wave
-    const unsigned long long wmask = __ballot(won);
-    if (wmask) {
-      const int leader = __ffsll((long long)wmask) - 1;
-      unsigned base = 0;
-      if ((int)lane_id() == leader) base = add_u32(&vol.ctr->block_count, (unsigned)__popcll(wmask));
-      base = (unsigned)__builtin_amdgcn_readlane((int)base, leader);
-      if (won) {
-        const unsigned idx = base + rank_in(wmask);
-        int pub;
-        if (idx < vol.pool_capacity) {
-          vol.block_keys[idx] = want;  // read only after the launch: no fence needed
-          pub = (int)idx;
-        } else {
-          pub = kBlockPoolFull;
-          add_u32(&vol.ctr->keys_pool_overflow, 1u);
-          set_flag(vol.ctr, TSDF_FLAG_POOL_EXHAUSTED);
-        }
-        __hip_atomic_store(&e->block, pub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        result = pub;
-        busy = false;
-      }
-    }
-  }
-  // a pool index is used as an address only if it lies inside the pool
-  if (active && (broken || result >= (int)vol.pool_capacity || result < kBlockTableFull)) {
-    set_flag(vol.ctr, TSDF_FLAG_INTERNAL);
-    result = kBlockTableFull;
-    missing = true;  // counted as a loss, not as a full table
-  } else if (active && result == kBlockTableFull && !missing) {
-    add_u32(&vol.ctr->table_full_events, 1u);
-    set_flag(vol.ctr, TSDF_FLAG_TABLE_FULL);
-  }
-  probes_out = probes;
-  missing_out = missing;
-  return result;
-}
-
-// ---------------------------------------------------------------------------
-// The band walk of one sample (shared by every phase that needs a voxel).
-// ---------------------------------------------------------------------------
-
-struct Sample {
-  int vx, vy, vz;
-  float val;
-  bool in_range;  // the voxel can be keyed
-  bool keep;      // passes the occlusion test (meaningful when in_range)
-};
-
-__device__ __forceinline__ Sample walk_sample(const FrameDev& f, float d, float a, float b,
-                                              int k_minus_K) {
-  Sample s;
-  const float z = d + (float)k_minus_K * f.v;
-  const float xc = a * z, yc = b * z, zc = z;
-  float w[3];
-#pragma unroll
-  for (int r = 0; r < 3; ++r) {
-    float acc = f.R[3 * r + 0] * xc;
-    acc = acc + f.R[3 * r + 1] * yc;
-    acc = acc + f.R[3 * r + 2] * zc;
-    w[r] = acc + f.t[r];
-  }
-  const float q0 = w[0] * f.iv, q1 = w[1] * f.iv, q2 = w[2] * f.iv;
-  s.in_range = (z > 0.0f) && (__builtin_fabsf(q0) < 8388608.0f) &&
-               (__builtin_fabsf(q1) < 8388608.0f) && (__builtin_fabsf(q2) < 8388608.0f);
-  s.vx = s.in_range ? (int)__builtin_floorf(q0) : 0;
-  s.vy = s.in_range ? (int)__builtin_floorf(q1) : 0;
-  s.vz = s.in_range ? (int)__builtin_floorf(q2) : 0;
-  const float c0 = ((float)s.vx + 0.5f) * f.v;
-  const float c1 = ((float)s.vy + 0.5f) * f.v;
-  const float c2 = ((float)s.vz + 0.5f) * f.v;
-  float zcv = f.R[2] * (c0 - f.t[0]);
-  zcv = zcv + f.R[5] * (c1 - f.t[1]);
-  zcv = zcv + f.R[8] * (c2 - f.t[2]);
-  const float sdf = d - zcv;
-  s.keep = (zcv > 0.0f) && !(sdf < -f.trunc);
-  s.val = sdf < f.trunc ? sdf : f.trunc;
-  return s;
-}
-
-// Per-sample state carried from phase 1 to phase 3 in one register:
-// bit 31 valid pair, bits 9..19 LDS slot (kSetNone when the set overflowed;
-// replaced by the dense block id in phase 3), bits 0..8 in-block voxel index.
-constexpr unsigned kPairValid = 1u << 31;
-
-__device__ __forceinline__ unsigned tile_of_group(unsigned g, unsigned n_tiles, bool remap) {
-  if (!remap) return g;
-  // Workgroups are dealt round-robin to the 8 XCDs.  Give XCD j the j-th
-  // contiguous run of tiles so that neighbouring tiles, which share blocks and
-  // table entries, meet in the same L2.
-  const unsigned q = n_tiles >> 3, r = n_tiles & 7u;
-  const unsigned xcd = g & 7u, local = g >> 3;
-  return xcd * q + (xcd < r ? xcd : r) + local;
-}
-
-template <int K, FuseMode kMode>
-__global__ __launch_bounds__(kThreads) void fuse_kernel(VolumeDev vol, FrameDev f,
-                                                        unsigned tiles_x, unsigned n_tiles,
-                                                        int remap) {
-  constexpr int NS = 2 * K + 1;
-  constexpr bool kInsert = kMode != FuseMode::kIntegrate;
-  constexpr bool kAccumulate = kMode != FuseMode::kAllocate;
-
-  // The key set is dead once phase 2 has read it; its space is reused by the
-  // phase-3 accumulator.
-  union SharedSet {
-    struct {
-      unsigned long long keys[kSetCap];
-      unsigned n;  // distinct keys in the set
-    } set;
-    float acc[kAccSlots];  // kAccBlocks blocks in the pool's own layout
-  };
-  __shared__ SharedSet sh;
-  __shared__ int s_blockd[kSetCap];            // pool index per dense block id
-  __shared__ unsigned short s_dense[kSetCap];  // dense block id per set slot
-  __shared__ unsigned short s_list[kSetCap];   // set slot per dense block id
-  unsigned long long* const s_keys = sh.set.keys;
-  unsigned* const s_n = &sh.set.n;
-
-  const unsigned tid = threadIdx.x;
-  for (unsigned i = tid; i < kSetCap; i += kThreads) s_keys[i] = kEmptyKey;
-  if (tid == 0) *s_n = 0;
-
-  const unsigned tile = tile_of_group(blockIdx.x, n_tiles, remap != 0);
-  const unsigned px = (tile % tiles_x) * kTileW + (tid % kTileW);
-  const unsigned py = (tile / tiles_x) * kTileH + (tid / kTileW);
-  const bool inside = px < f.width && py < f.height;
-  const float d = inside ? f.depth[(size_t)py * f.width + px] : 0.0f;
-  const bool point = inside && __builtin_isfinite(d) && d > 0.0f;
-  const float a = ((float)px - f.cx) * f.ifx;
-  const float b = ((float)py - f.cy) * f.ify;
-  __syncthreads();
-
-  // ---- phase 1: walk, per-point dedupe, per-wave key dedupe into LDS -------
-  unsigned st[NS];
-  float val[NS];
-  int hx[NS], hy[NS], hz[NS];
-  bool hv[NS];
-  unsigned n_pairs = 0, n_oor = 0;
-  unsigned long long prev_key = kEmptyKey;
-  unsigned prev_slot = kSetNone;
-#pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    const Sample smp = walk_sample(f, d, a, b, s - K);
-    const bool z_ok = point && (d + (float)(s - K) * f.v > 0.0f);
-    if (z_ok && !smp.in_range) ++n_oor;
-    const bool ok = point && smp.in_range;
-    // a voxel counts once per point: compare with this point's earlier samples
-    bool dup = false;
-#pragma unroll
-    for (int j = 0; j < s; ++j)
-      dup |= hv[j] && hx[j] == smp.vx && hy[j] == smp.vy && hz[j] == smp.vz;
-    hv[s] = ok;
-    hx[s] = smp.vx;
-    hy[s] = smp.vy;
-    hz[s] = smp.vz;
-    const bool pair = ok && !dup && smp.keep;
-    n_pairs += pair ? 1u : 0u;
-    const unsigned long long key = pack_key(smp.vx >> 3, smp.vy >> 3, smp.vz >> 3);
-    const unsigned loc = (unsigned)((((smp.vz & 7) * 8) + (smp.vy & 7)) * 8 + (smp.vx & 7));
-    val[s] = smp.val;
-    // consecutive samples of a point mostly share a block: reuse its slot
-    const bool need = pair && key != prev_key;
-    unsigned slot = prev_slot;
-    if (need) {
-      // every lane inserts its own key; the LDS serialises lanes of one wave that
-      // aim at the same slot, so exactly one of them claims it and the others
-      // find the key there
-      unsigned h = set_home(key);
-      slot = kSetNone;
-      for (unsigned i = 0; i < kSetCap; ++i) {
-        const unsigned long long old = atomicCAS(&s_keys[h], kEmptyKey, key);
-        if (old == kEmptyKey) {
-          s_list[atomicAdd(s_n, 1u)] = (unsigned short)h;
-          slot = h;
-          break;
-        }
-        if (old == key) {
-          slot = h;
-          break;
-        }
-        h = (h + 1) & (kSetCap - 1);
-      }
-    }
-    if (pair) {
-      prev_key = key;
-      prev_slot = slot;
-    }
-    st[s] = pair ? (kPairValid | (slot << 9) | loc) : 0u;
-  }
-  __syncthreads();
-
-  // ---- phase 2: resolve each distinct key of the tile once ----------------
-  const unsigned n_keys = *s_n;
-  unsigned my_probe_max = 0;
-  unsigned my_missing = 0;
-  for (unsigned base = 0; base < n_keys; base += kThreads) {
-    const unsigned j = base + tid;
-    const bool act = j < n_keys;
-    const unsigned h = act ? s_list[j] : 0u;
-    const unsigned long long key = act ? s_keys[h] : kEmptyKey;
-    unsigned probes = 0;
-    bool missing = false;
-    const int blk = resolve_key<kInsert>(vol, key, act, probes, missing);
-    if (act) {
-      s_blockd[j] = blk;
-      s_dense[h] = (unsigned short)j;
-      my_probe_max = probes > my_probe_max ? probes : my_probe_max;
-      my_missing += missing ? 1u : 0u;
-    }
-  }
-  __syncthreads();
-
-  // ---- phase 3: integrate --------------------------------------------------
-  unsigned n_drop = 0;
-  if (kAccumulate) {
-    // LDS slot -> dense block id; pairs beyond the LDS set go straight to HBM
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      const unsigned w = st[s];
-      if (!(w & kPairValid)) continue;
-      const unsigned slot = (w >> 9) & 0x7FFu;
-      if (slot != kSetNone) {
-        st[s] = kPairValid | ((unsigned)s_dense[slot] << 9) | (w & 511u);
-      } else {
-        // the tile had more distinct blocks than the LDS set holds: resolve
-        // this pair's key directly (same protocol, same result)
-        const Sample smp = walk_sample(f, d, a, b, s - K);
-        unsigned probes = 0;
-        bool missing = false;
-        const int blk = resolve_key<kInsert>(vol, pack_key(smp.vx >> 3, smp.vy >> 3, smp.vz >> 3),
-                                             true, probes, missing);
-        my_missing += missing ? 1u : 0u;
-        if (blk >= 0) {
-          float* bp = vol.voxels + (size_t)blk * kBlockFloats;
-          add_f32(bp + pool_tsdf_index(w & 511u), val[s]);
-          add_f32(bp + pool_weight_index(w & 511u), 1.0f);
-        } else {
-          ++n_drop;
-        }
-        st[s] = 0u;
-      }
-    }
-    for (unsigned i = tid; i < kAccSlots; i += kThreads) sh.acc[i] = 0.0f;
-    __syncthreads();
-    for (unsigned lo = 0; lo < n_keys; lo += kAccBlocks) {
-#pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        const unsigned w = st[s];
-        const unsigned db = ((w >> 9) & 0x7FFu) - lo;
-        if ((w & kPairValid) && db < kAccBlocks) {
-          float* ab = &sh.acc[db * kBlockFloats];
-          __hip_atomic_fetch_add(ab + pool_tsdf_index(w & 511u), val[s], __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_WORKGROUP);
-          __hip_atomic_fetch_add(ab + pool_weight_index(w & 511u), 1.0f, __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_WORKGROUP);
-        }
-      }
-      __syncthreads();
-      // flush: per block, each thread owns floats tid + 256q (q = 0..3) of the
-      // block's 1024; a wave instruction covers 64 consecutive floats = 4 rows,
-      // one 64-byte memory-side atomic request per touched row.  All LDS reads
-      // of a block are issued before any atomic or clearing write, so the
-      // flush pays one LDS latency per block rather than one per float.
-      for (unsigned bb = 0; bb < kAccBlocks && lo + bb < n_keys; ++bb) {
-        const int blk = s_blockd[lo + bb];  // uniform across the workgroup
-        float* ab = &sh.acc[bb * kBlockFloats];
-        float v[4], cn[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const unsigned i = q * kThreads + tid;
-          v[q] = ab[i];
-          cn[q] = ab[(i & ~15u) + 8u + (i & 7u)];  // this voxel's count
-        }
-        if (blk >= 0) {
-          float* bp = vol.voxels + (size_t)blk * kBlockFloats;
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-            if (cn[q] != 0.0f) add_f32(bp + q * kThreads + tid, v[q]);
-        } else if (tid & 8u) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q) n_drop += (unsigned)cn[q];
-        }
-        // every lane of a wave has read its rows before any lane clears them
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (cn[q] != 0.0f) ab[q * kThreads + tid] = 0.0f;
-      }
-      __syncthreads();
-    }
-  }
-
-  // ---- counters: one atomic per wave, spread over shards -------------------
-  const unsigned wave = tid / kWave;
-  const bool leader = lane_id() == 0;
-  if (kAccumulate) {
-    const unsigned n_pts = (unsigned)__popcll(__ballot(point));
-    const unsigned pw = wave_sum_small(n_pairs);
-    const unsigned sh = (blockIdx.x * 4u + wave) & (kCounterShards - 1);
-    if (leader && n_pts) add_u64(&vol.ctr->points_valid[sh], n_pts);
-    if (leader && pw) add_u64(&vol.ctr->pairs[sh], pw);
-    if (__ballot(n_drop)) {
-      const unsigned dw = wave_sum(n_drop);
-      if (leader) add_u64(&vol.ctr->pairs_dropped, dw);
-    }
-    if (__ballot(n_oor)) {
-      const unsigned ow = wave_sum_small(n_oor);
-      if (leader) add_u64(&vol.ctr->coord_out_of_range, ow);
-    }
-  }
-  if (__ballot(my_missing)) {
-    const unsigned mw = wave_sum_small(my_missing);
-    if (leader) add_u32(&vol.ctr->lookup_misses, mw);
-  }
-  if (__ballot(my_probe_max)) {
-    const unsigned pm = wave_max(my_probe_max);
-    // a plain read filters almost every update; the atomic keeps the maximum exact
-    if (leader && pm > *(volatile unsigned*)&vol.ctr->max_probe)
-      __hip_atomic_fetch_max(&vol.ctr->max_probe, pm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-}
 
 __global__ __launch_bounds__(256) void insert_blocks_kernel(VolumeDev vol, const int* coords,
                                                             unsigned n) {
@@ -655,31 +87,6 @@ unsigned grid_for(size_t work, unsigned cap) {
   return (unsigned)(g < 1 ? 1 : (g > cap ? cap : g));
 }
 
-template <int K>
-hipError_t launch_fuse_k(VolumeDev vol, const FrameDev& f, FuseMode mode, bool remap,
-                         hipStream_t s) {
-  const unsigned tx = (f.width + kTileW - 1) / kTileW;
-  const unsigned ty = (f.height + kTileH - 1) / kTileH;
-  const unsigned n_tiles = tx * ty;
-  if (n_tiles == 0) return hipSuccess;
-  const dim3 grid(n_tiles), block(kThreads);
-  switch (mode) {
-    case FuseMode::kFused:
-      hipLaunchKernelGGL((fuse_kernel<K, FuseMode::kFused>), grid, block, 0, s, vol, f, tx, n_tiles,
-                         (int)remap);
-      break;
-    case FuseMode::kAllocate:
-      hipLaunchKernelGGL((fuse_kernel<K, FuseMode::kAllocate>), grid, block, 0, s, vol, f, tx,
-                         n_tiles, (int)remap);
-      break;
-    case FuseMode::kIntegrate:
-      hipLaunchKernelGGL((fuse_kernel<K, FuseMode::kIntegrate>), grid, block, 0, s, vol, f, tx,
-                         n_tiles, (int)remap);
-      break;
-  }
-  return hipGetLastError();
-}
-
 }  // namespace
 
 hipError_t launch_fill_u32(void* ptr, unsigned value, size_t n_words, hipStream_t s) {
@@ -696,17 +103,21 @@ hipError_t launch_reset_used(VolumeDev vol, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_fuse(VolumeDev vol, const FrameDev& f, FuseMode mode, bool remap,
-                       hipStream_t s) {
-  switch (f.K) {
-    case 1: return launch_fuse_k<1>(vol, f, mode, remap, s);
-    case 2: return launch_fuse_k<2>(vol, f, mode, remap, s);
-    case 3: return launch_fuse_k<3>(vol, f, mode, remap, s);
-    case 4: return launch_fuse_k<4>(vol, f, mode, remap, s);
-    case 5: return launch_fuse_k<5>(vol, f, mode, remap, s);
-    case 6: return launch_fuse_k<6>(vol, f, mode, remap, s);
-    case 7: return launch_fuse_k<7>(vol, f, mode, remap, s);
-    case 8: return launch_fuse_k<8>(vol, f, mode, remap, s);
+int max_frames_per_group(int K) {
+  return K >= 1 && K <= TSDF_MAX_BAND_HALF ? max_frames_for(K) : 0;
+}
+
+hipError_t launch_fuse(VolumeDev vol, const WalkParams& wp, const FrameDev* frames, int n,
+                       int frames_per_group, FuseMode mode, bool remap, hipStream_t s) {
+  switch (wp.K) {
+    case 1: return launch_fuse_band1(vol, wp, frames, n, frames_per_group, mode, remap, s);
+    case 2: return launch_fuse_band2(vol, wp, frames, n, frames_per_group, mode, remap, s);
+    case 3: return launch_fuse_band3(vol, wp, frames, n, frames_per_group, mode, remap, s);
+    case 4: return launch_fuse_band4(vol, wp, frames, n, frames_per_group, mode, remap, s);
+    case 5: return launch_fuse_band5(vol, wp, frames, n, frames_per_group, mode, remap, s);
+    case 6: return launch_fuse_band6(vol, wp, frames, n, frames_per_group, mode, remap, s);
+    case 7: return launch_fuse_band7(vol, wp, frames, n, frames_per_group, mode, remap, s);
+    case 8: return launch_fuse_band8(vol, wp, frames, n, frames_per_group, mode, remap, s);
     default: return hipErrorInvalidValue;
   }
 }

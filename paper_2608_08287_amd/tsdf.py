@@ -25,12 +25,18 @@ OK, ERR_INVALID_ARGUMENT, ERR_BUFFER_TOO_SMALL, ERR_POOL_EXHAUSTED, ERR_TABLE_FU
 FLAG_POOL_EXHAUSTED, FLAG_TABLE_FULL, FLAG_COORD_RANGE, FLAG_INTERNAL = 1, 2, 4, 8
 FUSE_DEFAULT, FUSE_TWO_PASS, FUSE_ALLOCATE_ONLY, FUSE_INTEGRATE_ONLY = 0, 1, 2, 3
 FUSE_XCD_REMAP = 0x100
+
+
+def FUSE_BATCH(m: int) -> int:
+    """Flag: at most ``m`` frames per launch in ``fuse_frames`` (1..15)."""
+    return (m & 0xF) << 16
 BLOCK_VOXELS = 512
 EMPTY_KEY = 0xFFFFFFFFFFFFFFFF
 
 EXPORTED_SYMBOLS = (
     "tsdf_volume_bytes", "tsdf_volume_layout", "tsdf_create_volume", "tsdf_destroy_volume",
-    "tsdf_reset_volume", "tsdf_fuse_frame", "tsdf_fuse_frame_ex", "tsdf_query_status",
+    "tsdf_reset_volume", "tsdf_fuse_frame", "tsdf_fuse_frame_ex", "tsdf_fuse_frames",
+    "tsdf_query_status",
     "tsdf_extract_blocks", "tsdf_insert_blocks", "tsdf_status_str",
 )
 
@@ -93,6 +99,8 @@ def lib() -> C.CDLL:
         L.tsdf_fuse_frame.argtypes = [P, P, C.POINTER(CameraC), P]
         L.tsdf_fuse_frame_ex.restype = I
         L.tsdf_fuse_frame_ex.argtypes = [P, P, C.POINTER(CameraC), U32, P]
+        L.tsdf_fuse_frames.restype = I
+        L.tsdf_fuse_frames.argtypes = [P, U32, P, P, U32, P]
         L.tsdf_query_status.restype = I
         L.tsdf_query_status.argtypes = [P, P, C.POINTER(StatsC)]
         L.tsdf_extract_blocks.restype = I
@@ -209,6 +217,23 @@ class Volume:
                                       _stream_ptr(stream))
         if st != OK:
             raise TsdfError(st, "tsdf_fuse_frame")
+
+    def fuse_frames(self, depths: Sequence[torch.Tensor], cams, flags: int = 0, stream=None) -> None:
+        """Enqueue the fusion of several frames with as few launches as possible."""
+        n = len(depths)
+        structs = [c if isinstance(c, CameraC) else camera_struct(c) for c in cams]
+        if len(structs) != n:
+            raise ValueError("one camera per frame")
+        for d, c in zip(depths, structs):
+            if d.dtype != torch.float32 or not d.is_cuda or not d.is_contiguous():
+                raise TypeError("depth must be a contiguous float32 device tensor")
+            if d.numel() != c.width * c.height:
+                raise ValueError("depth size does not match the camera")
+        ptrs = (C.c_void_p * max(n, 1))(*[d.data_ptr() for d in depths])
+        cam_arr = (CameraC * max(n, 1))(*structs)
+        st = lib().tsdf_fuse_frames(self._h, n, ptrs, cam_arr, flags, _stream_ptr(stream))
+        if st != OK:
+            raise TsdfError(st, "tsdf_fuse_frames")
 
     def insert_blocks(self, coords: torch.Tensor, stream=None) -> None:
         """Allocate blocks for (n, 3) int32 device block coordinates."""

@@ -35,14 +35,17 @@ class GpuResult:
 
 def run_gpu(voxel_size, trunc, table_capacity, pool_capacity, depths: Sequence[np.ndarray], cams,
             prefill_blocks=None, flags=T.FUSE_DEFAULT, keep_volume=False,
-            vol: Optional[T.Volume] = None) -> GpuResult:
+            vol: Optional[T.Volume] = None, batched: bool = False) -> GpuResult:
     if vol is None:
         vol = T.Volume(voxel_size, trunc, table_capacity, pool_capacity)
     if prefill_blocks is not None:
         vol.insert_blocks(torch.from_numpy(np.ascontiguousarray(prefill_blocks, dtype=np.int32)).cuda())
     dev = [torch.from_numpy(np.ascontiguousarray(d, dtype=np.float32)).cuda() for d in depths]
-    for d, c in zip(dev, cams):
-        vol.fuse(d, c, flags)
+    if batched:
+        vol.fuse_frames(dev, cams, flags)
+    else:
+        for d, c in zip(dev, cams):
+            vol.fuse(d, c, flags)
     st = vol.stats()
     ex = vol.extract()
     torch.cuda.synchronize()

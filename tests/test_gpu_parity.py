@@ -280,3 +280,56 @@ def test_stress_C_table_full_is_reported(stress_full):
     assert g.stats.blocks_total == pre.size + 50
     _check_subset(g, full1, np.sort(scene_in))
     assert g.stats.table_full_events >= full1.keys.size - 50
+
+
+# ---------------------------------------------------------------------------
+# Several frames per launch (tsdf_fuse_frames)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("cap", [0, 1, 2, 3])
+def test_batched_room_frames(room, cap):
+    w, o = room
+    g = run_workload(w, flags=T.FUSE_BATCH(cap), batched=True, keep_volume=True)
+    assert_parity(g, o)
+    assert g.stats.frames == len(ROOM_FRAMES) and g.stats.status == T.OK
+    assert_table_invariants(g.vol, o.keys, o.keys.size)
+
+
+def test_batched_consecutive_trajectory_frames():
+    w = S.room_trajectory_workload(frames=range(40, 52))
+    o = O.fuse_workload(w)
+    g = run_workload(w, batched=True)
+    assert_parity(g, o)
+
+
+def test_batched_mixed_sizes_and_invalid_frames():
+    rng = np.random.default_rng(7)
+    cams, depths = [], []
+    for i, (W, H) in enumerate([(13, 9), (40, 23), (1, 1), (17, 33), (0, 4), (64, 48)]):
+        pose = np.concatenate([_rot(*rng.uniform(-2, 2, 3)), rng.uniform(-1, 1, (3, 1))], 1)
+        cams.append(S.Camera(W, H, 20.0 + i, 18.0, W / 2, H / 2, pose.astype(np.float32)))
+        d = rng.uniform(0.3, 1.2, (H, W)).astype(np.float32)
+        if d.size:
+            d[rng.random((H, W)) < 0.2] = np.nan
+        depths.append(d)
+    o = O.fuse_frames(0.01, 0.04, 1 << 14, depths, cams)
+    g = run_gpu(0.01, 0.04, 1 << 15, 1 << 14, depths, cams, batched=True, keep_volume=True)
+    assert_parity(g, o)
+    assert_table_invariants(g.vol, o.keys, o.keys.size)
+
+
+def test_batched_wide_band():
+    # K = 6 (13 samples): two frames per launch
+    w = S.room_trajectory_workload(frames=[3, 4, 5])
+    o = O.fuse_frames(0.005, 0.03, 1 << 18, w.depth, w.cameras)
+    g = run_gpu(0.005, 0.03, 1 << 20, 1 << 18, w.depth, w.cameras, batched=True)
+    assert_parity(g, o)
+
+
+def test_batched_stress_prefilled(stress_full):
+    w = S.plane_stress_workload("A", frames=[0, 1, 2, 3])
+    o = O.fuse_workload(w)
+    g = run_workload(w, batched=True, keep_volume=True)
+    assert_parity(g, o)
+    assert g.stats.pairs_dropped == 0
+    assert_table_invariants(g.vol, o.keys, o.keys.size)
