@@ -69,7 +69,7 @@ def main() -> int:
                     help="kernel structure of the plain per-frame path")
     ap.add_argument("--batch", type=int, default=16,
                     help="frames per tsdf_fuse_frames call on the headline path")
-    ap.add_argument("--per-group", type=int, default=1,
+    ap.add_argument("--per-group", type=int, default=2,
                     help="frames summed per workgroup on the headline path (1, 2 or 4)")
     ap.add_argument("--profile-copy-bytes", type=int, default=0,
                     help="after the run, copy this many bytes device-to-device three times "

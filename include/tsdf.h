@@ -167,13 +167,14 @@ tsdf_status tsdf_fuse_frame_ex(tsdf_volume* vol, const float* depth_dev, const t
 
 /* Fuse `n_frames` depth frames into the volume, up to 16 frames per launch:
  * the tiles of all frames of a launch share one grid, so one frame's start-up
- * overlaps another's pool updates.  With TSDF_FUSE_BATCH(m), m >= 2, each
- * workgroup also takes the same 16x16 pixel tile of 2 (m = 2, 3) or 4 (m >= 4)
- * consecutive frames and sums their contributions in LDS before adding them to
- * the pool, so frames of one trajectory that see the same surface share pool
- * updates (4 becomes 2 when round(trunc/voxel_size) > 4).  The result is that
- * of fusing the frames one by one with tsdf_fuse_frame, in any order (keys and
- * weights identical, TSDF sums up to float summation order).
+ * overlaps another's pool updates.  Each workgroup takes the same 16x16 pixel
+ * tile of F consecutive frames and sums their contributions in LDS before
+ * adding them to the pool, so frames of one trajectory that see the same
+ * surface share pool updates.  F is set by TSDF_FUSE_BATCH(m): m = 1 -> 1,
+ * m = 2 or 3 -> 2, m >= 4 -> 4, and m = 0 (the default) -> 2; F is capped at 2
+ * when round(trunc/voxel_size) > 4.  The result is that of fusing the frames
+ * one by one with tsdf_fuse_frame, in any order (keys and weights identical,
+ * TSDF sums up to float summation order).
  *   depth_devs  host array of n_frames device pointers (height x width float32)
  *   cams        host array of n_frames cameras (sizes may differ)
  *   flags       TSDF_FUSE_XCD_REMAP and/or TSDF_FUSE_BATCH(m), m in 0..15

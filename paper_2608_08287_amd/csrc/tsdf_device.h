@@ -369,8 +369,13 @@ __device__ __forceinline__ FrameDev pick_frame(const FrameBatch<NB>& fb, unsigne
 // (frames past the batch are empty).  F > 1 sums the frames' contributions to a
 // tile before they reach the pool; NB > F puts several frames in one grid so
 // one frame's start-up overlaps another's pool updates.
+// Two frames per workgroup would take ~146 VGPRs (3 waves per SIMD); asking
+// for 4 waves per SIMD costs a few spilled dwords and measures faster.
+constexpr int waves_per_eu_for(int F) { return F == 2 ? 4 : 1; }
+
 template <int K, int F, int NB, FuseMode kMode>
-__global__ __launch_bounds__(kThreads) void fuse_kernel(VolumeDev vol, WalkParams wp,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(waves_per_eu_for(F))))
+void fuse_kernel(VolumeDev vol, WalkParams wp,
                                                         FrameBatch<NB> fb, unsigned n_frames,
                                                         unsigned tiles_x, unsigned n_tiles,
                                                         int remap) {
