@@ -333,3 +333,31 @@ def test_batched_stress_prefilled(stress_full):
     assert_parity(g, o)
     assert g.stats.pairs_dropped == 0
     assert_table_invariants(g.vol, o.keys, o.keys.size)
+
+
+# ---------------------------------------------------------------------------
+# The full 300-frame trajectory in the benchmark's launch configuration
+# (properties that hold at any size; the oracle covers sampled frames above)
+# ---------------------------------------------------------------------------
+
+def test_full_trajectory_batched_equals_plain():
+    w = S.room_trajectory_workload(device="cuda")
+    log(f"  generated {len(w.depth)} frames")
+    g_b = run_workload(w, batched=True, keep_volume=True)            # tsdf_fuse_frames
+    g_p = run_workload(w, flags=T.FUSE_DEFAULT, keep_volume=True)    # one launch per frame
+    assert g_b.stats.status == T.OK and g_p.stats.status == T.OK
+    assert g_b.stats.pairs_dropped == 0 and g_b.stats.lookup_misses == 0
+    assert g_b.stats.points_valid == g_p.stats.points_valid == 300 * 640 * 480
+    assert g_b.stats.pairs == g_p.stats.pairs
+    assert np.array_equal(g_b.keys, g_p.keys)
+    assert np.array_equal(g_b.weights, g_p.weights)
+    assert float(np.abs(g_b.means - g_p.means).max()) <= 2e-5
+    # every weight is an observation count: the total is the number of pairs
+    assert int(g_b.weights.sum(dtype=np.float64)) == g_b.stats.pairs
+    # every allocated block received a contribution (same test in both stages)
+    assert np.all(g_b.weights.reshape(len(g_b.keys), -1).max(axis=1) > 0)
+    assert_table_invariants(g_b.vol, g_b.keys, g_b.keys.size)
+    # the frames the oracle also fused (ROOM_FRAMES, in the sampled-frames test) are
+    # a subset: their keys must all be present here
+    o = O.fuse_frames(w.voxel_size, w.trunc, w.pool_capacity, [w.depth[0]], [w.cameras[0]])
+    assert np.all(np.isin(o.keys, g_b.keys))
