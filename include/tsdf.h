@@ -16,11 +16,12 @@
  *  - Every call returns a tsdf_status.  No call aborts, prints or throws.
  *  - Arguments that are invalid are detected on the host; the call then returns
  *    TSDF_ERR_INVALID_ARGUMENT and enqueues nothing.
- *  - Device memory is owned by the caller: the volume arena, depth frames and
- *    extraction outputs are device pointers the caller allocated (with
- *    hipMalloc, or a framework's allocator) and keeps alive while work that uses
- *    them may still run.  The library owns only the small host handle made by
- *    tsdf_create_volume and allocates no device memory at any time.
+ *  - Device memory is owned by the caller: the volume arena, batch workspace,
+ *    depth frames and extraction outputs are device pointers the caller
+ *    allocated (with hipMalloc, or a framework's allocator) and keeps alive
+ *    while work that uses them may still run.  The library allocates no device
+ *    memory at any time; it owns host handles, and a batch also owns a small
+ *    pinned host staging ring, HIP events and HIP graphs (tsdf_batch_create).
  *  - `hip_stream` is a hipStream_t (NULL = the null stream).  All device work is
  *    enqueued on it in call order; only tsdf_query_status and
  *    tsdf_extract_blocks wait on it.  One volume must not be used from two
@@ -209,6 +210,80 @@ tsdf_status tsdf_extract_blocks(tsdf_volume* vol, void* hip_stream, uint32_t max
  * coord_out_of_range and skipped. */
 tsdf_status tsdf_insert_blocks(tsdf_volume* vol, const int32_t* block_coords_dev, uint32_t n,
                                void* hip_stream);
+
+/* ---------------------------------------------------------------------------
+ * Multi-volume batches.  One call fuses one frame into each of many
+ * independent volumes (one frame per item; an item may repeat a volume) with
+ * one persistent launch per band half-width present: a fixed grid of resident
+ * workgroups strides over the 16x16-pixel (or 32x8, 64x4) tiles of every
+ * item's frame, each tile running the same allocate-then-integrate steps as
+ * tsdf_fuse_frame against its own volume.  Each volume ends as if its items
+ * had been fused alone with tsdf_fuse_frame (keys and weights identical, TSDF
+ * sums up to float summation order); each volume's counters and sticky status
+ * are its own.
+ *
+ * The work list lives in a caller-owned device workspace; the kernels read
+ * their item ranges from it, so once the configuration is fixed the launches
+ * are kept as one instantiated HIP graph and replayed every call whatever the
+ * number and sizes of the items.  A batch is bound to the device current at
+ * tsdf_batch_create and is not thread-safe.
+ * ------------------------------------------------------------------------- */
+typedef struct tsdf_batch tsdf_batch;
+
+typedef struct tsdf_fuse_item {
+  tsdf_volume* volume;      /* target volume */
+  const float* depth_dev;   /* height x width float32, as for tsdf_fuse_frame */
+  tsdf_camera camera;
+} tsdf_fuse_item;
+
+/* The work partition of a batch launch. */
+typedef struct tsdf_batch_config {
+  uint32_t tile_width;     /* pixels per tile row: 16, 32 or 64 (tile height =
+                              256 / tile_width; one wave covers 64 / tile_width
+                              rows) */
+  uint32_t acc_blocks;     /* blocks a workgroup accumulates in LDS per pass:
+                              4, 8 or 16 */
+  uint32_t groups_per_cu;  /* workgroups of the persistent grid per compute
+                              unit; 0 = as many as can be resident */
+} tsdf_batch_config;
+
+/* Device workspace bytes for batches of up to `max_items` items (0 if
+ * max_items is 0 or above TSDF_BATCH_MAX_ITEMS). */
+#define TSDF_BATCH_MAX_ITEMS 65536u
+size_t tsdf_batch_workspace_bytes(uint32_t max_items);
+
+/* Make a batch over the caller's device workspace (>= the bytes above,
+ * 256-byte aligned).  The batch starts with the autotuner on: its first calls
+ * of tsdf_batch_fuse cycle through the candidate configurations (every
+ * tile_width x acc_blocks, at full and half residency), time each on the
+ * stream with HIP events, and then keep the fastest per pixel.  Results do not
+ * depend on the configuration. */
+tsdf_status tsdf_batch_create(uint32_t max_items, void* workspace_dev, size_t workspace_bytes,
+                              tsdf_batch** out);
+
+/* Release the host handle, its staging ring, events and graphs (waits for the
+ * batch's outstanding uploads).  The workspace is the caller's. */
+tsdf_status tsdf_batch_destroy(tsdf_batch* batch);
+
+/* Fix the configuration (stops any tuning) or restart the autotuner with
+ * `trials` timed calls per candidate (1..16). */
+tsdf_status tsdf_batch_set_config(tsdf_batch* batch, const tsdf_batch_config* config);
+tsdf_status tsdf_batch_autotune(tsdf_batch* batch, uint32_t trials);
+
+/* The configuration the next call uses; *tuned = 1 once it is fixed.  Reads
+ * the timings of finished tuning calls without waiting for pending ones. */
+tsdf_status tsdf_batch_get_config(tsdf_batch* batch, tsdf_batch_config* config, uint32_t* tuned);
+
+/* Fuse items[i].depth_dev into items[i].volume for i < n_items (n_items <= the
+ * batch's max_items): copies the work list to the workspace (a small
+ * host-to-device copy from the staging ring) and launches, both on
+ * `hip_stream`.  Asynchronous.  Volumes of a call must not be used on another
+ * stream until it has run.
+ *   flags  TSDF_BATCH_NO_GRAPH: launch directly even once the configuration is
+ *          fixed (by default a fixed configuration replays a HIP graph). */
+#define TSDF_BATCH_NO_GRAPH 0x1u
+tsdf_status tsdf_batch_fuse(tsdf_batch* batch, const tsdf_fuse_item* items, uint32_t n_items,
+                            uint32_t flags, void* hip_stream);
 
 /* Static text for a status code. */
 const char* tsdf_status_str(tsdf_status status);

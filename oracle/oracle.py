@@ -80,11 +80,12 @@ class OracleVolume:
         self._h = lib().ora_create(voxel_size, trunc, pool_capacity)
         if not self._h:
             raise ValueError("invalid oracle volume parameters")
+        self._destroy = lib().ora_destroy  # still reachable at interpreter exit
 
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            lib().ora_destroy(h)
+            self._destroy(h)
             self._h = None
 
     def insert_blocks(self, coords: np.ndarray) -> None:

@@ -1,44 +1,23 @@
 // Host half of libtsdf.so: argument checking, arena carving, launches and
-// status read-back for the C ABI declared in include/tsdf.h.
+// status read-back for the volume calls of the C ABI declared in
+// include/tsdf.h (multi-volume batches are in tsdf_batch.cpp).
 //
 // Every entry point validates on the host and returns before enqueuing anything
 // if an argument is wrong.  No entry point allocates device memory; the only
 // host allocation is the volume handle.
 
-#include <hip/hip_runtime.h>
-
-#include <cmath>
-#include <cstdint>
 #include <cstdlib>
-#include <cstring>
-#include <new>
 
-#include "../../include/tsdf.h"
-#include "tsdf_internal.h"
-
-struct tsdf_volume {
-  tsdf_volume_params params;
-  tsdf_layout layout;
-  tsdf::VolumeDev dev;
-  uint32_t frames;
-};
+#include "tsdf_host.h"
 
 namespace {
 
-constexpr uint64_t kAlign = 256;
-
-uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-
-bool finite(float x) { return std::isfinite(x); }
+using namespace tsdf_host;
 
 uint32_t next_pow2_at_least(uint64_t x) {
   uint64_t p = 1;
   while (p < x) p <<= 1;
   return p > 0xFFFFFFFFull ? 0u : (uint32_t)p;
-}
-
-int band_half(const tsdf_volume_params& p) {
-  return (int)std::llround((double)p.trunc / (double)p.voxel_size);
 }
 
 // Fills `out` for valid params; returns false otherwise.
@@ -70,26 +49,12 @@ bool make_layout(const tsdf_volume_params* p, tsdf_layout* out) {
   return true;
 }
 
-hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
-
-tsdf_status hip_status(hipError_t e) { return e == hipSuccess ? TSDF_OK : TSDF_ERR_HIP; }
-
 tsdf_status init_table_and_counters(tsdf_volume* v, hipStream_t s) {
   const tsdf_layout& L = v->layout;
   hipError_t e = tsdf::launch_fill_u32(v->dev.table, 0xFFFFFFFFu,
                                         (size_t)L.table_capacity * (sizeof(tsdf::TableEntry) / 4), s);
   if (e == hipSuccess) e = tsdf::launch_fill_u32(v->dev.ctr, 0u, tsdf::kCountersBytes / 4, s);
   return hip_status(e);
-}
-
-bool valid_camera(const tsdf_camera* c) {
-  if (!c) return false;
-  if ((uint64_t)c->width * (uint64_t)c->height > (1ull << 31)) return false;
-  if (!finite(c->fx) || !finite(c->fy) || !finite(c->cx) || !finite(c->cy)) return false;
-  if (c->fx == 0.0f || c->fy == 0.0f) return false;
-  for (int i = 0; i < 12; ++i)
-    if (!finite(c->pose[i])) return false;
-  return true;
 }
 
 }  // namespace
@@ -157,35 +122,6 @@ tsdf_status tsdf_reset_volume(tsdf_volume* vol, void* hip_stream) {
   if (st == TSDF_OK) vol->frames = 0;
   return st;
 }
-
-namespace {
-
-tsdf::FrameDev frame_dev(const float* depth_dev, const tsdf_camera* cam) {
-  tsdf::FrameDev f;
-  f.depth = depth_dev;
-  f.width = cam->width;
-  f.height = cam->height;
-  f.cx = cam->cx;
-  f.cy = cam->cy;
-  f.ifx = 1.0f / cam->fx;
-  f.ify = 1.0f / cam->fy;
-  for (int r = 0; r < 3; ++r) {
-    for (int c = 0; c < 3; ++c) f.R[3 * r + c] = cam->pose[4 * r + c];
-    f.t[r] = cam->pose[4 * r + 3];
-  }
-  return f;
-}
-
-tsdf::WalkParams walk_params(const tsdf_volume* vol) {
-  tsdf::WalkParams wp;
-  wp.v = vol->params.voxel_size;
-  wp.iv = 1.0f / vol->params.voxel_size;
-  wp.trunc = vol->params.trunc;
-  wp.K = band_half(vol->params);
-  return wp;
-}
-
-}  // namespace
 
 tsdf_status tsdf_fuse_frame_ex(tsdf_volume* vol, const float* depth_dev, const tsdf_camera* cam,
                                uint32_t flags, void* hip_stream) {

@@ -1,0 +1,490 @@
+// Host half of the multi-volume batch calls of include/tsdf.h: work-list
+// staging, the persistent launches, the online autotuner and the graph cache.
+//
+// Per call: the items are sorted by band half-width K (counting sort, stable),
+// each item's tile count is taken for the configuration's tile width, and the
+// work list (K ranges, tile prefix sums, item descriptors) is written into one
+// slot of a pinned host ring and copied to the device workspace on the
+// caller's stream.  Then one persistent kernel per K present runs over the
+// list.  The ring slot is reused only after the event recorded behind its copy
+// has completed, so the host never overwrites a list the copy engine has not
+// read yet; the device workspace has a single copy because every use of it is
+// ordered on the stream behind the copy that filled it.
+
+#include <algorithm>
+#include <cstdlib>
+#include <limits>
+#include <new>
+#include <vector>
+
+#include "tsdf_host.h"
+
+using namespace tsdf_host;
+
+namespace {
+
+constexpr int kRingSlots = 4;
+constexpr int kMaxGraphs = 4;
+constexpr uint64_t kHeaderBytes = 256;  // k_begin[kBatchKSlots], padded
+constexpr int kAccChoices[3] = {4, 8, 16};
+constexpr uint32_t kTileWidths[3] = {16, 32, 64};
+
+struct WorkLayout {
+  uint64_t tile_start, items, total;
+};
+
+WorkLayout work_layout(uint32_t max_items) {
+  WorkLayout L;
+  L.tile_start = kHeaderBytes;
+  L.items = align_up(L.tile_start + 4ull * ((uint64_t)max_items + 1));
+  L.total = align_up(L.items + sizeof(tsdf::BatchItem) * (uint64_t)max_items);
+  return L;
+}
+
+int acc_index(uint32_t ab) { return ab == 4 ? 0 : ab == 8 ? 1 : ab == 16 ? 2 : -1; }
+
+unsigned log2_u32(uint32_t x) {
+  unsigned l = 0;
+  while ((1u << l) < x) ++l;
+  return l;
+}
+
+bool valid_config(const tsdf_batch_config* c) {
+  return c && (c->tile_width == 16 || c->tile_width == 32 || c->tile_width == 64) &&
+         acc_index(c->acc_blocks) >= 0 && c->groups_per_cu <= 64;
+}
+
+struct Timing {
+  int cand;
+  hipEvent_t start, stop;
+  double pixels;
+};
+
+struct GraphEntry {
+  uint32_t k_mask;
+  tsdf_batch_config cfg;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  uint64_t last_use;
+};
+
+}  // namespace
+
+struct tsdf_batch {
+  uint32_t max_items;
+  char* ws;
+  WorkLayout L;
+  int n_cu;
+  int occupancy[TSDF_MAX_BAND_HALF + 1][3];  // resident workgroups per CU; 0 = not yet asked
+  // staging ring
+  char* ring;
+  hipEvent_t ring_done[kRingSlots];
+  bool ring_pending[kRingSlots];
+  int next_slot;
+  // configuration and tuner
+  tsdf_batch_config cfg;
+  bool tuned;
+  uint32_t trials;
+  std::vector<tsdf_batch_config> cands;
+  std::vector<double> best;  // per candidate: least seconds per pixel seen
+  uint32_t issued;           // tuning calls launched
+  std::vector<Timing> pending;
+  std::vector<Timing> spare;  // event pairs ready for reuse
+  // graphs
+  GraphEntry graphs[kMaxGraphs];
+  int n_graphs;
+  uint64_t calls;
+  // per-call scratch
+  std::vector<uint32_t> order;
+};
+
+namespace {
+
+int occupancy(tsdf_batch* b, int K, int ai) {
+  int& o = b->occupancy[K][ai];
+  if (o == 0) {
+    int n = 0;
+    const void* fn = tsdf::multi_kernel(K, kAccChoices[ai]);
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, 256, 0) != hipSuccess || n < 1)
+      n = 1;
+    o = n;
+  }
+  return o;
+}
+
+unsigned grid_for(tsdf_batch* b, int K, const tsdf_batch_config& c) {
+  const int ai = acc_index(c.acc_blocks);
+  int per_cu = occupancy(b, K, ai);
+  if (c.groups_per_cu != 0 && (int)c.groups_per_cu < per_cu) per_cu = (int)c.groups_per_cu;
+  return (unsigned)per_cu * (unsigned)b->n_cu;
+}
+
+void build_candidates(tsdf_batch* b) {
+  b->cands.clear();
+  for (uint32_t tw : kTileWidths) {
+    for (int ai = 0; ai < 3; ++ai) {
+      tsdf_batch_config c{tw, (uint32_t)kAccChoices[ai], 0u};
+      b->cands.push_back(c);
+    }
+  }
+  // half residency for the 16-pixel-wide tiles (K = 4 sets the number)
+  for (int ai = 0; ai < 3; ++ai) {
+    const int full = occupancy(b, 4, ai);
+    if (full >= 2) b->cands.push_back(tsdf_batch_config{16u, (uint32_t)kAccChoices[ai],
+                                                        (uint32_t)(full / 2)});
+  }
+  b->best.assign(b->cands.size(), std::numeric_limits<double>::infinity());
+}
+
+void release_timings(tsdf_batch* b) {
+  for (Timing& t : b->pending) {
+    (void)hipEventSynchronize(t.stop);
+    b->spare.push_back(t);
+  }
+  b->pending.clear();
+}
+
+// Fold in the timings of finished tuning calls; fix the configuration once
+// every candidate has all its trials.
+void poll_tuner(tsdf_batch* b) {
+  if (b->tuned) return;
+  size_t keep = 0;
+  for (size_t i = 0; i < b->pending.size(); ++i) {
+    Timing& t = b->pending[i];
+    if (hipEventQuery(t.stop) == hipSuccess) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, t.start, t.stop) == hipSuccess && t.pixels > 0.0) {
+        const double spp = 1e-3 * (double)ms / t.pixels;
+        if (spp < b->best[t.cand]) b->best[t.cand] = spp;
+      }
+      b->spare.push_back(t);
+    } else {
+      b->pending[keep++] = t;
+    }
+  }
+  b->pending.resize(keep);
+  const uint32_t total = (uint32_t)b->cands.size() * b->trials;
+  if (b->issued >= total && b->pending.empty()) {
+    size_t arg = 0;
+    for (size_t i = 1; i < b->best.size(); ++i)
+      if (b->best[i] < b->best[arg]) arg = i;
+    b->cfg = b->cands[arg];
+    b->tuned = true;
+  }
+}
+
+// The configuration of the next call and, while tuning, its candidate index.
+tsdf_batch_config next_config(tsdf_batch* b, int* cand) {
+  *cand = -1;
+  if (b->tuned) return b->cfg;
+  const uint32_t n = (uint32_t)b->cands.size();
+  if (b->issued < n * b->trials) {
+    *cand = (int)(b->issued % n);
+    return b->cands[*cand];
+  }
+  // every trial launched, some not finished: the best measured so far
+  size_t arg = 0;
+  for (size_t i = 1; i < b->best.size(); ++i)
+    if (b->best[i] < b->best[arg]) arg = i;
+  return std::isfinite(b->best[arg]) ? b->cands[arg] : b->cands[0];
+}
+
+tsdf::BatchWork device_work(const tsdf_batch* b) {
+  tsdf::BatchWork w;
+  w.k_begin = reinterpret_cast<const unsigned*>(b->ws);
+  w.tile_start = reinterpret_cast<const unsigned*>(b->ws + b->L.tile_start);
+  w.items = reinterpret_cast<const tsdf::BatchItem*>(b->ws + b->L.items);
+  return w;
+}
+
+hipError_t launch_direct(tsdf_batch* b, uint32_t k_mask, const tsdf_batch_config& c,
+                         const uint32_t* k_tiles, hipStream_t s) {
+  tsdf::BatchWork w = device_work(b);
+  unsigned tw_log2 = log2_u32(c.tile_width);
+  void* args[] = {&w, &tw_log2};
+  for (int K = 1; K <= TSDF_MAX_BAND_HALF; ++K) {
+    if (!(k_mask & (1u << K))) continue;
+    unsigned grid = grid_for(b, K, c);
+    if (k_tiles[K] < grid) grid = k_tiles[K];
+    const hipError_t e = hipLaunchKernel(tsdf::multi_kernel(K, (int)c.acc_blocks), dim3(grid),
+                                         dim3(256), args, 0, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+void destroy_graph(GraphEntry& g) {
+  (void)hipGraphExecDestroy(g.exec);
+  (void)hipGraphDestroy(g.graph);
+}
+
+// The instantiated graph of one kernel node per K in k_mask for configuration
+// c (no memory nodes: the work list arrives by the copy before the launch).
+hipError_t graph_for(tsdf_batch* b, uint32_t k_mask, const tsdf_batch_config& c, hipStream_t s,
+                     hipGraphExec_t* out) {
+  for (int i = 0; i < b->n_graphs; ++i) {
+    GraphEntry& g = b->graphs[i];
+    if (g.k_mask == k_mask && g.cfg.tile_width == c.tile_width &&
+        g.cfg.acc_blocks == c.acc_blocks && g.cfg.groups_per_cu == c.groups_per_cu) {
+      g.last_use = b->calls;
+      *out = g.exec;
+      return hipSuccess;
+    }
+  }
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipGraphCreate(&graph, 0);
+  if (e != hipSuccess) return e;
+  tsdf::BatchWork w = device_work(b);
+  unsigned tw_log2 = log2_u32(c.tile_width);
+  void* args[] = {&w, &tw_log2};
+  for (int K = 1; K <= TSDF_MAX_BAND_HALF && e == hipSuccess; ++K) {
+    if (!(k_mask & (1u << K))) continue;
+    hipKernelNodeParams p;
+    std::memset(&p, 0, sizeof(p));
+    p.func = const_cast<void*>(tsdf::multi_kernel(K, (int)c.acc_blocks));
+    p.gridDim = dim3(grid_for(b, K, c));
+    p.blockDim = dim3(256);
+    p.sharedMemBytes = 0;
+    p.kernelParams = args;
+    p.extra = nullptr;
+    hipGraphNode_t node;
+    e = hipGraphAddKernelNode(&node, graph, nullptr, 0, &p);
+  }
+  hipGraphExec_t exec = nullptr;
+  if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return e;
+  }
+  int slot = b->n_graphs;
+  if (slot == kMaxGraphs) {
+    // evict the least recently used; its last replay may still be queued
+    slot = 0;
+    for (int i = 1; i < kMaxGraphs; ++i)
+      if (b->graphs[i].last_use < b->graphs[slot].last_use) slot = i;
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      (void)hipGraphExecDestroy(exec);
+      (void)hipGraphDestroy(graph);
+      return e;
+    }
+    destroy_graph(b->graphs[slot]);
+  } else {
+    ++b->n_graphs;
+  }
+  b->graphs[slot] = GraphEntry{k_mask, c, graph, exec, b->calls};
+  *out = exec;
+  return hipSuccess;
+}
+
+void free_batch(tsdf_batch* b) {
+  for (int i = 0; i < kRingSlots; ++i) {
+    if (b->ring_done[i]) {
+      (void)hipEventSynchronize(b->ring_done[i]);
+      (void)hipEventDestroy(b->ring_done[i]);
+    }
+  }
+  release_timings(b);
+  for (Timing& t : b->spare) {
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+  }
+  for (int i = 0; i < b->n_graphs; ++i) destroy_graph(b->graphs[i]);
+  if (b->ring) (void)hipHostFree(b->ring);
+  delete b;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t tsdf_batch_workspace_bytes(uint32_t max_items) {
+  if (max_items == 0 || max_items > TSDF_BATCH_MAX_ITEMS) return 0;
+  return (size_t)work_layout(max_items).total;
+}
+
+tsdf_status tsdf_batch_create(uint32_t max_items, void* workspace_dev, size_t workspace_bytes,
+                              tsdf_batch** out) {
+  if (!out) return TSDF_ERR_INVALID_ARGUMENT;
+  *out = nullptr;
+  if (max_items == 0 || max_items > TSDF_BATCH_MAX_ITEMS) return TSDF_ERR_INVALID_ARGUMENT;
+  if (!workspace_dev || ((uintptr_t)workspace_dev % kAlign) != 0) return TSDF_ERR_INVALID_ARGUMENT;
+  const WorkLayout L = work_layout(max_items);
+  if (workspace_bytes < L.total) return TSDF_ERR_BUFFER_TOO_SMALL;
+  tsdf_batch* b = new (std::nothrow) tsdf_batch();
+  if (!b) return TSDF_ERR_INTERNAL;
+  b->max_items = max_items;
+  b->ws = static_cast<char*>(workspace_dev);
+  b->L = L;
+  std::memset(b->occupancy, 0, sizeof(b->occupancy));
+  b->ring = nullptr;
+  for (int i = 0; i < kRingSlots; ++i) {
+    b->ring_done[i] = nullptr;
+    b->ring_pending[i] = false;
+  }
+  b->next_slot = 0;
+  b->n_graphs = 0;
+  b->calls = 0;
+  b->tuned = false;
+  b->trials = 2;
+  b->issued = 0;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&b->n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->ring), kRingSlots * L.total,
+                                         hipHostMallocDefault);
+  for (int i = 0; i < kRingSlots && e == hipSuccess; ++i)
+    e = hipEventCreateWithFlags(&b->ring_done[i], hipEventDisableTiming);
+  if (e != hipSuccess || b->n_cu < 1) {
+    free_batch(b);
+    return TSDF_ERR_HIP;
+  }
+  b->order.reserve(max_items);
+  build_candidates(b);
+  b->cfg = b->cands[0];
+  *out = b;
+  return TSDF_OK;
+}
+
+tsdf_status tsdf_batch_destroy(tsdf_batch* batch) {
+  if (!batch) return TSDF_ERR_INVALID_ARGUMENT;
+  free_batch(batch);
+  return TSDF_OK;
+}
+
+tsdf_status tsdf_batch_set_config(tsdf_batch* batch, const tsdf_batch_config* config) {
+  if (!batch || !valid_config(config)) return TSDF_ERR_INVALID_ARGUMENT;
+  release_timings(batch);
+  batch->cfg = *config;
+  batch->tuned = true;
+  return TSDF_OK;
+}
+
+tsdf_status tsdf_batch_autotune(tsdf_batch* batch, uint32_t trials) {
+  if (!batch || trials < 1 || trials > 16) return TSDF_ERR_INVALID_ARGUMENT;
+  release_timings(batch);
+  batch->trials = trials;
+  batch->issued = 0;
+  batch->tuned = false;
+  batch->best.assign(batch->cands.size(), std::numeric_limits<double>::infinity());
+  return TSDF_OK;
+}
+
+tsdf_status tsdf_batch_get_config(tsdf_batch* batch, tsdf_batch_config* config, uint32_t* tuned) {
+  if (!batch) return TSDF_ERR_INVALID_ARGUMENT;
+  poll_tuner(batch);
+  int cand = -1;
+  const tsdf_batch_config c = next_config(batch, &cand);
+  if (config) *config = c;
+  if (tuned) *tuned = batch->tuned ? 1u : 0u;
+  return TSDF_OK;
+}
+
+tsdf_status tsdf_batch_fuse(tsdf_batch* b, const tsdf_fuse_item* items, uint32_t n_items,
+                            uint32_t flags, void* hip_stream) {
+  if (!b || (n_items > 0 && !items) || n_items > b->max_items) return TSDF_ERR_INVALID_ARGUMENT;
+  if ((flags & ~TSDF_BATCH_NO_GRAPH) != 0) return TSDF_ERR_INVALID_ARGUMENT;
+  for (uint32_t i = 0; i < n_items; ++i) {
+    const tsdf_fuse_item& it = items[i];
+    if (!it.volume || !valid_camera(&it.camera)) return TSDF_ERR_INVALID_ARGUMENT;
+    if ((uint64_t)it.camera.width * it.camera.height > 0 && !it.depth_dev)
+      return TSDF_ERR_INVALID_ARGUMENT;
+  }
+  if (n_items == 0) return TSDF_OK;
+  hipStream_t s = as_stream(hip_stream);
+  poll_tuner(b);
+  int cand = -1;
+  const tsdf_batch_config c = next_config(b, &cand);
+  const uint32_t tw = c.tile_width, th = 256u / tw;
+
+  // the ring slot: wait until the copy that last read it has run
+  const int slot = b->next_slot;
+  b->next_slot = (slot + 1) % kRingSlots;
+  if (b->ring_pending[slot] && hipEventSynchronize(b->ring_done[slot]) != hipSuccess)
+    return TSDF_ERR_HIP;
+  b->ring_pending[slot] = false;
+  char* host = b->ring + (size_t)slot * b->L.total;
+  unsigned* k_begin = reinterpret_cast<unsigned*>(host);
+  unsigned* tile_start = reinterpret_cast<unsigned*>(host + b->L.tile_start);
+  tsdf::BatchItem* out = reinterpret_cast<tsdf::BatchItem*>(host + b->L.items);
+
+  // counting sort by K
+  uint32_t count[tsdf::kBatchKSlots] = {0};
+  for (uint32_t i = 0; i < n_items; ++i) ++count[band_half(items[i].volume->params)];
+  uint32_t k_mask = 0, acc = 0;
+  for (int K = 0; K < tsdf::kBatchKSlots; ++K) {
+    k_begin[K] = acc;
+    acc += count[K];
+    if (count[K]) k_mask |= 1u << K;
+  }
+  uint32_t cursor[tsdf::kBatchKSlots];
+  for (int K = 0; K < tsdf::kBatchKSlots; ++K) cursor[K] = k_begin[K];
+  b->order.resize(n_items);
+  for (uint32_t i = 0; i < n_items; ++i) b->order[cursor[band_half(items[i].volume->params)]++] = i;
+
+  uint64_t tiles = 0;
+  double pixels = 0.0;
+  uint32_t k_tiles[tsdf::kBatchKSlots] = {0};
+  for (uint32_t j = 0; j < n_items; ++j) {
+    const tsdf_fuse_item& it = items[b->order[j]];
+    tsdf::BatchItem& bi = out[j];
+    std::memset(&bi, 0, sizeof(bi));
+    bi.vol = it.volume->dev;
+    bi.wp = walk_params(it.volume);
+    bi.fr = frame_dev(it.depth_dev, &it.camera);
+    const uint32_t tx = (it.camera.width + tw - 1) / tw;
+    const uint32_t ty = (it.camera.height + th - 1) / th;
+    bi.tiles_x = tx;
+    tile_start[j] = (uint32_t)tiles;
+    tiles += (uint64_t)tx * ty;
+    k_tiles[bi.wp.K] += tx * ty;
+    pixels += (double)it.camera.width * it.camera.height;
+    if (tiles > 0x7FFFFFFFull) return TSDF_ERR_INVALID_ARGUMENT;  // tile indices stay in 31 bits
+  }
+  tile_start[n_items] = (uint32_t)tiles;
+  for (int K = 0; K <= TSDF_MAX_BAND_HALF; ++K)
+    if (k_tiles[K] == 0) k_mask &= ~(1u << K);
+
+  const size_t bytes = (size_t)b->L.items + (size_t)n_items * sizeof(tsdf::BatchItem);
+  if (hipMemcpyAsync(b->ws, host, bytes, hipMemcpyHostToDevice, s) != hipSuccess) return TSDF_ERR_HIP;
+  if (hipEventRecord(b->ring_done[slot], s) != hipSuccess) return TSDF_ERR_HIP;
+  b->ring_pending[slot] = true;
+  ++b->calls;
+
+  if (k_mask != 0) {
+    hipError_t e = hipSuccess;
+    if (cand >= 0) {
+      Timing t;
+      if (!b->spare.empty()) {
+        t = b->spare.back();
+        b->spare.pop_back();
+      } else {
+        e = hipEventCreate(&t.start);
+        if (e == hipSuccess) e = hipEventCreate(&t.stop);
+        if (e != hipSuccess) return TSDF_ERR_HIP;
+      }
+      t.cand = cand;
+      t.pixels = pixels;
+      e = hipEventRecord(t.start, s);
+      if (e == hipSuccess) e = launch_direct(b, k_mask, c, k_tiles, s);
+      if (e == hipSuccess) e = hipEventRecord(t.stop, s);
+      if (e != hipSuccess) {
+        b->spare.push_back(t);
+        return TSDF_ERR_HIP;
+      }
+      b->pending.push_back(t);
+      ++b->issued;
+    } else if (b->tuned && !(flags & TSDF_BATCH_NO_GRAPH)) {
+      hipGraphExec_t exec = nullptr;
+      e = graph_for(b, k_mask, c, s, &exec);
+      if (e == hipSuccess) e = hipGraphLaunch(exec, s);
+    } else {
+      e = launch_direct(b, k_mask, c, k_tiles, s);
+    }
+    if (e != hipSuccess) return TSDF_ERR_HIP;
+  }
+  for (uint32_t i = 0; i < n_items; ++i) items[i].volume->frames++;
+  return TSDF_OK;
+}
+
+}  // extern "C"

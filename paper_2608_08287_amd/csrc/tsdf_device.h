@@ -373,48 +373,50 @@ __device__ __forceinline__ FrameDev pick_frame(const FrameBatch<NB>& fb, unsigne
 // for 4 waves per SIMD costs a few spilled dwords and measures faster.
 constexpr int waves_per_eu_for(int F) { return F == 2 ? 4 : 1; }
 
-template <int K, int F, int NB, FuseMode kMode>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(waves_per_eu_for(F))))
-void fuse_kernel(VolumeDev vol, WalkParams wp,
-                                                        FrameBatch<NB> fb, unsigned n_frames,
-                                                        unsigned tiles_x, unsigned n_tiles,
-                                                        int remap) {
-  constexpr int NS = 2 * K + 1;
-  constexpr bool kInsert = kMode != FuseMode::kIntegrate;
-  constexpr bool kAccumulate = kMode != FuseMode::kAllocate;
-
-  // The key set is dead once phase 2 has read it; its space is reused by the
-  // phase-3 accumulator.
-  union SharedSet {
+// LDS of one tile: the key set (phases 1-2) shares its space with the
+// accumulator of AB blocks (phase 3).
+template <int AB>
+struct TileShared {
+  union {
     struct {
       unsigned long long keys[kSetCap];
       unsigned n;  // distinct keys in the set
     } set;
-    float acc[kAccSlots];  // kAccBlocks blocks in the pool's own layout
-  };
-  __shared__ SharedSet sh;
-  __shared__ int s_blockd[kSetCap];            // pool index per dense block id
-  __shared__ unsigned short s_dense[kSetCap];  // dense block id per set slot
-  __shared__ unsigned short s_list[kSetCap];   // set slot per dense block id
-  unsigned long long* const s_keys = sh.set.keys;
-  unsigned* const s_n = &sh.set.n;
+    float acc[AB * kBlockFloats];
+  } u;
+  int blockd[kSetCap];
+  unsigned short dense[kSetCap];
+  unsigned short list[kSetCap];
+};
+
+// One 16x16 tile of F frames (or of one frame, F = 1): the three phases.  The
+// calling thread takes pixel (px, py) of every frame in frs; frames with width
+// 0 are empty.  Every thread of the workgroup must call it; it begins with a
+// workgroup barrier, so a persistent workgroup may call it tile after tile.
+template <int K, int F, int AB, FuseMode kMode>
+__device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams& wp,
+                                          const FrameDev (&frs)[F], unsigned px, unsigned py,
+                                          unsigned shard, TileShared<AB>& sh) {
+  constexpr int NS = 2 * K + 1;
+  constexpr bool kInsert = kMode != FuseMode::kIntegrate;
+  constexpr bool kAccumulate = kMode != FuseMode::kAllocate;
+
+  unsigned long long* const s_keys = sh.u.set.keys;
+  unsigned* const s_n = &sh.u.set.n;
+  int* const s_blockd = sh.blockd;            // pool index per dense block id
+  unsigned short* const s_dense = sh.dense;   // dense block id per set slot
+  unsigned short* const s_list = sh.list;     // set slot per dense block id
+  float* const s_acc = sh.u.acc;              // AB blocks in the pool's own layout
+  constexpr unsigned kAccSlots = AB * kBlockFloats;
 
   const unsigned tid = threadIdx.x;
+  __syncthreads();  // the previous tile of a persistent workgroup is done with the LDS
   for (unsigned i = tid; i < kSetCap; i += kThreads) s_keys[i] = kEmptyKey;
   if (tid == 0) *s_n = 0;
 
-  // the same pixel of each of the workgroup's frames
-  const unsigned group = blockIdx.x / n_tiles;
-  const unsigned tile = tile_of_group(blockIdx.x % n_tiles, n_tiles, remap != 0);
-  const unsigned px = (tile % tiles_x) * kTileW + (tid % kTileW);
-  const unsigned py = (tile / tiles_x) * kTileH + (tid / kTileW);
-  FrameDev frs[F];
   float d[F];
 #pragma unroll
   for (int fi = 0; fi < F; ++fi) {
-    const unsigned idx = group * F + fi;
-    frs[fi] = pick_frame(fb, idx);
-    if (idx >= n_frames) frs[fi].width = frs[fi].height = 0;  // past the batch: empty
     const FrameDev& fr = frs[fi];
     const bool inside = px < fr.width && py < fr.height;
     d[fi] = inside ? fr.depth[(size_t)py * fr.width + px] : 0.0f;
@@ -557,9 +559,9 @@ void fuse_kernel(VolumeDev vol, WalkParams wp,
         }
       }
     }
-    for (unsigned i = tid; i < kAccSlots; i += kThreads) sh.acc[i] = 0.0f;
+    for (unsigned i = tid; i < kAccSlots; i += kThreads) s_acc[i] = 0.0f;
     __syncthreads();
-    for (unsigned lo = 0; lo < n_keys; lo += kAccBlocks) {
+    for (unsigned lo = 0; lo < n_keys; lo += AB) {
 #pragma unroll
       for (int fi = 0; fi < F; ++fi) {
         const FrameDev& fr = frs[fi];
@@ -569,14 +571,14 @@ void fuse_kernel(VolumeDev vol, WalkParams wp,
         for (int s = 0; s < NS; ++s) {
           const unsigned w = st[fi][s];
           const unsigned db = ((w >> 9) & 0x7FFu) - lo;
-          if ((w & kPairValid) && db < kAccBlocks) {
+          if ((w & kPairValid) && db < AB) {
             // the empty asm makes the depth opaque to the optimiser so the
             // recomputation stays inside this pass instead of being hoisted out
             // of the loop (which would hold every pair's value in registers)
             float dk = d[fi];
             asm volatile("" : "+v"(dk));
             const float v = walk_sample(fr, wp, dk, a, b, s - K).val;
-            float* ab = &sh.acc[db * kBlockFloats];
+            float* ab = &s_acc[db * kBlockFloats];
             __hip_atomic_fetch_add(ab + pool_tsdf_index(w & 511u), v, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
             __hip_atomic_fetch_add(ab + pool_weight_index(w & 511u), 1.0f, __ATOMIC_RELAXED,
@@ -590,9 +592,9 @@ void fuse_kernel(VolumeDev vol, WalkParams wp,
       // one 64-byte memory-side atomic request per touched row.  All LDS reads
       // of a block are issued before any atomic or clearing write, so the
       // flush pays one LDS latency per block rather than one per float.
-      for (unsigned bb = 0; bb < kAccBlocks && lo + bb < n_keys; ++bb) {
+      for (unsigned bb = 0; bb < AB && lo + bb < n_keys; ++bb) {
         const int blk = s_blockd[lo + bb];  // uniform across the workgroup
-        float* ab = &sh.acc[bb * kBlockFloats];
+        float* ab = &s_acc[bb * kBlockFloats];
         float v[4], cn[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -624,7 +626,7 @@ void fuse_kernel(VolumeDev vol, WalkParams wp,
   if (kAccumulate) {
     const unsigned pts_w = wave_sum(n_pts);
     const unsigned pairs_w = wave_sum(n_pairs);
-    const unsigned sh_i = (blockIdx.x * 4u + wave) & (kCounterShards - 1);
+    const unsigned sh_i = (shard * 4u + wave) & (kCounterShards - 1);
     if (leader && pts_w) add_u64(&vol.ctr->points_valid[sh_i], pts_w);
     if (leader && pairs_w) add_u64(&vol.ctr->pairs[sh_i], pairs_w);
     if (__ballot(n_drop)) {
@@ -645,6 +647,83 @@ void fuse_kernel(VolumeDev vol, WalkParams wp,
     // a plain read filters almost every update; the atomic keeps the maximum exact
     if (leader && pm > *(volatile unsigned*)&vol.ctr->max_probe)
       __hip_atomic_fetch_max(&vol.ctr->max_probe, pm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// One workgroup = one 16x16 tile of F consecutive frames of the launch's NB
+// frames: workgroup g covers tile g % n_tiles of frames F * (g / n_tiles) + 0..F-1
+// (frames past the batch are empty).  F > 1 sums the frames' contributions to a
+// tile before they reach the pool; NB > F puts several frames in one grid so
+// one frame's start-up overlaps another's pool updates.
+template <int K, int F, int NB, FuseMode kMode>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(waves_per_eu_for(F))))
+void fuse_kernel(VolumeDev vol, WalkParams wp, FrameBatch<NB> fb, unsigned n_frames,
+                 unsigned tiles_x, unsigned n_tiles, int remap) {
+  __shared__ TileShared<kAccBlocks> sh;
+  const unsigned group = blockIdx.x / n_tiles;
+  const unsigned tile = tile_of_group(blockIdx.x % n_tiles, n_tiles, remap != 0);
+  const unsigned px = (tile % tiles_x) * kTileW + (threadIdx.x % kTileW);
+  const unsigned py = (tile / tiles_x) * kTileH + (threadIdx.x / kTileW);
+  FrameDev frs[F];
+#pragma unroll
+  for (int fi = 0; fi < F; ++fi) {
+    const unsigned idx = group * F + fi;
+    frs[fi] = pick_frame(fb, idx);
+    if (idx >= n_frames) frs[fi].width = frs[fi].height = 0;  // past the batch: empty
+  }
+  fuse_tile<K, F, kAccBlocks, kMode>(vol, wp, frs, px, py, blockIdx.x, sh);
+}
+
+// Many volumes, one frame each, in one persistent launch.  The grid is a
+// fixed number of resident workgroups; workgroup g takes global tiles
+// first + g, first + g + gridDim.x, ... of the items of band K (items sorted by
+// K, tiles numbered by the prefix sum in the work list), finds each tile's item
+// by bisection and runs the same tile steps as the one-volume kernel against
+// that item's volume.  Tiles are tw = 2^tw_log2 pixels wide and 256 / tw tall.
+// Every value the loop reads is uniform across the workgroup, so the item
+// descriptors come in through scalar loads.
+// The work list is read-only for the whole launch: read it through the
+// constant address space, where uniform loads become scalar loads that may be
+// repeated at will instead of values held in registers.
+template <typename T>
+using ConstPtr = const __attribute__((address_space(4))) T*;
+
+template <int K, int AB>
+__global__ __launch_bounds__(kThreads) void fuse_multi_kernel(BatchWork w, unsigned tw_log2) {
+  __shared__ TileShared<AB> sh;
+  const ConstPtr<unsigned> k_begin = (ConstPtr<unsigned>)w.k_begin;
+  const ConstPtr<unsigned> tile_start = (ConstPtr<unsigned>)w.tile_start;
+  const ConstPtr<BatchItem> items = (ConstPtr<BatchItem>)w.items;
+  const unsigned first = k_begin[K], last = k_begin[K + 1];
+  if (first >= last) return;
+  const unsigned t_end = tile_start[last];
+  const unsigned lx = threadIdx.x & ((1u << tw_log2) - 1u);
+  const unsigned ly = threadIdx.x >> tw_log2;
+  const unsigned th = kThreads >> tw_log2;
+  for (unsigned t = tile_start[first] + blockIdx.x; t < t_end; t += gridDim.x) {
+    // the item i with tile_start[i] <= t < tile_start[i + 1]
+    unsigned lo = first, hi = last;
+    while (hi - lo > 1u) {
+      const unsigned mid = (lo + hi) >> 1;
+      if (tile_start[mid] <= t) lo = mid;
+      else hi = mid;
+    }
+    const BatchItem& it = *(const BatchItem*)&items[lo];
+    const unsigned local = t - tile_start[lo];
+    const unsigned px = ((local % it.tiles_x) << tw_log2) + lx;
+    const unsigned py = (local / it.tiles_x) * th + ly;
+    const FrameDev frs[1] = {it.fr};
+    fuse_tile<K, 1, AB, FuseMode::kFused>(it.vol, it.wp, frs, px, py, blockIdx.x, sh);
+  }
+}
+
+template <int K>
+const void* multi_kernel_k(int acc_blocks) {
+  switch (acc_blocks) {
+    case 4: return reinterpret_cast<const void*>(&fuse_multi_kernel<K, 4>);
+    case 8: return reinterpret_cast<const void*>(&fuse_multi_kernel<K, 8>);
+    case 16: return reinterpret_cast<const void*>(&fuse_multi_kernel<K, 16>);
+    default: return nullptr;
   }
 }
 

@@ -1,4 +1,4 @@
-// The fused kernel for a band of 7 samples (K = 3).
+// The fused kernels (one volume; many volumes) for a band of 7 samples (K = 3).
 #include "tsdf_device.h"
 
 namespace tsdf {
@@ -7,5 +7,7 @@ hipError_t launch_fuse_band3(VolumeDev vol, const WalkParams& wp, const FrameDev
                              int frames_per_group, FuseMode mode, bool remap, hipStream_t s) {
   return launch_fuse_k<3>(vol, wp, frames, n, frames_per_group, mode, remap, s);
 }
+
+const void* multi_kernel_band3(int acc_blocks) { return multi_kernel_k<3>(acc_blocks); }
 
 }  // namespace tsdf

@@ -1,4 +1,4 @@
-// The fused kernel for a band of 9 samples (K = 4).
+// The fused kernels (one volume; many volumes) for a band of 9 samples (K = 4).
 #include "tsdf_device.h"
 
 namespace tsdf {
@@ -7,5 +7,7 @@ hipError_t launch_fuse_band4(VolumeDev vol, const WalkParams& wp, const FrameDev
                              int frames_per_group, FuseMode mode, bool remap, hipStream_t s) {
   return launch_fuse_k<4>(vol, wp, frames, n, frames_per_group, mode, remap, s);
 }
+
+const void* multi_kernel_band4(int acc_blocks) { return multi_kernel_k<4>(acc_blocks); }
 
 }  // namespace tsdf

@@ -87,6 +87,28 @@ constexpr int kMaxBatchFrames = 16;
 
 enum class FuseMode : int { kFused = 0, kAllocate = 1, kIntegrate = 2 };
 
+// One item of a multi-volume batch: a frame and the volume it goes into, as
+// the persistent kernel reads it from the device workspace.
+struct BatchItem {
+  VolumeDev vol;
+  WalkParams wp;
+  FrameDev fr;
+  unsigned tiles_x;  // tiles per row of this frame for the launch's tile width
+  unsigned pad;
+};
+static_assert(sizeof(BatchItem) % 16 == 0, "items stay 16-byte aligned");
+
+// The work list of one batch launch, in the device workspace.  Items are
+// sorted by band half-width K; the items of K are k_begin[K] .. k_begin[K+1]-1
+// and their tiles are the global tile indices tile_start[first] ..
+// tile_start[last]-1 (tile_start is the exclusive prefix sum of tile counts).
+constexpr int kBatchKSlots = 16;  // k_begin entries (K = 0 .. 9 used)
+struct BatchWork {
+  const unsigned* k_begin;
+  const unsigned* tile_start;
+  const BatchItem* items;
+};
+
 hipError_t launch_fill_u32(void* ptr, unsigned value, size_t n_words, hipStream_t s);
 hipError_t launch_reset_used(VolumeDev vol, hipStream_t s);
 // Fuse n_frames (1..kMaxBatchFrames) frames in one launch, frames_per_group of
@@ -111,6 +133,19 @@ hipError_t launch_fuse_band7(VolumeDev vol, const WalkParams& wp, const FrameDev
                              int frames_per_group, FuseMode mode, bool remap, hipStream_t s);
 hipError_t launch_fuse_band8(VolumeDev vol, const WalkParams& wp, const FrameDev* frames, int n,
                              int frames_per_group, FuseMode mode, bool remap, hipStream_t s);
+// The persistent multi-volume kernel for band half-width K accumulating
+// acc_blocks (4, 8 or 16) blocks in LDS per pass, as a host function pointer
+// for hipLaunchKernel / graph kernel nodes; nullptr for other values.  Its
+// arguments are (BatchWork work, unsigned tile_width_log2).
+const void* multi_kernel(int K, int acc_blocks);
+const void* multi_kernel_band1(int acc_blocks);
+const void* multi_kernel_band2(int acc_blocks);
+const void* multi_kernel_band3(int acc_blocks);
+const void* multi_kernel_band4(int acc_blocks);
+const void* multi_kernel_band5(int acc_blocks);
+const void* multi_kernel_band6(int acc_blocks);
+const void* multi_kernel_band7(int acc_blocks);
+const void* multi_kernel_band8(int acc_blocks);
 hipError_t launch_insert_blocks(VolumeDev vol, const int* coords, unsigned n, hipStream_t s);
 hipError_t launch_extract(VolumeDev vol, unsigned n_blocks, unsigned long long* keys,
                           float* tsdf, float* weight, hipStream_t s);

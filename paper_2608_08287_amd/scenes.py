@@ -297,3 +297,77 @@ def plane_stress_workload(sub_case: str = "A", n_frames: int = 100,
         depth.append(render_depth(cam, scene, 0.0005, 2000 + k, device))
     pre = random_block_coords(n_pre, seed=3) if n_pre else None
     return Workload(f"plane_stress_{sub_case}", 0.004, 0.016, C, pool, cams, depth, pre)
+
+
+# ---------------------------------------------------------------------------
+# Many independent volumes, one frame each per tick.
+# ---------------------------------------------------------------------------
+
+FRAME_SIZES = ((160, 120), (320, 240), (640, 480), (1280, 720))
+
+
+@dataclasses.dataclass(frozen=True)
+class VolumeSpec:
+    width: int
+    height: int
+    voxel_size: float
+    trunc: float
+    table_capacity: int
+    pool_capacity: int
+    scene_seed: int
+    orbit_offset: int   # orbit frame of tick 0
+    noise_seed: int     # tick k draws its noise with seed noise_seed + k
+
+
+class MultiVolumeWorkload:
+    """``n_volumes`` independent reconstructions, each fed one frame per tick.
+
+    From ``default_rng(seed)``: per volume a frame size uniform over ``sizes``,
+    a voxel edge uniform over 5..10 mm (whole millimetres) and a table exponent
+    e uniform over ``log2_tables[0]..log2_tables[1]``; then the drawn exponents
+    are dealt to the volumes in the reverse order of their voxel edges (the
+    finest voxels get the largest tables; ties keep volume order), which keeps
+    every marginal uniform while giving each volume room for its surface: a
+    pool that runs out turns every later new key into a probe of a full table.
+    Truncation is 4 voxels, the table 2^e slots, the pool half the table.  Each
+    volume has its own room scene (``room_scene`` with a drawn seed) and its own
+    starting point on the 300-frame orbit; intrinsics scale with the width
+    (``orbit_camera``).  Tick k gives volume i orbit frame ``orbit_offset + k``
+    with noise sigma 0.002 z^2, seed ``noise_seed + k``.
+    """
+
+    def __init__(self, n_volumes: int = 64, seed: int = 3, sizes=FRAME_SIZES,
+                 log2_tables=(16, 20), n_orbit: int = 300):
+        rng = np.random.default_rng(seed)
+        self.n_orbit = n_orbit
+        size_idx = rng.integers(0, len(sizes), size=n_volumes)
+        voxel_mm = rng.integers(5, 11, size=n_volumes)
+        exps = rng.integers(log2_tables[0], log2_tables[1] + 1, size=n_volumes)
+        scene_seeds = rng.integers(1, 1 << 30, size=n_volumes)
+        offsets = rng.integers(0, n_orbit, size=n_volumes)
+        exp_of = np.empty(n_volumes, dtype=np.int64)
+        exp_of[np.argsort(voxel_mm, kind="stable")] = np.sort(exps)[::-1]
+        self.specs: List[VolumeSpec] = []
+        for i in range(n_volumes):
+            w, h = sizes[int(size_idx[i])]
+            v = int(voxel_mm[i]) * 1e-3
+            e = int(exp_of[i])
+            self.specs.append(VolumeSpec(
+                width=w, height=h, voxel_size=v, trunc=4.0 * v, table_capacity=1 << e,
+                pool_capacity=1 << (e - 1), scene_seed=int(scene_seeds[i]),
+                orbit_offset=int(offsets[i]), noise_seed=(i + 1) * 100000))
+        self._scenes = [room_scene(s.scene_seed) for s in self.specs]
+
+    def __len__(self) -> int:
+        return len(self.specs)
+
+    def camera(self, i: int, tick: int) -> Camera:
+        s = self.specs[i]
+        return orbit_camera((s.orbit_offset + tick) % self.n_orbit, self.n_orbit, s.width, s.height)
+
+    def depth(self, i: int, tick: int, device="cpu") -> np.ndarray:
+        return render_depth(self.camera(i, tick), self._scenes[i], lambda z: 0.002 * z * z,
+                            self.specs[i].noise_seed + tick, device)
+
+    def pixels(self) -> int:
+        return sum(s.width * s.height for s in self.specs)

@@ -38,7 +38,11 @@ EXPORTED_SYMBOLS = (
     "tsdf_reset_volume", "tsdf_fuse_frame", "tsdf_fuse_frame_ex", "tsdf_fuse_frames",
     "tsdf_query_status",
     "tsdf_extract_blocks", "tsdf_insert_blocks", "tsdf_status_str",
+    "tsdf_batch_workspace_bytes", "tsdf_batch_create", "tsdf_batch_destroy",
+    "tsdf_batch_set_config", "tsdf_batch_autotune", "tsdf_batch_get_config", "tsdf_batch_fuse",
 )
+BATCH_NO_GRAPH = 0x1
+BATCH_MAX_ITEMS = 65536
 
 
 class VolumeParams(C.Structure):
@@ -65,6 +69,15 @@ class LayoutC(C.Structure):
     _fields_ = [("counters", C.c_uint64), ("table", C.c_uint64), ("block_keys", C.c_uint64),
                 ("voxels", C.c_uint64), ("total_bytes", C.c_uint64),
                 ("table_capacity", C.c_uint32), ("pool_capacity", C.c_uint32)]
+
+
+class FuseItemC(C.Structure):
+    _fields_ = [("volume", C.c_void_p), ("depth_dev", C.c_void_p), ("camera", CameraC)]
+
+
+class BatchConfigC(C.Structure):
+    _fields_ = [("tile_width", C.c_uint32), ("acc_blocks", C.c_uint32),
+                ("groups_per_cu", C.c_uint32)]
 
 
 class TsdfError(RuntimeError):
@@ -109,6 +122,20 @@ def lib() -> C.CDLL:
         L.tsdf_insert_blocks.argtypes = [P, P, U32, P]
         L.tsdf_status_str.restype = C.c_char_p
         L.tsdf_status_str.argtypes = [I]
+        L.tsdf_batch_workspace_bytes.restype = C.c_size_t
+        L.tsdf_batch_workspace_bytes.argtypes = [U32]
+        L.tsdf_batch_create.restype = I
+        L.tsdf_batch_create.argtypes = [U32, P, C.c_size_t, C.POINTER(P)]
+        L.tsdf_batch_destroy.restype = I
+        L.tsdf_batch_destroy.argtypes = [P]
+        L.tsdf_batch_set_config.restype = I
+        L.tsdf_batch_set_config.argtypes = [P, C.POINTER(BatchConfigC)]
+        L.tsdf_batch_autotune.restype = I
+        L.tsdf_batch_autotune.argtypes = [P, U32]
+        L.tsdf_batch_get_config.restype = I
+        L.tsdf_batch_get_config.argtypes = [P, C.POINTER(BatchConfigC), C.POINTER(U32)]
+        L.tsdf_batch_fuse.restype = I
+        L.tsdf_batch_fuse.argtypes = [P, C.POINTER(FuseItemC), U32, U32, P]
         _lib = L
     return _lib
 
@@ -302,3 +329,78 @@ def fuse_frames(vol: Volume, depths: Sequence[torch.Tensor], cams: Sequence, fla
     structs = [c if isinstance(c, CameraC) else camera_struct(c) for c in cams]
     for d, c in zip(depths, structs):
         vol.fuse(d, c, flags, stream)
+
+
+@dataclass(frozen=True)
+class BatchConfig:
+    tile_width: int     # 16, 32 or 64 pixels (tile height 256 / tile_width)
+    acc_blocks: int     # LDS accumulator blocks per pass: 4, 8 or 16
+    groups_per_cu: int  # persistent workgroups per CU, 0 = all that fit
+
+
+class Batch:
+    """Multi-volume batch launcher (``tsdf_batch_*``) with its device workspace."""
+
+    def __init__(self, max_items: int, device: str | torch.device = "cuda"):
+        nbytes = int(lib().tsdf_batch_workspace_bytes(max_items))
+        if nbytes == 0:
+            raise TsdfError(ERR_INVALID_ARGUMENT, "tsdf_batch_workspace_bytes")
+        self.max_items = max_items
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self._h = C.c_void_p()
+        st = lib().tsdf_batch_create(max_items, C.c_void_p(self.workspace.data_ptr()), nbytes,
+                                     C.byref(self._h))
+        if st != OK:
+            raise TsdfError(st, "tsdf_batch_create")
+        self._items = (FuseItemC * max_items)()
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) and self._h.value:
+            lib().tsdf_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_config(self, cfg: BatchConfig) -> None:
+        c = BatchConfigC(cfg.tile_width, cfg.acc_blocks, cfg.groups_per_cu)
+        st = lib().tsdf_batch_set_config(self._h, C.byref(c))
+        if st != OK:
+            raise TsdfError(st, "tsdf_batch_set_config")
+
+    def autotune(self, trials: int = 2) -> None:
+        st = lib().tsdf_batch_autotune(self._h, trials)
+        if st != OK:
+            raise TsdfError(st, "tsdf_batch_autotune")
+
+    def config(self) -> tuple[BatchConfig, bool]:
+        c, tuned = BatchConfigC(), C.c_uint32(0)
+        st = lib().tsdf_batch_get_config(self._h, C.byref(c), C.byref(tuned))
+        if st != OK:
+            raise TsdfError(st, "tsdf_batch_get_config")
+        return BatchConfig(c.tile_width, c.acc_blocks, c.groups_per_cu), bool(tuned.value)
+
+    def fuse(self, volumes: Sequence[Volume], depths: Sequence[torch.Tensor], cams,
+             flags: int = 0, stream=None) -> None:
+        """Enqueue one frame into each listed volume (a volume may repeat)."""
+        n = len(volumes)
+        if len(depths) != n or len(cams) != n:
+            raise ValueError("one depth frame and one camera per item")
+        if n > self.max_items:
+            raise ValueError("more items than the batch was made for")
+        for i, (v, d, cam) in enumerate(zip(volumes, depths, cams)):
+            c = cam if isinstance(cam, CameraC) else camera_struct(cam)
+            if d.dtype != torch.float32 or not d.is_cuda or not d.is_contiguous():
+                raise TypeError("depth must be a contiguous float32 device tensor")
+            if d.numel() != c.width * c.height:
+                raise ValueError("depth size does not match the camera")
+            it = self._items[i]
+            it.volume = v.handle.value
+            it.depth_dev = d.data_ptr()
+            it.camera = c
+        st = lib().tsdf_batch_fuse(self._h, self._items, n, flags, _stream_ptr(stream))
+        if st != OK:
+            raise TsdfError(st, "tsdf_batch_fuse")

@@ -46,6 +46,11 @@ def run_gpu(voxel_size, trunc, table_capacity, pool_capacity, depths: Sequence[n
     else:
         for d, c in zip(dev, cams):
             vol.fuse(d, c, flags)
+    return result_of(vol, keep_volume)
+
+
+def result_of(vol: T.Volume, keep_volume=False) -> GpuResult:
+    """Stats and extracted blocks of a volume, blocks sorted by key, on the host."""
     st = vol.stats()
     ex = vol.extract()
     torch.cuda.synchronize()
@@ -55,6 +60,53 @@ def run_gpu(voxel_size, trunc, table_capacity, pool_capacity, depths: Sequence[n
     if keep_volume:
         res.vol = vol
     return res
+
+
+STAT_FIELDS = ("points_valid", "pairs", "pairs_dropped", "coord_out_of_range", "blocks_total",
+               "keys_pool_overflow", "lookup_misses", "status_bits", "frames")
+
+
+def assert_conserved(v: T.Volume, st: T.Stats) -> None:
+    """Every pair that passed the walk is either in a weight or counted as
+    dropped, and the pool is full whenever pairs were dropped."""
+    ex = v.extract()
+    assert ex.keys.numel() == st.blocks_total
+    assert torch.unique(ex.keys).numel() == ex.keys.numel(), "a key owns two blocks"
+    assert int(ex.weight.double().sum().item()) + st.pairs_dropped == st.pairs
+    if st.pairs_dropped:
+        assert st.blocks_total == v.layout.pool_capacity
+        assert st.status_bits & T.FLAG_POOL_EXHAUSTED
+
+
+def assert_same_volume(a: T.Volume, b: T.Volume, atol=TSDF_ATOL) -> T.Stats:
+    """Two GPU volumes hold the same fusion result: block keys and weights
+    identical, TSDF means within atol, counters equal.  Compared on the device
+    (packed keys use 63 bits, so int64 order is key order).
+
+    Once a pool runs out, which keys got its last blocks depends on the order
+    in which workgroups reached them, so for volumes that dropped pairs only
+    the order-free facts are compared (points, pairs, a full pool, status) and
+    each volume must conserve its pairs."""
+    sa, sb = a.stats(), b.stats()
+    if sa.pairs_dropped or sb.pairs_dropped:
+        for f in ("points_valid", "pairs", "coord_out_of_range", "blocks_total", "status_bits",
+                  "frames"):
+            assert getattr(sa, f) == getattr(sb, f), (f, getattr(sa, f), getattr(sb, f))
+        assert_conserved(a, sa)
+        assert_conserved(b, sb)
+        return sa
+    for f in STAT_FIELDS:
+        assert getattr(sa, f) == getattr(sb, f), (f, getattr(sa, f), getattr(sb, f))
+    ea, eb = a.extract(), b.extract()
+    assert ea.keys.numel() == eb.keys.numel()
+    ka, ia = torch.sort(ea.keys)
+    kb, ib = torch.sort(eb.keys)
+    assert torch.equal(ka, kb), "block key sets differ"
+    assert torch.equal(ea.weight[ia], eb.weight[ib]), "weights differ"
+    if ka.numel():
+        err = (ea.tsdf[ia].double() - eb.tsdf[ib].double()).abs().max().item()
+        assert err <= atol, err
+    return sa
 
 
 def run_workload(w, flags=T.FUSE_DEFAULT, keep_volume=False, **kw) -> GpuResult:

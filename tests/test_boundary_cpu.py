@@ -95,3 +95,37 @@ def test_status_strings():
     for s in range(8):
         assert T.status_str(s) and T.status_str(s) != "unknown status"
     assert T.status_str(99) == "unknown status"
+
+
+def test_batch_workspace_bytes():
+    L = T.lib()
+    assert L.tsdf_batch_workspace_bytes(0) == 0
+    assert L.tsdf_batch_workspace_bytes(T.BATCH_MAX_ITEMS + 1) == 0
+    prev = 0
+    for n in (1, 2, 64, 1000, T.BATCH_MAX_ITEMS):
+        b = L.tsdf_batch_workspace_bytes(n)
+        assert b % 256 == 0 and b > prev
+        # k ranges + tile prefix sums + one 144-byte descriptor per item
+        assert b >= 256 + 4 * (n + 1) + 144 * n
+        prev = b
+
+
+def test_batch_rejects_bad_arguments_before_any_device_work():
+    L = T.lib()
+    h = C.c_void_p()
+    need = L.tsdf_batch_workspace_bytes(8)
+    assert L.tsdf_batch_create(8, C.c_void_p(4096), need, None) == T.ERR_INVALID_ARGUMENT
+    assert L.tsdf_batch_create(0, C.c_void_p(4096), need, C.byref(h)) == T.ERR_INVALID_ARGUMENT
+    assert L.tsdf_batch_create(T.BATCH_MAX_ITEMS + 1, C.c_void_p(4096), 1 << 40,
+                               C.byref(h)) == T.ERR_INVALID_ARGUMENT
+    assert L.tsdf_batch_create(8, None, need, C.byref(h)) == T.ERR_INVALID_ARGUMENT
+    assert L.tsdf_batch_create(8, C.c_void_p(4096 + 16), need, C.byref(h)) == T.ERR_INVALID_ARGUMENT
+    assert L.tsdf_batch_create(8, C.c_void_p(4096), need - 1, C.byref(h)) == T.ERR_BUFFER_TOO_SMALL
+    assert not h.value
+    cfg = T.BatchConfigC(16, 8, 0)
+    tuned = C.c_uint32()
+    assert L.tsdf_batch_destroy(None) == T.ERR_INVALID_ARGUMENT
+    assert L.tsdf_batch_set_config(None, C.byref(cfg)) == T.ERR_INVALID_ARGUMENT
+    assert L.tsdf_batch_autotune(None, 2) == T.ERR_INVALID_ARGUMENT
+    assert L.tsdf_batch_get_config(None, C.byref(cfg), C.byref(tuned)) == T.ERR_INVALID_ARGUMENT
+    assert L.tsdf_batch_fuse(None, None, 0, 0, None) == T.ERR_INVALID_ARGUMENT
