@@ -31,6 +31,7 @@ METRIC = "depth points fused/s + p50/p99 frame latency, batched-served vs plain"
 HBM_PEAK_GBS = 8000.0
 CSRC = os.path.join(ROOT, "paper_2608_08287_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fuse_kernel_room_orbit_640x480_traffic.json")
+MULTI_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fuse_multi_kernel_64_volumes_traffic.json")
 
 
 def log(msg: str) -> None:
@@ -112,9 +113,14 @@ def bench_multi(args) -> int:
     t0 = time.time()
     A = make()
     batch = T.Batch(nv)
-    batch.autotune(args.trials)
+    if args.batch_config:
+        tw, ppt, ab, gpc = (int(x) for x in args.batch_config.split(","))
+        batch.set_config(T.BatchConfig(tw, ppt, ab, gpc))
+    else:
+        batch.autotune(args.trials)
     k = 0
-    tuned = False
+    tuned = batch.config()[1]
+    cfg = batch.config()[0]
     while not tuned:
         d, c = tick(k)
         batch.fuse(A, d, c)
@@ -125,6 +131,9 @@ def bench_multi(args) -> int:
             raise RuntimeError("autotuner did not settle")
     n_tune = k
     log(f"[bench] tuned after {n_tune} ticks ({time.time() - t0:.1f}s): {cfg}")
+    tuning = [{"tile_width": c.tile_width, "pixels_per_thread": c.pixels_per_thread,
+               "acc_blocks": c.acc_blocks, "groups_per_cu": c.groups_per_cu,
+               "ns_per_pixel": t if np.isfinite(t) else None} for c, t in batch.candidates()]
     first = n_tune
     ticks = list(range(first, first + args.warmup + args.steps))
     for kk in ticks:
@@ -239,6 +248,12 @@ def bench_multi(args) -> int:
     bytes_per_tick = float(np.mean(tick_bytes))
     mean_tick_ms = float(np.mean(tick_ms_b))
     achieved = bytes_per_tick / (mean_tick_ms * 1e-3) / 1e9
+    cfg_str = f"{cfg.tile_width},{cfg.pixels_per_thread},{cfg.acc_blocks},{cfg.groups_per_cu}"
+    traffic = None
+    if os.path.exists(MULTI_TRAFFIC_FILE) and nv == 64:
+        tr = json.load(open(MULTI_TRAFFIC_FILE))
+        if tr.get("kernel_sha") == kernel_sha() and tr.get("batch_config") == cfg_str:
+            traffic = tr.get("bytes_per_launch")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -258,6 +273,14 @@ def bench_multi(args) -> int:
                "sample": f"tick 0 of the first {nf} volumes, each fused into its own volume "
                          f"({pts} points, {t_c:.1f} s including depth rendering, one thread)"}
 
+    if args.profile_copy_bytes:
+        src = torch.empty(args.profile_copy_bytes, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -276,9 +299,10 @@ def bench_multi(args) -> int:
                         f"1280x720, {w.pixels()} pixels per tick), voxels 5..10 mm, truncation "
                         f"4 voxels, tables 2^16..2^20 slots, pools half the table",
             "path": "tsdf_batch_fuse: one persistent launch per tick, replayed as a HIP graph",
-            "batch_config": {"tile_width": cfg.tile_width, "acc_blocks": cfg.acc_blocks,
-                             "groups_per_cu": cfg.groups_per_cu},
-            "tuning_ticks": n_tune, "points_per_step": pts_timed / args.steps,
+            "batch_config": {"tile_width": cfg.tile_width,
+                             "pixels_per_thread": cfg.pixels_per_thread,
+                             "acc_blocks": cfg.acc_blocks, "groups_per_cu": cfg.groups_per_cu},
+            "tuning_ticks": n_tune, "tuning": tuning, "points_per_step": pts_timed / args.steps,
             "parallelism": "single GPU",
         },
         "batched": {"value": value, "ms_per_tick": wall_b / args.steps * 1e3,
@@ -288,8 +312,8 @@ def bench_multi(args) -> int:
         "speedup_vs_plain": value / plain_value,
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "kernel": f"fuse_multi_kernel<4, {cfg.acc_blocks}>",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": f"fuse_multi_kernel<4, {cfg.pixels_per_thread}, {cfg.acc_blocks}>",
             "algorithmic_bytes_per_launch": bytes_per_tick, "mean_launch_ms": mean_tick_ms,
             "launch_ms_includes": "the work-list copy before the launch",
             "touched_voxels_per_tick": acc["V"] / args.steps,
@@ -324,7 +348,10 @@ def main() -> int:
                     help="trajectory: one volume, the 300-frame orbit (default); multi: many "
                          "volumes, one frame each per tick, through the batch API")
     ap.add_argument("--volumes", type=int, default=64, help="multi: volumes per tick")
-    ap.add_argument("--trials", type=int, default=1, help="multi: autotuner trials per candidate")
+    ap.add_argument("--trials", type=int, default=2, help="multi: autotuner trials per candidate")
+    ap.add_argument("--batch-config", default="",
+                    help="multi: fixed tile_width,pixels_per_thread,acc_blocks,groups_per_cu "
+                         "instead of tuning")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "

@@ -236,15 +236,17 @@ typedef struct tsdf_fuse_item {
   tsdf_camera camera;
 } tsdf_fuse_item;
 
-/* The work partition of a batch launch. */
+/* The work partition of a batch launch.  A workgroup of 256 threads takes a
+ * tile tile_width pixels wide and pixels_per_thread * 256 / tile_width tall;
+ * each thread takes pixels_per_thread pixels of one column, so a wave covers
+ * 64 * pixels_per_thread points.  The workgroup sums the tile's contributions
+ * in LDS, acc_blocks voxel blocks per pass, before adding them to the pool. */
 typedef struct tsdf_batch_config {
-  uint32_t tile_width;     /* pixels per tile row: 16, 32 or 64 (tile height =
-                              256 / tile_width; one wave covers 64 / tile_width
-                              rows) */
-  uint32_t acc_blocks;     /* blocks a workgroup accumulates in LDS per pass:
-                              4, 8 or 16 */
-  uint32_t groups_per_cu;  /* workgroups of the persistent grid per compute
-                              unit; 0 = as many as can be resident */
+  uint32_t tile_width;         /* 16, 32 or 64 */
+  uint32_t pixels_per_thread;  /* 1 or 2 */
+  uint32_t acc_blocks;         /* 4, 8 or 16 (8 or 16 with 2 pixels per thread) */
+  uint32_t groups_per_cu;      /* workgroups of the persistent grid per compute
+                                  unit; 0 = as many as can be resident */
 } tsdf_batch_config;
 
 /* Device workspace bytes for batches of up to `max_items` items (0 if
@@ -254,10 +256,10 @@ size_t tsdf_batch_workspace_bytes(uint32_t max_items);
 
 /* Make a batch over the caller's device workspace (>= the bytes above,
  * 256-byte aligned).  The batch starts with the autotuner on: its first calls
- * of tsdf_batch_fuse cycle through the candidate configurations (every
- * tile_width x acc_blocks, at full and half residency), time each on the
- * stream with HIP events, and then keep the fastest per pixel.  Results do not
- * depend on the configuration. */
+ * of tsdf_batch_fuse cycle through the candidate configurations (tile widths,
+ * pixels per thread and LDS blocks per pass at full residency, and a few at
+ * half residency), time each on the stream with HIP events, and then keep the
+ * fastest per pixel.  Results do not depend on the configuration. */
 tsdf_status tsdf_batch_create(uint32_t max_items, void* workspace_dev, size_t workspace_bytes,
                               tsdf_batch** out);
 
@@ -273,6 +275,13 @@ tsdf_status tsdf_batch_autotune(tsdf_batch* batch, uint32_t trials);
 /* The configuration the next call uses; *tuned = 1 once it is fixed.  Reads
  * the timings of finished tuning calls without waiting for pending ones. */
 tsdf_status tsdf_batch_get_config(tsdf_batch* batch, tsdf_batch_config* config, uint32_t* tuned);
+
+/* The autotuner's candidates and the least time per pixel it has measured
+ * for each (nanoseconds; infinity if not yet measured).  Up to `max` entries
+ * are written; *n_out receives the number of candidates.  Either output array
+ * may be NULL. */
+tsdf_status tsdf_batch_candidates(tsdf_batch* batch, uint32_t max, tsdf_batch_config* configs,
+                                  double* ns_per_pixel, uint32_t* n_out);
 
 /* Fuse items[i].depth_dev into items[i].volume for i < n_items (n_items <= the
  * batch's max_items): copies the work list to the workspace (a small

@@ -28,6 +28,7 @@ constexpr int kMaxGraphs = 4;
 constexpr uint64_t kHeaderBytes = 256;  // k_begin[kBatchKSlots], padded
 constexpr int kAccChoices[3] = {4, 8, 16};
 constexpr uint32_t kTileWidths[3] = {16, 32, 64};
+constexpr int kMaxPixelsPerThread = 2;
 
 struct WorkLayout {
   uint64_t tile_start, items, total;
@@ -50,8 +51,15 @@ unsigned log2_u32(uint32_t x) {
 }
 
 bool valid_config(const tsdf_batch_config* c) {
-  return c && (c->tile_width == 16 || c->tile_width == 32 || c->tile_width == 64) &&
-         acc_index(c->acc_blocks) >= 0 && c->groups_per_cu <= 64;
+  if (!c || !(c->tile_width == 16 || c->tile_width == 32 || c->tile_width == 64)) return false;
+  if (c->pixels_per_thread < 1 || c->pixels_per_thread > (uint32_t)kMaxPixelsPerThread) return false;
+  if (acc_index(c->acc_blocks) < 0 || c->groups_per_cu > 64) return false;
+  return tsdf::multi_kernel(1, (int)c->pixels_per_thread, (int)c->acc_blocks) != nullptr;
+}
+
+bool same_config(const tsdf_batch_config& a, const tsdf_batch_config& b) {
+  return a.tile_width == b.tile_width && a.pixels_per_thread == b.pixels_per_thread &&
+         a.acc_blocks == b.acc_blocks && a.groups_per_cu == b.groups_per_cu;
 }
 
 struct Timing {
@@ -75,7 +83,8 @@ struct tsdf_batch {
   char* ws;
   WorkLayout L;
   int n_cu;
-  int occupancy[TSDF_MAX_BAND_HALF + 1][3];  // resident workgroups per CU; 0 = not yet asked
+  // resident workgroups per CU by [K][pixels per thread - 1][acc index]; 0 = not yet asked
+  int occupancy[TSDF_MAX_BAND_HALF + 1][kMaxPixelsPerThread][3];
   // staging ring
   char* ring;
   hipEvent_t ring_done[kRingSlots];
@@ -100,11 +109,11 @@ struct tsdf_batch {
 
 namespace {
 
-int occupancy(tsdf_batch* b, int K, int ai) {
-  int& o = b->occupancy[K][ai];
+int occupancy(tsdf_batch* b, int K, int ppt, int ai) {
+  int& o = b->occupancy[K][ppt - 1][ai];
   if (o == 0) {
     int n = 0;
-    const void* fn = tsdf::multi_kernel(K, kAccChoices[ai]);
+    const void* fn = tsdf::multi_kernel(K, ppt, kAccChoices[ai]);
     if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, 256, 0) != hipSuccess || n < 1)
       n = 1;
     o = n;
@@ -114,24 +123,24 @@ int occupancy(tsdf_batch* b, int K, int ai) {
 
 unsigned grid_for(tsdf_batch* b, int K, const tsdf_batch_config& c) {
   const int ai = acc_index(c.acc_blocks);
-  int per_cu = occupancy(b, K, ai);
+  int per_cu = occupancy(b, K, (int)c.pixels_per_thread, ai);
   if (c.groups_per_cu != 0 && (int)c.groups_per_cu < per_cu) per_cu = (int)c.groups_per_cu;
   return (unsigned)per_cu * (unsigned)b->n_cu;
 }
 
+// Every tile width x pixels per thread x accumulator size at full residency,
+// then the 16-pixel-wide, 8-block shapes at half residency (K = 4 sets the
+// number).
 void build_candidates(tsdf_batch* b) {
   b->cands.clear();
-  for (uint32_t tw : kTileWidths) {
-    for (int ai = 0; ai < 3; ++ai) {
-      tsdf_batch_config c{tw, (uint32_t)kAccChoices[ai], 0u};
-      b->cands.push_back(c);
-    }
-  }
-  // half residency for the 16-pixel-wide tiles (K = 4 sets the number)
-  for (int ai = 0; ai < 3; ++ai) {
-    const int full = occupancy(b, 4, ai);
-    if (full >= 2) b->cands.push_back(tsdf_batch_config{16u, (uint32_t)kAccChoices[ai],
-                                                        (uint32_t)(full / 2)});
+  for (int ppt = 1; ppt <= kMaxPixelsPerThread; ++ppt)
+    for (uint32_t tw : kTileWidths)
+      for (int ab : kAccChoices)
+        if (tsdf::multi_kernel(4, ppt, ab))
+          b->cands.push_back(tsdf_batch_config{tw, (uint32_t)ppt, (uint32_t)ab, 0u});
+  for (int ppt = 1; ppt <= kMaxPixelsPerThread; ++ppt) {
+    const int full = occupancy(b, 4, ppt, acc_index(8));
+    if (full >= 2) b->cands.push_back(tsdf_batch_config{16u, (uint32_t)ppt, 8u, (uint32_t)(full / 2)});
   }
   b->best.assign(b->cands.size(), std::numeric_limits<double>::infinity());
 }
@@ -206,8 +215,9 @@ hipError_t launch_direct(tsdf_batch* b, uint32_t k_mask, const tsdf_batch_config
     if (!(k_mask & (1u << K))) continue;
     unsigned grid = grid_for(b, K, c);
     if (k_tiles[K] < grid) grid = k_tiles[K];
-    const hipError_t e = hipLaunchKernel(tsdf::multi_kernel(K, (int)c.acc_blocks), dim3(grid),
-                                         dim3(256), args, 0, s);
+    const hipError_t e =
+        hipLaunchKernel(tsdf::multi_kernel(K, (int)c.pixels_per_thread, (int)c.acc_blocks),
+                        dim3(grid), dim3(256), args, 0, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -224,8 +234,7 @@ hipError_t graph_for(tsdf_batch* b, uint32_t k_mask, const tsdf_batch_config& c,
                      hipGraphExec_t* out) {
   for (int i = 0; i < b->n_graphs; ++i) {
     GraphEntry& g = b->graphs[i];
-    if (g.k_mask == k_mask && g.cfg.tile_width == c.tile_width &&
-        g.cfg.acc_blocks == c.acc_blocks && g.cfg.groups_per_cu == c.groups_per_cu) {
+    if (g.k_mask == k_mask && same_config(g.cfg, c)) {
       g.last_use = b->calls;
       *out = g.exec;
       return hipSuccess;
@@ -241,7 +250,7 @@ hipError_t graph_for(tsdf_batch* b, uint32_t k_mask, const tsdf_batch_config& c,
     if (!(k_mask & (1u << K))) continue;
     hipKernelNodeParams p;
     std::memset(&p, 0, sizeof(p));
-    p.func = const_cast<void*>(tsdf::multi_kernel(K, (int)c.acc_blocks));
+    p.func = const_cast<void*>(tsdf::multi_kernel(K, (int)c.pixels_per_thread, (int)c.acc_blocks));
     p.gridDim = dim3(grid_for(b, K, c));
     p.blockDim = dim3(256);
     p.sharedMemBytes = 0;
@@ -380,6 +389,19 @@ tsdf_status tsdf_batch_get_config(tsdf_batch* batch, tsdf_batch_config* config, 
   return TSDF_OK;
 }
 
+tsdf_status tsdf_batch_candidates(tsdf_batch* batch, uint32_t max, tsdf_batch_config* configs,
+                                  double* ns_per_pixel, uint32_t* n_out) {
+  if (!batch || !n_out) return TSDF_ERR_INVALID_ARGUMENT;
+  poll_tuner(batch);
+  const uint32_t n = (uint32_t)batch->cands.size();
+  *n_out = n;
+  for (uint32_t i = 0; i < n && i < max; ++i) {
+    if (configs) configs[i] = batch->cands[i];
+    if (ns_per_pixel) ns_per_pixel[i] = batch->best[i] * 1e9;
+  }
+  return TSDF_OK;
+}
+
 tsdf_status tsdf_batch_fuse(tsdf_batch* b, const tsdf_fuse_item* items, uint32_t n_items,
                             uint32_t flags, void* hip_stream) {
   if (!b || (n_items > 0 && !items) || n_items > b->max_items) return TSDF_ERR_INVALID_ARGUMENT;
@@ -395,7 +417,7 @@ tsdf_status tsdf_batch_fuse(tsdf_batch* b, const tsdf_fuse_item* items, uint32_t
   poll_tuner(b);
   int cand = -1;
   const tsdf_batch_config c = next_config(b, &cand);
-  const uint32_t tw = c.tile_width, th = 256u / tw;
+  const uint32_t tw = c.tile_width, th = c.pixels_per_thread * (256u / tw);
 
   // the ring slot: wait until the copy that last read it has run
   const int slot = b->next_slot;

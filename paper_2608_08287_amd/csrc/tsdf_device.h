@@ -389,14 +389,17 @@ struct TileShared {
   unsigned short list[kSetCap];
 };
 
-// One 16x16 tile of F frames (or of one frame, F = 1): the three phases.  The
-// calling thread takes pixel (px, py) of every frame in frs; frames with width
-// 0 are empty.  Every thread of the workgroup must call it; it begins with a
-// workgroup barrier, so a persistent workgroup may call it tile after tile.
+// One tile of F pixel slots per thread: the three phases.  Slot fi of the
+// calling thread is pixel (px[fi], py[fi]) of frame frs[fi]; the slots may be
+// the same pixel of F frames of one trajectory or F pixels of one frame.
+// Frames with width 0 are empty.  Every thread of the workgroup must call it;
+// it begins with a workgroup barrier, so a persistent workgroup may call it
+// tile after tile.
 template <int K, int F, int AB, FuseMode kMode>
 __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams& wp,
-                                          const FrameDev (&frs)[F], unsigned px, unsigned py,
-                                          unsigned shard, TileShared<AB>& sh) {
+                                          const FrameDev (&frs)[F], const unsigned (&px)[F],
+                                          const unsigned (&py)[F], unsigned shard,
+                                          TileShared<AB>& sh) {
   constexpr int NS = 2 * K + 1;
   constexpr bool kInsert = kMode != FuseMode::kIntegrate;
   constexpr bool kAccumulate = kMode != FuseMode::kAllocate;
@@ -418,8 +421,8 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
 #pragma unroll
   for (int fi = 0; fi < F; ++fi) {
     const FrameDev& fr = frs[fi];
-    const bool inside = px < fr.width && py < fr.height;
-    d[fi] = inside ? fr.depth[(size_t)py * fr.width + px] : 0.0f;
+    const bool inside = px[fi] < fr.width && py[fi] < fr.height;
+    d[fi] = inside ? fr.depth[(size_t)py[fi] * fr.width + px[fi]] : 0.0f;
   }
   __syncthreads();
 
@@ -433,8 +436,8 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
     const float df = d[fi];
     const bool point = __builtin_isfinite(df) && df > 0.0f;  // 0 outside the frame
     n_pts += point ? 1u : 0u;
-    const float a = ((float)px - fr.cx) * fr.ifx;
-    const float b = ((float)py - fr.cy) * fr.ify;
+    const float a = ((float)px[fi] - fr.cx) * fr.ifx;
+    const float b = ((float)py[fi] - fr.cy) * fr.ify;
     int hx[NS], hy[NS], hz[NS];
     bool hv[NS];
     unsigned long long prev_key = kEmptyKey;
@@ -538,8 +541,8 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
 #pragma unroll
     for (int fi = 0; fi < F; ++fi) {
       const FrameDev& fr = frs[fi];
-      const float a = ((float)px - fr.cx) * fr.ifx;
-      const float b = ((float)py - fr.cy) * fr.ify;
+      const float a = ((float)px[fi] - fr.cx) * fr.ifx;
+      const float b = ((float)py[fi] - fr.cy) * fr.ify;
       for (unsigned m = ovf[fi]; m != 0u; m &= m - 1u) {
         const int s = __builtin_ctz(m);
         const Sample smp = walk_sample(fr, wp, d[fi], a, b, s - K);
@@ -565,8 +568,8 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
 #pragma unroll
       for (int fi = 0; fi < F; ++fi) {
         const FrameDev& fr = frs[fi];
-        const float a = ((float)px - fr.cx) * fr.ifx;
-        const float b = ((float)py - fr.cy) * fr.ify;
+        const float a = ((float)px[fi] - fr.cx) * fr.ifx;
+        const float b = ((float)py[fi] - fr.cy) * fr.ify;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
           const unsigned w = st[fi][s];
@@ -662,14 +665,17 @@ void fuse_kernel(VolumeDev vol, WalkParams wp, FrameBatch<NB> fb, unsigned n_fra
   __shared__ TileShared<kAccBlocks> sh;
   const unsigned group = blockIdx.x / n_tiles;
   const unsigned tile = tile_of_group(blockIdx.x % n_tiles, n_tiles, remap != 0);
-  const unsigned px = (tile % tiles_x) * kTileW + (threadIdx.x % kTileW);
-  const unsigned py = (tile / tiles_x) * kTileH + (threadIdx.x / kTileW);
+  const unsigned x = (tile % tiles_x) * kTileW + (threadIdx.x % kTileW);
+  const unsigned y = (tile / tiles_x) * kTileH + (threadIdx.x / kTileW);
   FrameDev frs[F];
+  unsigned px[F], py[F];
 #pragma unroll
   for (int fi = 0; fi < F; ++fi) {
     const unsigned idx = group * F + fi;
     frs[fi] = pick_frame(fb, idx);
     if (idx >= n_frames) frs[fi].width = frs[fi].height = 0;  // past the batch: empty
+    px[fi] = x;
+    py[fi] = y;
   }
   fuse_tile<K, F, kAccBlocks, kMode>(vol, wp, frs, px, py, blockIdx.x, sh);
 }
@@ -679,17 +685,25 @@ void fuse_kernel(VolumeDev vol, WalkParams wp, FrameBatch<NB> fb, unsigned n_fra
 // first + g, first + g + gridDim.x, ... of the items of band K (items sorted by
 // K, tiles numbered by the prefix sum in the work list), finds each tile's item
 // by bisection and runs the same tile steps as the one-volume kernel against
-// that item's volume.  Tiles are tw = 2^tw_log2 pixels wide and 256 / tw tall.
-// Every value the loop reads is uniform across the workgroup, so the item
-// descriptors come in through scalar loads.
-// The work list is read-only for the whole launch: read it through the
+// that item's volume.  A tile is tw = 2^tw_log2 pixels wide and PPT * 256 / tw
+// tall: each thread takes PPT pixels of one column, 256 / tw rows apart, so a
+// wave covers 64 * PPT pixels and the workgroup sums 256 * PPT pixels'
+// contributions before they reach the pool.
+//
+// The work list is read-only for the whole launch: it is read through the
 // constant address space, where uniform loads become scalar loads that may be
 // repeated at will instead of values held in registers.
 template <typename T>
 using ConstPtr = const __attribute__((address_space(4))) T*;
 
-template <int K, int AB>
-__global__ __launch_bounds__(kThreads) void fuse_multi_kernel(BatchWork w, unsigned tw_log2) {
+// Two pixels per thread need ~146 VGPRs; with an 8-block accumulator four
+// workgroups fit a CU's LDS, so registers are capped to match (a few dwords
+// spill).  A 16-block accumulator allows two workgroups per CU: no cap.
+constexpr int multi_waves_per_eu(int ppt, int ab) { return ppt == 2 && ab <= 8 ? 4 : 1; }
+
+template <int K, int PPT, int AB>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(multi_waves_per_eu(PPT, AB))))
+void fuse_multi_kernel(BatchWork w, unsigned tw_log2) {
   __shared__ TileShared<AB> sh;
   const ConstPtr<unsigned> k_begin = (ConstPtr<unsigned>)w.k_begin;
   const ConstPtr<unsigned> tile_start = (ConstPtr<unsigned>)w.tile_start;
@@ -699,7 +713,7 @@ __global__ __launch_bounds__(kThreads) void fuse_multi_kernel(BatchWork w, unsig
   const unsigned t_end = tile_start[last];
   const unsigned lx = threadIdx.x & ((1u << tw_log2) - 1u);
   const unsigned ly = threadIdx.x >> tw_log2;
-  const unsigned th = kThreads >> tw_log2;
+  const unsigned rows = kThreads >> tw_log2;  // rows per pixel slot
   for (unsigned t = tile_start[first] + blockIdx.x; t < t_end; t += gridDim.x) {
     // the item i with tile_start[i] <= t < tile_start[i + 1]
     unsigned lo = first, hi = last;
@@ -710,21 +724,38 @@ __global__ __launch_bounds__(kThreads) void fuse_multi_kernel(BatchWork w, unsig
     }
     const BatchItem& it = *(const BatchItem*)&items[lo];
     const unsigned local = t - tile_start[lo];
-    const unsigned px = ((local % it.tiles_x) << tw_log2) + lx;
-    const unsigned py = (local / it.tiles_x) * th + ly;
-    const FrameDev frs[1] = {it.fr};
-    fuse_tile<K, 1, AB, FuseMode::kFused>(it.vol, it.wp, frs, px, py, blockIdx.x, sh);
+    const unsigned x = ((local % it.tiles_x) << tw_log2) + lx;
+    const unsigned y0 = (local / it.tiles_x) * (rows * PPT) + ly;
+    FrameDev frs[PPT];
+    unsigned px[PPT], py[PPT];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+      frs[p] = it.fr;
+      px[p] = x;
+      py[p] = y0 + p * rows;
+    }
+    fuse_tile<K, PPT, AB, FuseMode::kFused>(it.vol, it.wp, frs, px, py, blockIdx.x, sh);
   }
 }
 
 template <int K>
-const void* multi_kernel_k(int acc_blocks) {
-  switch (acc_blocks) {
-    case 4: return reinterpret_cast<const void*>(&fuse_multi_kernel<K, 4>);
-    case 8: return reinterpret_cast<const void*>(&fuse_multi_kernel<K, 8>);
-    case 16: return reinterpret_cast<const void*>(&fuse_multi_kernel<K, 16>);
-    default: return nullptr;
+const void* multi_kernel_k(int pixels_per_thread, int acc_blocks) {
+  if (pixels_per_thread == 1) {
+    switch (acc_blocks) {
+      case 4: return reinterpret_cast<const void*>(&fuse_multi_kernel<K, 1, 4>);
+      case 8: return reinterpret_cast<const void*>(&fuse_multi_kernel<K, 1, 8>);
+      case 16: return reinterpret_cast<const void*>(&fuse_multi_kernel<K, 1, 16>);
+      default: return nullptr;
+    }
   }
+  if (pixels_per_thread == 2) {
+    switch (acc_blocks) {
+      case 8: return reinterpret_cast<const void*>(&fuse_multi_kernel<K, 2, 8>);
+      case 16: return reinterpret_cast<const void*>(&fuse_multi_kernel<K, 2, 16>);
+      default: return nullptr;
+    }
+  }
+  return nullptr;
 }
 
 // Frames a workgroup may sum before flushing, keeping the per-pair state

@@ -133,19 +133,20 @@ hipError_t launch_fuse_band7(VolumeDev vol, const WalkParams& wp, const FrameDev
                              int frames_per_group, FuseMode mode, bool remap, hipStream_t s);
 hipError_t launch_fuse_band8(VolumeDev vol, const WalkParams& wp, const FrameDev* frames, int n,
                              int frames_per_group, FuseMode mode, bool remap, hipStream_t s);
-// The persistent multi-volume kernel for band half-width K accumulating
-// acc_blocks (4, 8 or 16) blocks in LDS per pass, as a host function pointer
-// for hipLaunchKernel / graph kernel nodes; nullptr for other values.  Its
-// arguments are (BatchWork work, unsigned tile_width_log2).
-const void* multi_kernel(int K, int acc_blocks);
-const void* multi_kernel_band1(int acc_blocks);
-const void* multi_kernel_band2(int acc_blocks);
-const void* multi_kernel_band3(int acc_blocks);
-const void* multi_kernel_band4(int acc_blocks);
-const void* multi_kernel_band5(int acc_blocks);
-const void* multi_kernel_band6(int acc_blocks);
-const void* multi_kernel_band7(int acc_blocks);
-const void* multi_kernel_band8(int acc_blocks);
+// The persistent multi-volume kernel for band half-width K taking
+// pixels_per_thread (1 or 2) pixels per thread and accumulating acc_blocks
+// (4, 8 or 16; 8 or 16 with 2 pixels) blocks in LDS per pass, as a host
+// function pointer for hipLaunchKernel / graph kernel nodes; nullptr for
+// other values.  Its arguments are (BatchWork work, unsigned tile_width_log2).
+const void* multi_kernel(int K, int pixels_per_thread, int acc_blocks);
+const void* multi_kernel_band1(int pixels_per_thread, int acc_blocks);
+const void* multi_kernel_band2(int pixels_per_thread, int acc_blocks);
+const void* multi_kernel_band3(int pixels_per_thread, int acc_blocks);
+const void* multi_kernel_band4(int pixels_per_thread, int acc_blocks);
+const void* multi_kernel_band5(int pixels_per_thread, int acc_blocks);
+const void* multi_kernel_band6(int pixels_per_thread, int acc_blocks);
+const void* multi_kernel_band7(int pixels_per_thread, int acc_blocks);
+const void* multi_kernel_band8(int pixels_per_thread, int acc_blocks);
 hipError_t launch_insert_blocks(VolumeDev vol, const int* coords, unsigned n, hipStream_t s);
 hipError_t launch_extract(VolumeDev vol, unsigned n_blocks, unsigned long long* keys,
                           float* tsdf, float* weight, hipStream_t s);

@@ -122,16 +122,16 @@ hipError_t launch_fuse(VolumeDev vol, const WalkParams& wp, const FrameDev* fram
   }
 }
 
-const void* multi_kernel(int K, int acc_blocks) {
+const void* multi_kernel(int K, int pixels_per_thread, int acc_blocks) {
   switch (K) {
-    case 1: return multi_kernel_band1(acc_blocks);
-    case 2: return multi_kernel_band2(acc_blocks);
-    case 3: return multi_kernel_band3(acc_blocks);
-    case 4: return multi_kernel_band4(acc_blocks);
-    case 5: return multi_kernel_band5(acc_blocks);
-    case 6: return multi_kernel_band6(acc_blocks);
-    case 7: return multi_kernel_band7(acc_blocks);
-    case 8: return multi_kernel_band8(acc_blocks);
+    case 1: return multi_kernel_band1(pixels_per_thread, acc_blocks);
+    case 2: return multi_kernel_band2(pixels_per_thread, acc_blocks);
+    case 3: return multi_kernel_band3(pixels_per_thread, acc_blocks);
+    case 4: return multi_kernel_band4(pixels_per_thread, acc_blocks);
+    case 5: return multi_kernel_band5(pixels_per_thread, acc_blocks);
+    case 6: return multi_kernel_band6(pixels_per_thread, acc_blocks);
+    case 7: return multi_kernel_band7(pixels_per_thread, acc_blocks);
+    case 8: return multi_kernel_band8(pixels_per_thread, acc_blocks);
     default: return nullptr;
   }
 }

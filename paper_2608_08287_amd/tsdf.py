@@ -39,7 +39,8 @@ EXPORTED_SYMBOLS = (
     "tsdf_query_status",
     "tsdf_extract_blocks", "tsdf_insert_blocks", "tsdf_status_str",
     "tsdf_batch_workspace_bytes", "tsdf_batch_create", "tsdf_batch_destroy",
-    "tsdf_batch_set_config", "tsdf_batch_autotune", "tsdf_batch_get_config", "tsdf_batch_fuse",
+    "tsdf_batch_set_config", "tsdf_batch_autotune", "tsdf_batch_get_config",
+    "tsdf_batch_candidates", "tsdf_batch_fuse",
 )
 BATCH_NO_GRAPH = 0x1
 BATCH_MAX_ITEMS = 65536
@@ -76,8 +77,8 @@ class FuseItemC(C.Structure):
 
 
 class BatchConfigC(C.Structure):
-    _fields_ = [("tile_width", C.c_uint32), ("acc_blocks", C.c_uint32),
-                ("groups_per_cu", C.c_uint32)]
+    _fields_ = [("tile_width", C.c_uint32), ("pixels_per_thread", C.c_uint32),
+                ("acc_blocks", C.c_uint32), ("groups_per_cu", C.c_uint32)]
 
 
 class TsdfError(RuntimeError):
@@ -134,6 +135,9 @@ def lib() -> C.CDLL:
         L.tsdf_batch_autotune.argtypes = [P, U32]
         L.tsdf_batch_get_config.restype = I
         L.tsdf_batch_get_config.argtypes = [P, C.POINTER(BatchConfigC), C.POINTER(U32)]
+        L.tsdf_batch_candidates.restype = I
+        L.tsdf_batch_candidates.argtypes = [P, U32, C.POINTER(BatchConfigC), C.POINTER(C.c_double),
+                                            C.POINTER(U32)]
         L.tsdf_batch_fuse.restype = I
         L.tsdf_batch_fuse.argtypes = [P, C.POINTER(FuseItemC), U32, U32, P]
         _lib = L
@@ -333,9 +337,10 @@ def fuse_frames(vol: Volume, depths: Sequence[torch.Tensor], cams: Sequence, fla
 
 @dataclass(frozen=True)
 class BatchConfig:
-    tile_width: int     # 16, 32 or 64 pixels (tile height 256 / tile_width)
-    acc_blocks: int     # LDS accumulator blocks per pass: 4, 8 or 16
-    groups_per_cu: int  # persistent workgroups per CU, 0 = all that fit
+    tile_width: int         # 16, 32 or 64 pixels
+    pixels_per_thread: int  # 1 or 2 (tile height pixels_per_thread * 256 / tile_width)
+    acc_blocks: int         # LDS accumulator blocks per pass: 4, 8 or 16 (8, 16 with 2 pixels)
+    groups_per_cu: int      # persistent workgroups per CU, 0 = all that fit
 
 
 class Batch:
@@ -366,7 +371,7 @@ class Batch:
             pass
 
     def set_config(self, cfg: BatchConfig) -> None:
-        c = BatchConfigC(cfg.tile_width, cfg.acc_blocks, cfg.groups_per_cu)
+        c = BatchConfigC(cfg.tile_width, cfg.pixels_per_thread, cfg.acc_blocks, cfg.groups_per_cu)
         st = lib().tsdf_batch_set_config(self._h, C.byref(c))
         if st != OK:
             raise TsdfError(st, "tsdf_batch_set_config")
@@ -381,7 +386,20 @@ class Batch:
         st = lib().tsdf_batch_get_config(self._h, C.byref(c), C.byref(tuned))
         if st != OK:
             raise TsdfError(st, "tsdf_batch_get_config")
-        return BatchConfig(c.tile_width, c.acc_blocks, c.groups_per_cu), bool(tuned.value)
+        return (BatchConfig(c.tile_width, c.pixels_per_thread, c.acc_blocks, c.groups_per_cu),
+                bool(tuned.value))
+
+    def candidates(self) -> list[tuple[BatchConfig, float]]:
+        """The tuner's candidates with the least ns per pixel measured for each."""
+        n = C.c_uint32(0)
+        L = lib()
+        if L.tsdf_batch_candidates(self._h, 0, None, None, C.byref(n)) != OK:
+            raise TsdfError(ERR_INVALID_ARGUMENT, "tsdf_batch_candidates")
+        cfgs = (BatchConfigC * max(n.value, 1))()
+        ns = (C.c_double * max(n.value, 1))()
+        L.tsdf_batch_candidates(self._h, n.value, cfgs, ns, C.byref(n))
+        return [(BatchConfig(c.tile_width, c.pixels_per_thread, c.acc_blocks, c.groups_per_cu),
+                 float(t)) for c, t in zip(cfgs[:n.value], ns[:n.value])]
 
     def fuse(self, volumes: Sequence[Volume], depths: Sequence[torch.Tensor], cams,
              flags: int = 0, stream=None) -> None:

@@ -122,10 +122,12 @@ def test_batch_rejects_bad_arguments_before_any_device_work():
     assert L.tsdf_batch_create(8, C.c_void_p(4096 + 16), need, C.byref(h)) == T.ERR_INVALID_ARGUMENT
     assert L.tsdf_batch_create(8, C.c_void_p(4096), need - 1, C.byref(h)) == T.ERR_BUFFER_TOO_SMALL
     assert not h.value
-    cfg = T.BatchConfigC(16, 8, 0)
+    cfg = T.BatchConfigC(16, 1, 8, 0)
     tuned = C.c_uint32()
     assert L.tsdf_batch_destroy(None) == T.ERR_INVALID_ARGUMENT
     assert L.tsdf_batch_set_config(None, C.byref(cfg)) == T.ERR_INVALID_ARGUMENT
     assert L.tsdf_batch_autotune(None, 2) == T.ERR_INVALID_ARGUMENT
     assert L.tsdf_batch_get_config(None, C.byref(cfg), C.byref(tuned)) == T.ERR_INVALID_ARGUMENT
     assert L.tsdf_batch_fuse(None, None, 0, 0, None) == T.ERR_INVALID_ARGUMENT
+    n = C.c_uint32()
+    assert L.tsdf_batch_candidates(None, 0, None, None, C.byref(n)) == T.ERR_INVALID_ARGUMENT

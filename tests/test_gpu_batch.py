@@ -17,8 +17,10 @@ from parity import assert_parity, assert_same_volume, log, result_of
 pytestmark = pytest.mark.gpu
 
 SMALL = ((160, 120), (320, 240))
-CONFIGS = [T.BatchConfig(tw, ab, gpc) for tw in (16, 32, 64) for ab in (4, 8, 16)
-           for gpc in (0, 1)]
+CONFIGS = ([T.BatchConfig(tw, 1, ab, gpc) for tw in (16, 32, 64) for ab in (4, 8, 16)
+            for gpc in (0, 1)]
+           + [T.BatchConfig(tw, 2, ab, gpc) for tw in (16, 32, 64) for ab in (8, 16)
+              for gpc in (0, 1)])
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -87,7 +89,8 @@ def test_batch_equals_single_volume_path():
         assert st.pairs > 0 and st.pairs_dropped == 0
 
 
-@pytest.mark.parametrize("cfg", CONFIGS, ids=lambda c: f"tw{c.tile_width}_ab{c.acc_blocks}_g{c.groups_per_cu}")
+@pytest.mark.parametrize("cfg", CONFIGS, ids=lambda c: f"tw{c.tile_width}_p{c.pixels_per_thread}_"
+                                                      f"ab{c.acc_blocks}_g{c.groups_per_cu}")
 def test_every_configuration(cfg):
     w = S.MultiVolumeWorkload(4, seed=13, sizes=S.FRAME_SIZES, log2_tables=(17, 17))
     batch = T.Batch(4)
@@ -106,7 +109,7 @@ def test_replays_with_changing_work_lists(flags):
     w = S.MultiVolumeWorkload(7, seed=14, sizes=S.FRAME_SIZES, log2_tables=(17, 17))
     which = [[0, 1, 2, 3, 4, 5, 6], [3], [6, 0, 2], [1, 2, 3, 4], [5, 5, 5, 1], [0, 6]]
     batch = T.Batch(8)
-    batch.set_config(T.BatchConfig(16, 8, 0))
+    batch.set_config(T.BatchConfig(16, 2, 8, 0))
     a = fuse_batched(w, len(which), batch, which, flags)
     b = fuse_alone(w, len(which), which)
     for i in range(len(w)):
@@ -122,7 +125,7 @@ def test_mixed_band_widths_in_one_call():
     batch = T.Batch(8)
     for mode in ("tune", "graph"):
         if mode == "graph":
-            batch.set_config(T.BatchConfig(32, 8, 0))
+            batch.set_config(T.BatchConfig(32, 2, 16, 0))
         a = [T.Volume(*p) for p in vol_params]
         b = [T.Volume(*p) for p in vol_params]
         for k in range(2):
@@ -168,7 +171,11 @@ def test_autotuner_settles_and_stays_correct():
         torch.cuda.synchronize()
         cfg, tuned = batch.config()
     assert cfg.tile_width in (16, 32, 64) and cfg.acc_blocks in (4, 8, 16)
+    assert cfg.pixels_per_thread in (1, 2)
     log(f"  tuned after {ticks} calls: {cfg}")
+    cands = batch.candidates()
+    assert len(cands) >= 15 and all(np.isfinite(t) and t > 0 for _, t in cands)
+    assert cfg == min(cands, key=lambda ct: ct[1])[0]
     ref = fuse_alone(w, ticks)
     for i in range(len(w)):
         assert_same_volume(vols[i], ref[i])
@@ -203,7 +210,8 @@ def test_batch_argument_errors():
     assert L.tsdf_batch_fuse(batch._h, items, 3, 0, None) == T.ERR_INVALID_ARGUMENT
     assert L.tsdf_batch_fuse(batch._h, items, 1, 0, None) == T.ERR_INVALID_ARGUMENT  # null volume
     assert L.tsdf_batch_fuse(batch._h, None, 0, 0x2, None) == T.ERR_INVALID_ARGUMENT  # unknown flag
-    for bad in (T.BatchConfigC(8, 8, 0), T.BatchConfigC(16, 5, 0), T.BatchConfigC(16, 8, 65)):
+    for bad in (T.BatchConfigC(8, 1, 8, 0), T.BatchConfigC(16, 1, 5, 0), T.BatchConfigC(16, 1, 8, 65),
+                T.BatchConfigC(16, 0, 8, 0), T.BatchConfigC(16, 3, 8, 0), T.BatchConfigC(16, 2, 4, 0)):
         assert L.tsdf_batch_set_config(batch._h, bad) == T.ERR_INVALID_ARGUMENT
     assert L.tsdf_batch_autotune(batch._h, 0) == T.ERR_INVALID_ARGUMENT
     assert L.tsdf_batch_autotune(batch._h, 17) == T.ERR_INVALID_ARGUMENT
@@ -227,7 +235,7 @@ def test_full_size_multi_volume_tick():
         log(f"  {mode}")
         batch = T.Batch(64)
         if mode == "graph":
-            batch.set_config(T.BatchConfig(16, 8, 0))
+            batch.set_config(T.BatchConfig(16, 1, 8, 0))
         vols = make_volumes(w)
         for d, c in dev:
             batch.fuse(vols, d, c)
