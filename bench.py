@@ -326,6 +326,142 @@ def bench_multi(args) -> int:
     return 0
 
 
+def bench_serve(args) -> int:
+    """Serving: sessions fed by Poisson frame arrivals, through tsdf_server_*.
+
+    256 sessions (frame sizes 160x120 .. 1280x720, voxels 5..10 mm, pools
+    2^14..2^18 blocks, tables twice the pool) are admitted against a 200 GB
+    budget.  An arrival trace of 3000 frames/s for one second is replayed in
+    real time by the library's native driver twice on fresh sessions: served
+    (continuous batching across sessions) and plain (one tsdf_fuse_frame per
+    frame on arrival); each reports every frame's latency.  Then the same
+    frames are replayed with every arrival at time zero, which measures the
+    capacity (points/s) of each path.  The session counters of the served and
+    plain runs must agree.
+    """
+    import torch
+
+    from paper_2608_08287_amd import scenes as S
+    from paper_2608_08287_amd import tsdf as T
+
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    w = S.ServingWorkload(args.sessions, rate=args.rate, duration_s=args.duration)
+    n = len(w)
+    depths = [torch.from_numpy(w.depth(int(s), int(k), device="cuda")).cuda()
+              for s, k in zip(w.session_of, w.frame_of)]
+    cams = [T.camera_struct(w.camera(int(s), int(k))) for s, k in zip(w.session_of, w.frame_of)]
+    points = int(sum(int((d > 0).sum()) for d in depths))
+    log(f"[bench] rendered {n} frames for {len(w.specs)} sessions in {time.time() - t0:.1f}s "
+        f"({points} points)")
+    need = sum(T.volume_bytes(T.volume_params(sp.voxel_size, sp.trunc, sp.table_capacity,
+                                              sp.pool_capacity)) for sp in w.specs)
+    cfg = T.BatchConfig(*(int(x) for x in args.batch_config.split(","))) if args.batch_config \
+        else T.BatchConfig(16, 1, 8, 0)
+
+    def run(mode, budget):
+        server = T.Server(budget, max_sessions=len(w.specs) + 1, max_batch=args.max_batch,
+                          max_inflight=args.max_inflight, max_queue=max(4096, n))
+        server.batch_config(cfg)
+        ids = []
+        for sp in w.specs:
+            sid = server.open(sp.voxel_size, sp.trunc, sp.table_capacity, sp.pool_capacity)
+            if sid is None:
+                raise RuntimeError("a session was not admitted")
+            ids.append(sid)
+        # warm the launch path (graph instantiation, first dispatches) on a
+        # throwaway session
+        sp = w.specs[0]
+        warm = server.open(sp.voxel_size, sp.trunc, sp.table_capacity, sp.pool_capacity)
+        for j in range(3):
+            server.submit(warm, depths[0], cams[0], j)
+        got = 0
+        while got < 3:
+            server.step()
+            got += len(server.completions())
+        server.close_session(warm)
+        torch.cuda.synchronize()
+        sess = [ids[int(s)] for s in w.session_of]
+        lat, elapsed = server.replay(w.arrival_ns, sess, depths, cams, mode)
+        _, cap_elapsed = server.replay(np.zeros(n, dtype=np.int64), sess, depths, cams, mode)
+        stats = [server.session(i)[0].stats() for i in ids]
+        fails = [i for i in ids if server.session(i)[1] != T.OK]
+        used = server.load()["budget_used"]
+        server.close()
+        del server
+        torch.cuda.empty_cache()
+        return lat, elapsed, cap_elapsed, stats, fails, used
+
+    lat_s, el_s, cap_s, st_s, fail_s, used = run(T.REPLAY_SERVED, int(args.budget_gb * 1e9))
+    log(f"[bench] served: p50 {np.percentile(lat_s, 50) / 1e3:.1f} us, "
+        f"p99 {np.percentile(lat_s, 99) / 1e3:.1f} us; capacity {points / cap_s * 1e9:.3e} points/s")
+    lat_p, el_p, cap_p, st_p, fail_p, _ = run(T.REPLAY_PLAIN, int(need * 1.02) + (64 << 20))
+    log(f"[bench] plain: p50 {np.percentile(lat_p, 50) / 1e3:.1f} us, "
+        f"p99 {np.percentile(lat_p, 99) / 1e3:.1f} us; capacity {points / cap_p * 1e9:.3e} points/s")
+    for i, (a, b) in enumerate(zip(st_s, st_p)):
+        for f in ("points_valid", "pairs", "pairs_dropped", "blocks_total", "frames"):
+            if getattr(a, f) != getattr(b, f):
+                print(f"gate failed: session {i} {f} {getattr(a, f)} != {getattr(b, f)}",
+                      file=sys.stderr)
+                return 1
+    dropped = sum(a.pairs_dropped for a in st_s)
+    if fail_s or fail_p or dropped:
+        print(f"gate failed: sessions failed {fail_s} / {fail_p}, {dropped} pairs dropped",
+              file=sys.stderr)
+        return 1
+    refused = int(np.sum(lat_s < 0))
+    # the capacity replay fuses every frame a second time: its points are `points` again
+    value = points / (cap_s * 1e-9)
+    plain_value = points / (cap_p * 1e-9)
+
+    def pct(x, q):
+        return float(np.percentile(x[x >= 0], q) / 1e6)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": cap_s * 1e-6,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{len(w.specs)} sessions, Poisson arrivals at {args.rate:g} frames/s for "
+                        f"{args.duration:g} s ({n} frames, {points} points; frames 160x120.."
+                        f"1280x720), voxels 5..10 mm, pools 2^14..2^18 blocks, tables 2x pool, "
+                        f"budget {args.budget_gb:g} GB ({used / 1e9:.1f} GB admitted)",
+            "path": f"tsdf_server: continuous batching, up to {args.max_batch} frames per launch, "
+                    f"{args.max_inflight} launch(es) in flight, graph replay",
+            "batch_config": {"tile_width": cfg.tile_width, "pixels_per_thread": cfg.pixels_per_thread,
+                             "acc_blocks": cfg.acc_blocks, "groups_per_cu": cfg.groups_per_cu},
+            "step": "every frame of the trace arriving at once (capacity)",
+            "parallelism": "single GPU",
+        },
+        "served": {
+            "p50_latency_ms": pct(lat_s, 50), "p99_latency_ms": pct(lat_s, 99),
+            "max_latency_ms": pct(lat_s, 100), "refused_frames": refused,
+            "sustained_points_per_s": points / (el_s * 1e-9),
+            "capacity_points_per_s": value,
+        },
+        "plain": {
+            "p50_latency_ms": pct(lat_p, 50), "p99_latency_ms": pct(lat_p, 99),
+            "max_latency_ms": pct(lat_p, 100),
+            "sustained_points_per_s": points / (el_p * 1e-9),
+            "capacity_points_per_s": plain_value,
+        },
+        "capacity_vs_plain": value / plain_value,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -344,9 +480,16 @@ def main() -> int:
     ap.add_argument("--profile-copy-bytes", type=int, default=0,
                     help="after the run, copy this many bytes device-to-device three times "
                          "(a kernel of known traffic for scaling hardware byte counters)")
-    ap.add_argument("--workload", choices=["trajectory", "multi"], default="trajectory",
+    ap.add_argument("--workload", choices=["trajectory", "multi", "serve"], default="trajectory",
                     help="trajectory: one volume, the 300-frame orbit (default); multi: many "
-                         "volumes, one frame each per tick, through the batch API")
+                         "volumes, one frame each per tick, through the batch API; serve: "
+                         "sessions with Poisson arrivals through the server")
+    ap.add_argument("--sessions", type=int, default=256, help="serve: sessions")
+    ap.add_argument("--rate", type=float, default=3000.0, help="serve: frames/s, all sessions")
+    ap.add_argument("--duration", type=float, default=1.0, help="serve: seconds of arrivals")
+    ap.add_argument("--budget-gb", type=float, default=200.0, help="serve: session budget")
+    ap.add_argument("--max-batch", type=int, default=256, help="serve: frames per launch")
+    ap.add_argument("--max-inflight", type=int, default=2, help="serve: launches in flight")
     ap.add_argument("--volumes", type=int, default=64, help="multi: volumes per tick")
     ap.add_argument("--trials", type=int, default=2, help="multi: autotuner trials per candidate")
     ap.add_argument("--batch-config", default="",
@@ -357,12 +500,12 @@ def main() -> int:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "the volume is not sharded across GPUs", file=sys.stderr)
         return 2
-    if args.workload == "multi":
+    if args.workload in ("multi", "serve"):
         import torch
         if not torch.cuda.is_available():
             print("bench.py needs a GPU", file=sys.stderr)
             return 1
-        return bench_multi(args)
+        return bench_multi(args) if args.workload == "multi" else bench_serve(args)
 
     import torch
 

@@ -49,7 +49,8 @@ typedef enum tsdf_status {
   TSDF_ERR_TABLE_FULL = 4,        /* a key found neither itself nor a free slot (sticky) */
   TSDF_ERR_COORD_RANGE = 5,       /* a sample's voxel lies outside the key range (sticky) */
   TSDF_ERR_INTERNAL = 6,          /* an invariant broke on the device (sticky) */
-  TSDF_ERR_HIP = 7                /* a HIP runtime call failed */
+  TSDF_ERR_HIP = 7,               /* a HIP runtime call failed */
+  TSDF_ERR_BUDGET = 8             /* a region, queue or session table has no room */
 } tsdf_status;
 
 /* Sticky status bits, as returned in tsdf_stats.status_bits. */
@@ -293,6 +294,138 @@ tsdf_status tsdf_batch_candidates(tsdf_batch* batch, uint32_t max, tsdf_batch_co
 #define TSDF_BATCH_NO_GRAPH 0x1u
 tsdf_status tsdf_batch_fuse(tsdf_batch* batch, const tsdf_fuse_item* items, uint32_t n_items,
                             uint32_t flags, void* hip_stream);
+
+/* ---------------------------------------------------------------------------
+ * Device-region sub-allocator.  Carves 256-byte-aligned ranges out of one
+ * caller-owned device region (first fit, neighbouring free ranges merged).
+ * Host bookkeeping only: the region's memory is never read or written, and
+ * every call works without a GPU.  Not thread-safe.
+ * ------------------------------------------------------------------------- */
+typedef struct tsdf_region tsdf_region;
+
+/* Manage [device_base, device_base + bytes); the usable part starts at the
+ * first 256-byte boundary and is a whole number of 256-byte units. */
+tsdf_status tsdf_region_create(void* device_base, uint64_t bytes, tsdf_region** out);
+tsdf_status tsdf_region_destroy(tsdf_region* region);
+
+/* A range of at least `bytes` (rounded up to 256); TSDF_ERR_BUDGET if no free
+ * range is large enough. */
+tsdf_status tsdf_region_alloc(tsdf_region* region, uint64_t bytes, void** out);
+
+/* Return a range from tsdf_region_alloc; anything else is rejected with
+ * TSDF_ERR_INVALID_ARGUMENT. */
+tsdf_status tsdf_region_free(tsdf_region* region, void* ptr);
+
+/* Usable bytes, bytes handed out, the largest free range and the number of
+ * live ranges; any output may be NULL. */
+tsdf_status tsdf_region_usage(const tsdf_region* region, uint64_t* capacity, uint64_t* used,
+                              uint64_t* largest_free, uint32_t* n_live);
+
+/* ---------------------------------------------------------------------------
+ * Serving.  A server holds many reconstruction sessions, each one resident
+ * volume carved from a device budget, and fuses the frames submitted to them
+ * with continuous batching: each launch takes every queued frame (up to
+ * max_batch, first come first served, any mix of sessions) through the batch
+ * path above, and a new launch starts whenever fewer than max_inflight are
+ * running.  A session's result is the one it would have alone (the batch
+ * path's guarantee).  After each launch a small kernel copies every
+ * session's sticky status to pinned host memory; a session whose pool or
+ * table ran out is marked failed, and its later frames are refused instead of
+ * probing a full table, without touching the other sessions.
+ *
+ * The server is driven from one host thread: tsdf_server_submit queues,
+ * tsdf_server_step retires finished launches and starts new ones, and
+ * tsdf_server_completions hands back the tags of finished frames.  All device
+ * work goes to the stream given at creation.  Depth frames must stay valid
+ * until their tags come back.
+ * ------------------------------------------------------------------------- */
+typedef struct tsdf_server tsdf_server;
+
+typedef struct tsdf_server_params {
+  uint32_t max_sessions;  /* 1 .. 65536 */
+  uint32_t max_batch;     /* frames per launch, 1 .. TSDF_BATCH_MAX_ITEMS */
+  uint32_t max_inflight;  /* launches running at once, 1 .. 16 */
+  uint32_t max_queue;     /* frames waiting, max_batch .. 2^24 */
+} tsdf_server_params;
+
+/* Device workspace bytes for `params` (the batch work list); 0 if invalid. */
+size_t tsdf_server_workspace_bytes(const tsdf_server_params* params);
+
+/* Make a server.  workspace_dev: >= tsdf_server_workspace_bytes, 256-aligned.
+ * Session volumes are carved from [session_region_dev, + budget_bytes).  The
+ * server also owns a tsdf_batch (its autotuner starts on), pinned host status
+ * words and one HIP event per in-flight launch. */
+tsdf_status tsdf_server_create(const tsdf_server_params* params, void* workspace_dev,
+                               size_t workspace_bytes, void* session_region_dev,
+                               uint64_t budget_bytes, void* hip_stream, tsdf_server** out);
+
+/* Wait for every launch, then free the server's host resources.  Queued
+ * frames are dropped without completions. */
+tsdf_status tsdf_server_destroy(tsdf_server* server);
+
+/* Admit a session: carve tsdf_volume_bytes(params) from the budget and
+ * enqueue the volume's initialisation.  TSDF_ERR_BUDGET if the budget (or
+ * the session table) has no room. */
+tsdf_status tsdf_server_open(tsdf_server* server, const tsdf_volume_params* params,
+                             uint32_t* session_out);
+
+/* Retire a session: its queued frames are dropped (completed with
+ * TSDF_ERR_INVALID_ARGUMENT), the server waits for launches that hold its
+ * frames, and its memory returns to the budget. */
+tsdf_status tsdf_server_close(tsdf_server* server, uint32_t session);
+
+/* Queue one frame (depth_dev: height x width float32 on the device) for a
+ * session.  Returns TSDF_ERR_BUDGET if the queue is full, and the session's
+ * failure status (TSDF_ERR_POOL_EXHAUSTED, TSDF_ERR_TABLE_FULL,
+ * TSDF_ERR_INTERNAL) once it has failed. */
+tsdf_status tsdf_server_submit(tsdf_server* server, uint32_t session, const float* depth_dev,
+                               const tsdf_camera* camera, uint64_t tag);
+
+/* Retire finished launches (non-blocking) and, if fewer than max_inflight
+ * are running and frames are queued, launch one batch.  *launched (may be
+ * NULL) receives the number of frames launched. */
+tsdf_status tsdf_server_step(tsdf_server* server, uint32_t* launched);
+
+/* Pop up to `max` finished frames: their tags and statuses (TSDF_OK when
+ * fused; a failed session's status when its frame was refused at launch;
+ * TSDF_ERR_INVALID_ARGUMENT when its session was closed first). */
+tsdf_status tsdf_server_completions(tsdf_server* server, uint64_t* tags, int32_t* statuses,
+                                    uint32_t max, uint32_t* n_out);
+
+/* A session's volume (for tsdf_query_status / tsdf_extract_blocks on the
+ * server's stream) and its failure status (TSDF_OK while healthy). */
+tsdf_status tsdf_server_session(tsdf_server* server, uint32_t session, tsdf_volume** volume,
+                                int32_t* failure);
+
+/* The server's batch, e.g. to fix its configuration. */
+tsdf_status tsdf_server_batch(tsdf_server* server, tsdf_batch** out);
+
+/* Frames queued and in flight, launches in flight, sessions open, and budget
+ * bytes used; any output may be NULL. */
+tsdf_status tsdf_server_load(tsdf_server* server, uint32_t* queued, uint32_t* inflight_frames,
+                             uint32_t* inflight_launches, uint32_t* sessions,
+                             uint64_t* budget_used);
+
+/* Replay an arrival trace in real time on the host's steady clock and report
+ * each request's latency: completion (when the host sees the frame's launch
+ * finish) minus arrival.  Requests must be sorted by arrival_ns, offsets from
+ * the start of the replay.
+ *   TSDF_REPLAY_SERVED  through tsdf_server_submit / _step / _completions
+ *   TSDF_REPLAY_PLAIN   one tsdf_fuse_frame per request, launched when it
+ *                       arrives, on the server's stream (the comparison)
+ * latency_ns[i] gets request i's latency (-1 if it was refused);
+ * *elapsed_ns the time from the start to the last completion. */
+typedef struct tsdf_request {
+  uint64_t arrival_ns;
+  uint32_t session;
+  uint32_t reserved;
+  const float* depth_dev;
+  tsdf_camera camera;
+} tsdf_request;
+#define TSDF_REPLAY_SERVED 0u
+#define TSDF_REPLAY_PLAIN 1u
+tsdf_status tsdf_server_replay(tsdf_server* server, const tsdf_request* requests, uint32_t n,
+                               uint32_t mode, double* latency_ns, double* elapsed_ns);
 
 /* Static text for a status code. */
 const char* tsdf_status_str(tsdf_status status);

@@ -19,8 +19,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libtsdf.so")
-SOURCES = ([os.path.join(CSRC, "tsdf_api.cpp"), os.path.join(CSRC, "tsdf_batch.cpp"),
-            os.path.join(CSRC, "tsdf_kernels.hip")]
+SOURCES = ([os.path.join(CSRC, n) for n in ("tsdf_api.cpp", "tsdf_batch.cpp", "tsdf_arena.cpp",
+                                             "tsdf_server.cpp", "tsdf_kernels.hip")]
            + sorted(glob.glob(os.path.join(CSRC, "tsdf_fuse_k*.hip"))))
 BUILD_DIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -266,6 +266,7 @@ const char* tsdf_status_str(tsdf_status status) {
     case TSDF_ERR_COORD_RANGE: return "voxel coordinate outside the key range";
     case TSDF_ERR_INTERNAL: return "internal invariant violated";
     case TSDF_ERR_HIP: return "HIP runtime error";
+    case TSDF_ERR_BUDGET: return "no room in the region, queue or session table";
   }
   return "unknown status";
 }

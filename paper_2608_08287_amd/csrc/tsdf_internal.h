@@ -147,6 +147,9 @@ const void* multi_kernel_band5(int pixels_per_thread, int acc_blocks);
 const void* multi_kernel_band6(int pixels_per_thread, int acc_blocks);
 const void* multi_kernel_band7(int pixels_per_thread, int acc_blocks);
 const void* multi_kernel_band8(int pixels_per_thread, int acc_blocks);
+// out[i] = the sticky status bits of the volume whose counters ctrs[i] points
+// to (0 for a null pointer), i < n.  ctrs and out may be host-mapped memory.
+hipError_t launch_gather_status(DevCounters* const* ctrs, unsigned n, unsigned* out, hipStream_t s);
 hipError_t launch_insert_blocks(VolumeDev vol, const int* coords, unsigned n, hipStream_t s);
 hipError_t launch_extract(VolumeDev vol, unsigned n_blocks, unsigned long long* keys,
                           float* tsdf, float* weight, hipStream_t s);

@@ -122,6 +122,21 @@ hipError_t launch_fuse(VolumeDev vol, const WalkParams& wp, const FrameDev* fram
   }
 }
 
+__global__ __launch_bounds__(256) void gather_status_kernel(DevCounters* const* ctrs, unsigned n, unsigned* out) {
+  const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const DevCounters* c = ctrs[i];
+  const unsigned bits =
+      c ? __hip_atomic_load(&c->status_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+  __hip_atomic_store(&out[i], bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+hipError_t launch_gather_status(DevCounters* const* ctrs, unsigned n, unsigned* out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_status_kernel, dim3((n + 255) / 256), dim3(256), 0, s, ctrs, n, out);
+  return hipGetLastError();
+}
+
 const void* multi_kernel(int K, int pixels_per_thread, int acc_blocks) {
   switch (K) {
     case 1: return multi_kernel_band1(pixels_per_thread, acc_blocks);

@@ -371,3 +371,65 @@ class MultiVolumeWorkload:
 
     def pixels(self) -> int:
         return sum(s.width * s.height for s in self.specs)
+
+
+class ServingWorkload:
+    """Reconstruction sessions fed by Poisson frame arrivals.
+
+    From ``default_rng(seed)``: per session a frame size uniform over
+    ``sizes``, a voxel edge uniform over 5..10 mm and a pool exponent e
+    uniform over ``log2_pools[0]..log2_pools[1]``; the exponents are dealt in
+    the reverse order of the voxel edges, as in ``MultiVolumeWorkload``.  Pool
+    2^e blocks, table twice the pool (the paper's sizing), truncation 4 voxels,
+    an own room scene and orbit start.  Arrivals form one Poisson process of
+    ``rate`` frames/s (exponential gaps), each arrival going to a session drawn
+    uniformly, so every session sees a Poisson process of rate / n.  A
+    session's k-th frame is its orbit frame ``orbit_offset + k`` with noise
+    seed ``noise_seed + k``.
+    """
+
+    def __init__(self, n_sessions: int = 256, rate: float = 3000.0, duration_s: float = 1.0,
+                 seed: int = 4, sizes=FRAME_SIZES, log2_pools=(14, 18), n_orbit: int = 300):
+        rng = np.random.default_rng(seed)
+        self.n_orbit = n_orbit
+        size_idx = rng.integers(0, len(sizes), size=n_sessions)
+        voxel_mm = rng.integers(5, 11, size=n_sessions)
+        exps = rng.integers(log2_pools[0], log2_pools[1] + 1, size=n_sessions)
+        scene_seeds = rng.integers(1, 1 << 30, size=n_sessions)
+        offsets = rng.integers(0, n_orbit, size=n_sessions)
+        exp_of = np.empty(n_sessions, dtype=np.int64)
+        exp_of[np.argsort(voxel_mm, kind="stable")] = np.sort(exps)[::-1]
+        self.specs: List[VolumeSpec] = []
+        for i in range(n_sessions):
+            w, h = sizes[int(size_idx[i])]
+            v = int(voxel_mm[i]) * 1e-3
+            e = int(exp_of[i])
+            self.specs.append(VolumeSpec(
+                width=w, height=h, voxel_size=v, trunc=4.0 * v, table_capacity=1 << (e + 1),
+                pool_capacity=1 << e, scene_seed=int(scene_seeds[i]),
+                orbit_offset=int(offsets[i]), noise_seed=(i + 1) * 100000 + 7))
+        gaps = rng.exponential(1.0 / rate, size=int(rate * duration_s * 1.5) + 16)
+        t = np.cumsum(gaps)
+        t = t[t < duration_s]
+        self.arrival_ns = np.round(t * 1e9).astype(np.int64)
+        self.session_of = rng.integers(0, n_sessions, size=t.size)
+        # frame index within its session
+        self.frame_of = np.zeros(t.size, dtype=np.int64)
+        seen = np.zeros(n_sessions, dtype=np.int64)
+        for j, s in enumerate(self.session_of):
+            self.frame_of[j] = seen[s]
+            seen[s] += 1
+        self._scenes = {}
+
+    def __len__(self) -> int:
+        return int(self.arrival_ns.size)
+
+    def camera(self, session: int, k: int) -> Camera:
+        s = self.specs[session]
+        return orbit_camera((s.orbit_offset + k) % self.n_orbit, self.n_orbit, s.width, s.height)
+
+    def depth(self, session: int, k: int, device="cpu") -> np.ndarray:
+        if session not in self._scenes:
+            self._scenes[session] = room_scene(self.specs[session].scene_seed)
+        return render_depth(self.camera(session, k), self._scenes[session],
+                            lambda z: 0.002 * z * z, self.specs[session].noise_seed + k, device)

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libtsdf.so")
 
 # tsdf_status
 OK, ERR_INVALID_ARGUMENT, ERR_BUFFER_TOO_SMALL, ERR_POOL_EXHAUSTED, ERR_TABLE_FULL, \
-    ERR_COORD_RANGE, ERR_INTERNAL, ERR_HIP = range(8)
+    ERR_COORD_RANGE, ERR_INTERNAL, ERR_HIP, ERR_BUDGET = range(9)
 FLAG_POOL_EXHAUSTED, FLAG_TABLE_FULL, FLAG_COORD_RANGE, FLAG_INTERNAL = 1, 2, 4, 8
 FUSE_DEFAULT, FUSE_TWO_PASS, FUSE_ALLOCATE_ONLY, FUSE_INTEGRATE_ONLY = 0, 1, 2, 3
 FUSE_XCD_REMAP = 0x100
@@ -41,7 +41,13 @@ EXPORTED_SYMBOLS = (
     "tsdf_batch_workspace_bytes", "tsdf_batch_create", "tsdf_batch_destroy",
     "tsdf_batch_set_config", "tsdf_batch_autotune", "tsdf_batch_get_config",
     "tsdf_batch_candidates", "tsdf_batch_fuse",
+    "tsdf_region_create", "tsdf_region_destroy", "tsdf_region_alloc", "tsdf_region_free",
+    "tsdf_region_usage",
+    "tsdf_server_workspace_bytes", "tsdf_server_create", "tsdf_server_destroy", "tsdf_server_open",
+    "tsdf_server_close", "tsdf_server_submit", "tsdf_server_step", "tsdf_server_completions",
+    "tsdf_server_session", "tsdf_server_batch", "tsdf_server_load", "tsdf_server_replay",
 )
+REPLAY_SERVED, REPLAY_PLAIN = 0, 1
 BATCH_NO_GRAPH = 0x1
 BATCH_MAX_ITEMS = 65536
 
@@ -79,6 +85,16 @@ class FuseItemC(C.Structure):
 class BatchConfigC(C.Structure):
     _fields_ = [("tile_width", C.c_uint32), ("pixels_per_thread", C.c_uint32),
                 ("acc_blocks", C.c_uint32), ("groups_per_cu", C.c_uint32)]
+
+
+class ServerParamsC(C.Structure):
+    _fields_ = [("max_sessions", C.c_uint32), ("max_batch", C.c_uint32),
+                ("max_inflight", C.c_uint32), ("max_queue", C.c_uint32)]
+
+
+class RequestC(C.Structure):
+    _fields_ = [("arrival_ns", C.c_uint64), ("session", C.c_uint32), ("reserved", C.c_uint32),
+                ("depth_dev", C.c_void_p), ("camera", CameraC)]
 
 
 class TsdfError(RuntimeError):
@@ -138,6 +154,45 @@ def lib() -> C.CDLL:
         L.tsdf_batch_candidates.restype = I
         L.tsdf_batch_candidates.argtypes = [P, U32, C.POINTER(BatchConfigC), C.POINTER(C.c_double),
                                             C.POINTER(U32)]
+        L.tsdf_region_create.restype = I
+        L.tsdf_region_create.argtypes = [P, C.c_uint64, C.POINTER(P)]
+        L.tsdf_region_destroy.restype = I
+        L.tsdf_region_destroy.argtypes = [P]
+        L.tsdf_region_alloc.restype = I
+        L.tsdf_region_alloc.argtypes = [P, C.c_uint64, C.POINTER(P)]
+        L.tsdf_region_free.restype = I
+        L.tsdf_region_free.argtypes = [P, P]
+        L.tsdf_region_usage.restype = I
+        L.tsdf_region_usage.argtypes = [P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
+                                        C.POINTER(C.c_uint64), C.POINTER(U32)]
+        L.tsdf_server_workspace_bytes.restype = C.c_size_t
+        L.tsdf_server_workspace_bytes.argtypes = [C.POINTER(ServerParamsC)]
+        L.tsdf_server_create.restype = I
+        L.tsdf_server_create.argtypes = [C.POINTER(ServerParamsC), P, C.c_size_t, P, C.c_uint64, P,
+                                         C.POINTER(P)]
+        L.tsdf_server_destroy.restype = I
+        L.tsdf_server_destroy.argtypes = [P]
+        L.tsdf_server_open.restype = I
+        L.tsdf_server_open.argtypes = [P, C.POINTER(VolumeParams), C.POINTER(U32)]
+        L.tsdf_server_close.restype = I
+        L.tsdf_server_close.argtypes = [P, U32]
+        L.tsdf_server_submit.restype = I
+        L.tsdf_server_submit.argtypes = [P, U32, P, C.POINTER(CameraC), C.c_uint64]
+        L.tsdf_server_step.restype = I
+        L.tsdf_server_step.argtypes = [P, C.POINTER(U32)]
+        L.tsdf_server_completions.restype = I
+        L.tsdf_server_completions.argtypes = [P, C.POINTER(C.c_uint64), C.POINTER(C.c_int32), U32,
+                                              C.POINTER(U32)]
+        L.tsdf_server_session.restype = I
+        L.tsdf_server_session.argtypes = [P, U32, C.POINTER(P), C.POINTER(C.c_int32)]
+        L.tsdf_server_batch.restype = I
+        L.tsdf_server_batch.argtypes = [P, C.POINTER(P)]
+        L.tsdf_server_load.restype = I
+        L.tsdf_server_load.argtypes = [P, C.POINTER(U32), C.POINTER(U32), C.POINTER(U32),
+                                       C.POINTER(U32), C.POINTER(C.c_uint64)]
+        L.tsdf_server_replay.restype = I
+        L.tsdf_server_replay.argtypes = [P, C.POINTER(RequestC), U32, U32, C.POINTER(C.c_double),
+                                         C.POINTER(C.c_double)]
         L.tsdf_batch_fuse.restype = I
         L.tsdf_batch_fuse.argtypes = [P, C.POINTER(FuseItemC), U32, U32, P]
         _lib = L
@@ -200,7 +255,40 @@ class Extracted:
     weight: torch.Tensor   # (n, 512) float32
 
 
-class Volume:
+class _VolumeCalls:
+    """Status and extraction calls shared by every volume handle (needs
+    ``_h`` and ``device``)."""
+
+    def stats(self, stream=None) -> Stats:
+        s = StatsC()
+        st = lib().tsdf_query_status(self._h, _stream_ptr(stream), C.byref(s))
+        if st == ERR_HIP or st == ERR_INVALID_ARGUMENT:
+            raise TsdfError(st, "tsdf_query_status")
+        return Stats(s.points_valid, s.pairs, s.pairs_dropped, s.coord_out_of_range, s.blocks_total,
+                     s.keys_pool_overflow, s.table_full_events, s.max_probe, s.lookup_misses,
+                     s.status_bits, s.frames, st)
+
+    def extract(self, stream=None) -> Extracted:
+        n = C.c_uint32(0)
+        L = lib()
+        st = L.tsdf_extract_blocks(self._h, _stream_ptr(stream), 0, None, None, None, C.byref(n))
+        if st not in (OK, ERR_BUFFER_TOO_SMALL):
+            raise TsdfError(st, "tsdf_extract_blocks")
+        nb = n.value
+        dev = self.device
+        keys = torch.empty(nb, dtype=torch.int64, device=dev)
+        tsdf = torch.empty((nb, BLOCK_VOXELS), dtype=torch.float32, device=dev)
+        weight = torch.empty((nb, BLOCK_VOXELS), dtype=torch.float32, device=dev)
+        st = L.tsdf_extract_blocks(self._h, _stream_ptr(stream), nb, C.c_void_p(keys.data_ptr()),
+                                   C.c_void_p(tsdf.data_ptr()), C.c_void_p(weight.data_ptr()),
+                                   C.byref(n))
+        if st != OK:
+            raise TsdfError(st, "tsdf_extract_blocks")
+        return Extracted(keys, tsdf, weight)
+
+
+
+class Volume(_VolumeCalls):
     """One resident TSDF volume in a device arena owned by this object."""
 
     def __init__(self, voxel_size: float, trunc: float, table_capacity: int, pool_capacity: int,
@@ -211,6 +299,7 @@ class Volume:
             raise TsdfError(ERR_INVALID_ARGUMENT, "volume parameters")
         self.layout = layout(self.params)
         self.arena = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.device = self.arena.device
         self._h = C.c_void_p()
         st = lib().tsdf_create_volume(C.byref(self.params), C.c_void_p(self.arena.data_ptr()),
                                       nbytes, _stream_ptr(stream), C.byref(self._h))
@@ -274,33 +363,6 @@ class Volume:
         st = lib().tsdf_insert_blocks(self._h, C.c_void_p(coords.data_ptr()), n, _stream_ptr(stream))
         if st != OK:
             raise TsdfError(st, "tsdf_insert_blocks")
-
-    def stats(self, stream=None) -> Stats:
-        s = StatsC()
-        st = lib().tsdf_query_status(self._h, _stream_ptr(stream), C.byref(s))
-        if st == ERR_HIP or st == ERR_INVALID_ARGUMENT:
-            raise TsdfError(st, "tsdf_query_status")
-        return Stats(s.points_valid, s.pairs, s.pairs_dropped, s.coord_out_of_range, s.blocks_total,
-                     s.keys_pool_overflow, s.table_full_events, s.max_probe, s.lookup_misses,
-                     s.status_bits, s.frames, st)
-
-    def extract(self, stream=None) -> Extracted:
-        n = C.c_uint32(0)
-        L = lib()
-        st = L.tsdf_extract_blocks(self._h, _stream_ptr(stream), 0, None, None, None, C.byref(n))
-        if st not in (OK, ERR_BUFFER_TOO_SMALL):
-            raise TsdfError(st, "tsdf_extract_blocks")
-        nb = n.value
-        dev = self.arena.device
-        keys = torch.empty(nb, dtype=torch.int64, device=dev)
-        tsdf = torch.empty((nb, BLOCK_VOXELS), dtype=torch.float32, device=dev)
-        weight = torch.empty((nb, BLOCK_VOXELS), dtype=torch.float32, device=dev)
-        st = L.tsdf_extract_blocks(self._h, _stream_ptr(stream), nb, C.c_void_p(keys.data_ptr()),
-                                   C.c_void_p(tsdf.data_ptr()), C.c_void_p(weight.data_ptr()),
-                                   C.byref(n))
-        if st != OK:
-            raise TsdfError(st, "tsdf_extract_blocks")
-        return Extracted(keys, tsdf, weight)
 
     # Zero-copy views of the carved regions (for invariant checks and consumers).
     def table_view(self) -> torch.Tensor:
@@ -422,3 +484,192 @@ class Batch:
         st = lib().tsdf_batch_fuse(self._h, self._items, n, flags, _stream_ptr(stream))
         if st != OK:
             raise TsdfError(st, "tsdf_batch_fuse")
+
+
+class Region:
+    """Host bookkeeping of a device region (``tsdf_region_*``); no GPU needed."""
+
+    def __init__(self, base: int, nbytes: int):
+        self._h = C.c_void_p()
+        st = lib().tsdf_region_create(C.c_void_p(base), nbytes, C.byref(self._h))
+        if st != OK:
+            raise TsdfError(st, "tsdf_region_create")
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) and self._h.value:
+            lib().tsdf_region_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def alloc(self, nbytes: int) -> Optional[int]:
+        """Device address of a new range, or None when nothing fits."""
+        p = C.c_void_p()
+        st = lib().tsdf_region_alloc(self._h, nbytes, C.byref(p))
+        if st == ERR_BUDGET:
+            return None
+        if st != OK:
+            raise TsdfError(st, "tsdf_region_alloc")
+        return p.value
+
+    def free(self, ptr: int) -> None:
+        st = lib().tsdf_region_free(self._h, C.c_void_p(ptr))
+        if st != OK:
+            raise TsdfError(st, "tsdf_region_free")
+
+    def usage(self) -> tuple[int, int, int, int]:
+        """(capacity, used, largest free range, live ranges)."""
+        cap, used, big, n = C.c_uint64(), C.c_uint64(), C.c_uint64(), C.c_uint32()
+        st = lib().tsdf_region_usage(self._h, C.byref(cap), C.byref(used), C.byref(big), C.byref(n))
+        if st != OK:
+            raise TsdfError(st, "tsdf_region_usage")
+        return cap.value, used.value, big.value, n.value
+
+
+class SessionVolume(_VolumeCalls):
+    """A session's volume as held by a server: status and extraction on the
+    server's stream (the arena belongs to the server's budget)."""
+
+    def __init__(self, handle: int, params: VolumeParams, stream: torch.cuda.Stream,
+                 device: torch.device):
+        self._h = C.c_void_p(handle)
+        self.params = params
+        self.layout = layout(params)
+        self.device = device
+        self._stream = stream
+
+    @property
+    def handle(self) -> C.c_void_p:
+        return self._h
+
+    def stats(self, stream=None) -> Stats:
+        return super().stats(self._stream if stream is None else stream)
+
+    def extract(self, stream=None) -> Extracted:
+        out = super().extract(self._stream if stream is None else stream)
+        torch.cuda.current_stream(self.device).wait_stream(self._stream)
+        return out
+
+
+class Server:
+    """Serving loop (``tsdf_server_*``): sessions carved from one device
+    budget, frames batched across sessions, on a stream of its own."""
+
+    def __init__(self, budget_bytes: int, max_sessions: int = 256, max_batch: int = 256,
+                 max_inflight: int = 1, max_queue: int = 4096, device="cuda"):
+        self.params = ServerParamsC(max_sessions, max_batch, max_inflight, max_queue)
+        L = lib()
+        ws = int(L.tsdf_server_workspace_bytes(C.byref(self.params)))
+        if ws == 0:
+            raise TsdfError(ERR_INVALID_ARGUMENT, "tsdf_server_workspace_bytes")
+        self.device = torch.device(device)
+        self.workspace = torch.empty(ws, dtype=torch.uint8, device=self.device)
+        self.region = torch.empty(budget_bytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.Stream(device=self.device)
+        self._h = C.c_void_p()
+        st = L.tsdf_server_create(C.byref(self.params), C.c_void_p(self.workspace.data_ptr()), ws,
+                                  C.c_void_p(self.region.data_ptr()), budget_bytes,
+                                  C.c_void_p(self.stream.cuda_stream), C.byref(self._h))
+        if st != OK:
+            raise TsdfError(st, "tsdf_server_create")
+        self._vol_params = {}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) and self._h.value:
+            lib().tsdf_server_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def open(self, voxel_size: float, trunc: float, table_capacity: int,
+             pool_capacity: int) -> Optional[int]:
+        """A new session id, or None when the budget has no room."""
+        p = volume_params(voxel_size, trunc, table_capacity, pool_capacity)
+        sid = C.c_uint32()
+        st = lib().tsdf_server_open(self._h, C.byref(p), C.byref(sid))
+        if st == ERR_BUDGET:
+            return None
+        if st != OK:
+            raise TsdfError(st, "tsdf_server_open")
+        self._vol_params[sid.value] = p
+        return sid.value
+
+    def close_session(self, sid: int) -> None:
+        st = lib().tsdf_server_close(self._h, sid)
+        if st != OK:
+            raise TsdfError(st, "tsdf_server_close")
+        self._vol_params.pop(sid, None)
+
+    def submit(self, sid: int, depth: torch.Tensor, cam, tag: int) -> int:
+        """Queue a frame; returns the status (OK, ERR_BUDGET or a failure)."""
+        c = cam if isinstance(cam, CameraC) else camera_struct(cam)
+        if depth.numel() != c.width * c.height:
+            raise ValueError("depth size does not match the camera")
+        return lib().tsdf_server_submit(self._h, sid, C.c_void_p(depth.data_ptr()), C.byref(c), tag)
+
+    def step(self) -> int:
+        n = C.c_uint32()
+        st = lib().tsdf_server_step(self._h, C.byref(n))
+        if st != OK:
+            raise TsdfError(st, "tsdf_server_step")
+        return n.value
+
+    def completions(self, max_n: int = 1024) -> list[tuple[int, int]]:
+        tags = (C.c_uint64 * max_n)()
+        sts = (C.c_int32 * max_n)()
+        n = C.c_uint32()
+        st = lib().tsdf_server_completions(self._h, tags, sts, max_n, C.byref(n))
+        if st != OK:
+            raise TsdfError(st, "tsdf_server_completions")
+        return [(tags[i], sts[i]) for i in range(n.value)]
+
+    def session(self, sid: int) -> tuple[SessionVolume, int]:
+        h = C.c_void_p()
+        fail = C.c_int32()
+        st = lib().tsdf_server_session(self._h, sid, C.byref(h), C.byref(fail))
+        if st != OK:
+            raise TsdfError(st, "tsdf_server_session")
+        return SessionVolume(h.value, self._vol_params[sid], self.stream, self.device), fail.value
+
+    def batch_config(self, cfg: BatchConfig) -> None:
+        b = C.c_void_p()
+        lib().tsdf_server_batch(self._h, C.byref(b))
+        c = BatchConfigC(cfg.tile_width, cfg.pixels_per_thread, cfg.acc_blocks, cfg.groups_per_cu)
+        st = lib().tsdf_batch_set_config(b, C.byref(c))
+        if st != OK:
+            raise TsdfError(st, "tsdf_batch_set_config")
+
+    def load(self) -> dict:
+        q, f, l, s, u = C.c_uint32(), C.c_uint32(), C.c_uint32(), C.c_uint32(), C.c_uint64()
+        st = lib().tsdf_server_load(self._h, C.byref(q), C.byref(f), C.byref(l), C.byref(s),
+                                    C.byref(u))
+        if st != OK:
+            raise TsdfError(st, "tsdf_server_load")
+        return {"queued": q.value, "inflight_frames": f.value, "inflight_launches": l.value,
+                "sessions": s.value, "budget_used": u.value}
+
+    def replay(self, arrivals_ns: Sequence[int], sessions: Sequence[int],
+               depths: Sequence[torch.Tensor], cams, mode: int = REPLAY_SERVED):
+        """Real-time replay of an arrival trace: (latency_ns array, elapsed_ns)."""
+        n = len(arrivals_ns)
+        reqs = (RequestC * max(n, 1))()
+        for i in range(n):
+            c = cams[i] if isinstance(cams[i], CameraC) else camera_struct(cams[i])
+            reqs[i].arrival_ns = int(arrivals_ns[i])
+            reqs[i].session = int(sessions[i])
+            reqs[i].depth_dev = depths[i].data_ptr()
+            reqs[i].camera = c
+        lat = (C.c_double * max(n, 1))()
+        el = C.c_double()
+        st = lib().tsdf_server_replay(self._h, reqs, n, mode, lat, C.byref(el))
+        if st != OK:
+            raise TsdfError(st, "tsdf_server_replay")
+        return np.array(lat[:n]), el.value

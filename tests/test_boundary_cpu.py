@@ -92,7 +92,7 @@ def test_null_handles_are_rejected():
 
 
 def test_status_strings():
-    for s in range(8):
+    for s in range(9):
         assert T.status_str(s) and T.status_str(s) != "unknown status"
     assert T.status_str(99) == "unknown status"
 
