@@ -385,7 +385,8 @@ def bench_serve(args) -> int:
         lat, elapsed = server.replay(w.arrival_ns, sess, depths, cams, mode)
         _, cap_elapsed = server.replay(np.zeros(n, dtype=np.int64), sess, depths, cams, mode)
         stats = [server.session(i)[0].stats() for i in ids]
-        fails = [i for i in ids if server.session(i)[1] != T.OK]
+        fails = [k for k, i in enumerate(ids)
+                 if server.session(i)[1] != T.OK or stats[k].status != T.OK]
         used = server.load()["budget_used"]
         server.close()
         del server
@@ -398,6 +399,11 @@ def bench_serve(args) -> int:
     lat_p, el_p, cap_p, st_p, fail_p, _ = run(T.REPLAY_PLAIN, int(need * 1.02) + (64 << 20))
     log(f"[bench] plain: p50 {np.percentile(lat_p, 50) / 1e3:.1f} us, "
         f"p99 {np.percentile(lat_p, 99) / 1e3:.1f} us; capacity {points / cap_p * 1e9:.3e} points/s")
+    if fail_s or fail_p:
+        bad = sorted(set(fail_s) | set(fail_p))
+        print(f"gate failed: sessions whose pool or table ran out (served {fail_s}, plain "
+              f"{fail_p}); status bits {[st_s[i].status_bits for i in bad]}", file=sys.stderr)
+        return 1
     for i, (a, b) in enumerate(zip(st_s, st_p)):
         for f in ("points_valid", "pairs", "pairs_dropped", "blocks_total", "frames"):
             if getattr(a, f) != getattr(b, f):

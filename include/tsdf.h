@@ -326,12 +326,14 @@ tsdf_status tsdf_region_usage(const tsdf_region* region, uint64_t* capacity, uin
  * volume carved from a device budget, and fuses the frames submitted to them
  * with continuous batching: each launch takes every queued frame (up to
  * max_batch, first come first served, any mix of sessions) through the batch
- * path above, and a new launch starts whenever fewer than max_inflight are
- * running.  A session's result is the one it would have alone (the batch
- * path's guarantee).  After each launch a small kernel copies every
- * session's sticky status to pinned host memory; a session whose pool or
- * table ran out is marked failed, and its later frames are refused instead of
- * probing a full table, without touching the other sessions.
+ * path above (a lone frame through tsdf_fuse_frame), and a new launch starts
+ * whenever fewer than max_inflight are running.  A session's result is the
+ * one it would have alone (the batch path's guarantee).  Behind each launch a
+ * small kernel copies every session's sticky status to pinned host memory;
+ * once that copy has finished, a session whose pool or table ran out is
+ * marked failed, and its later frames are refused instead of probing a full
+ * table, without touching the other sessions.  Frames are handed back when
+ * their launch finishes, ahead of the status copy.
  *
  * The server is driven from one host thread: tsdf_server_submit queues,
  * tsdf_server_step retires finished launches and starts new ones, and
@@ -414,7 +416,9 @@ tsdf_status tsdf_server_load(tsdf_server* server, uint32_t* queued, uint32_t* in
  *   TSDF_REPLAY_PLAIN   one tsdf_fuse_frame per request, launched when it
  *                       arrives, on the server's stream (the comparison)
  * latency_ns[i] gets request i's latency (-1 if it was refused);
- * *elapsed_ns the time from the start to the last completion. */
+ * *elapsed_ns the time from the start to the last completion.  The server
+ * must have no queued, running or uncollected frames when the replay starts
+ * (TSDF_ERR_INVALID_ARGUMENT otherwise). */
 typedef struct tsdf_request {
   uint64_t arrival_ns;
   uint32_t session;

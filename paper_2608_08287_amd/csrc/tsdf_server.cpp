@@ -39,9 +39,14 @@ struct Pending {
   uint64_t tag;
 };
 
+// One launch: its frames complete at `done`; the status copy behind it
+// completes at `gathered`.  Frames are handed back as soon as `done` has
+// passed, so the status copy stays off the frames' latency.
 struct Launch {
   uint64_t seq;
   hipEvent_t done;
+  hipEvent_t gathered;
+  bool frames_retired = false;
   std::vector<uint32_t> sessions;  // one entry per frame
   std::vector<uint64_t> tags;
 };
@@ -77,6 +82,7 @@ struct tsdf_server {
   uint32_t n_open = 0;
   std::deque<Pending> queue;
   std::deque<Launch> inflight;
+  uint32_t running = 0;  // launches whose frames have not completed
   std::vector<hipEvent_t> spare_events;
   std::deque<std::pair<uint64_t, int32_t>> done;
   uint64_t next_seq = 0;
@@ -101,12 +107,17 @@ void release_session(tsdf_server* s, uint32_t id) {
   --s->n_open;
 }
 
-// Move finished launches' frames to the completion list and read the status
-// words their gather wrote.  Non-blocking unless `wait_all`.
+hipError_t poll(hipEvent_t ev, bool wait) {
+  return wait ? hipEventSynchronize(ev) : hipEventQuery(ev);
+}
+
+// Hand back the frames of launches that have finished, and read the status
+// words of those whose status copy has finished.  Launches retire in order
+// (one stream).  Non-blocking unless `wait_all`.
 tsdf_status retire(tsdf_server* s, bool wait_all) {
-  while (!s->inflight.empty()) {
-    Launch& L = s->inflight.front();
-    hipError_t e = wait_all ? hipEventSynchronize(L.done) : hipEventQuery(L.done);
+  for (Launch& L : s->inflight) {
+    if (L.frames_retired) continue;
+    const hipError_t e = poll(L.done, wait_all);
     if (e == hipErrorNotReady) break;
     if (e != hipSuccess) return TSDF_ERR_HIP;
     for (size_t i = 0; i < L.tags.size(); ++i) {
@@ -114,6 +125,14 @@ tsdf_status retire(tsdf_server* s, bool wait_all) {
       --s->sessions[L.sessions[i]].inflight;
     }
     s->inflight_frames -= (uint32_t)L.tags.size();
+    L.frames_retired = true;
+    --s->running;
+  }
+  while (!s->inflight.empty() && s->inflight.front().frames_retired) {
+    Launch& L = s->inflight.front();
+    const hipError_t e = poll(L.gathered, wait_all);
+    if (e == hipErrorNotReady) break;
+    if (e != hipSuccess) return TSDF_ERR_HIP;
     // statuses copied behind this launch are current for sessions opened
     // before it was made
     for (uint32_t id = 0; id < s->p.max_sessions; ++id) {
@@ -122,9 +141,20 @@ tsdf_status retire(tsdf_server* s, bool wait_all) {
       ss.failure = failure_of(__atomic_load_n(&s->status_host[id], __ATOMIC_ACQUIRE));
     }
     s->spare_events.push_back(L.done);
+    s->spare_events.push_back(L.gathered);
     s->inflight.pop_front();
   }
   return TSDF_OK;
+}
+
+bool take_event(tsdf_server* s, hipEvent_t* ev) {
+  if (s->spare_events.empty()) {
+    if (hipEventCreateWithFlags(ev, hipEventDisableTiming) != hipSuccess) return false;
+    return true;
+  }
+  *ev = s->spare_events.back();
+  s->spare_events.pop_back();
+  return true;
 }
 
 tsdf_status launch_one(tsdf_server* s, uint32_t* launched) {
@@ -143,26 +173,32 @@ tsdf_status launch_one(tsdf_server* s, uint32_t* launched) {
     L.tags.push_back(q.tag);
   }
   if (s->items.empty()) return TSDF_OK;
-  if (s->spare_events.empty()) {
-    hipEvent_t ev;
-    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return TSDF_ERR_HIP;
-    s->spare_events.push_back(ev);
+  if (!take_event(s, &L.done)) return TSDF_ERR_HIP;
+  if (!take_event(s, &L.gathered)) {
+    s->spare_events.push_back(L.done);
+    return TSDF_ERR_HIP;
   }
-  L.done = s->spare_events.back();
-  s->spare_events.pop_back();
-  tsdf_status st = tsdf_batch_fuse(s->batch, s->items.data(), (uint32_t)s->items.size(), 0,
-                                   s->stream);
+  // A lone frame takes the one-volume kernel: no work list to copy, no tile
+  // search.  Several frames share one persistent launch.
+  const tsdf_fuse_item& one = s->items[0];
+  tsdf_status st = s->items.size() == 1
+                       ? tsdf_fuse_frame(one.volume, one.depth_dev, &one.camera, s->stream)
+                       : tsdf_batch_fuse(s->batch, s->items.data(), (uint32_t)s->items.size(), 0,
+                                         s->stream);
+  if (st == TSDF_OK) st = hip_status(hipEventRecord(L.done, s->stream));
   if (st == TSDF_OK)
     st = hip_status(tsdf::launch_gather_status(s->ctr_dev, s->p.max_sessions, s->status_dev,
                                                s->stream));
-  if (st == TSDF_OK) st = hip_status(hipEventRecord(L.done, s->stream));
+  if (st == TSDF_OK) st = hip_status(hipEventRecord(L.gathered, s->stream));
   if (st != TSDF_OK) {
     s->spare_events.push_back(L.done);
+    s->spare_events.push_back(L.gathered);
     return st;
   }
   L.seq = s->next_seq++;
   for (uint32_t id : L.sessions) ++s->sessions[id].inflight;
   s->inflight_frames += (uint32_t)L.tags.size();
+  ++s->running;
   if (launched) *launched = (uint32_t)L.tags.size();
   s->inflight.push_back(std::move(L));
   return TSDF_OK;
@@ -172,7 +208,10 @@ void free_server(tsdf_server* s) {
   if (s->stream) (void)hipStreamSynchronize(s->stream);
   for (uint32_t id = 0; id < s->sessions.size(); ++id)
     if (s->sessions[id].open) release_session(s, id);
-  for (Launch& L : s->inflight) s->spare_events.push_back(L.done);
+  for (Launch& L : s->inflight) {
+    s->spare_events.push_back(L.done);
+    s->spare_events.push_back(L.gathered);
+  }
   for (hipEvent_t ev : s->spare_events) (void)hipEventDestroy(ev);
   if (s->batch) (void)tsdf_batch_destroy(s->batch);
   if (s->region) (void)tsdf_region_destroy(s->region);
@@ -302,7 +341,7 @@ tsdf_status tsdf_server_step(tsdf_server* s, uint32_t* launched) {
   if (launched) *launched = 0;
   tsdf_status st = retire(s, false);
   if (st != TSDF_OK) return st;
-  if (s->inflight.size() < s->p.max_inflight && !s->queue.empty()) st = launch_one(s, launched);
+  if (s->running < s->p.max_inflight && !s->queue.empty()) st = launch_one(s, launched);
   return st;
 }
 
@@ -341,7 +380,7 @@ tsdf_status tsdf_server_load(tsdf_server* s, uint32_t* queued, uint32_t* infligh
   if (!s) return TSDF_ERR_INVALID_ARGUMENT;
   if (queued) *queued = (uint32_t)s->queue.size();
   if (inflight_frames) *inflight_frames = s->inflight_frames;
-  if (inflight_launches) *inflight_launches = (uint32_t)s->inflight.size();
+  if (inflight_launches) *inflight_launches = s->running;
   if (sessions) *sessions = s->n_open;
   if (budget_used) return tsdf_region_usage(s->region, nullptr, budget_used, nullptr, nullptr);
   return TSDF_OK;
@@ -357,8 +396,11 @@ tsdf_status tsdf_server_replay(tsdf_server* s, const tsdf_request* reqs, uint32_
       return TSDF_ERR_INVALID_ARGUMENT;
     if (!valid_camera(&reqs[i].camera)) return TSDF_ERR_INVALID_ARGUMENT;
   }
-  if (!s->queue.empty() || !s->inflight.empty() || !s->done.empty())
-    return TSDF_ERR_INVALID_ARGUMENT;  // the replay owns the server while it runs
+  // the replay owns the server while it runs: nothing may be queued or
+  // waiting to be collected; launches still finishing are waited for
+  if (!s->queue.empty() || s->running > 0 || !s->done.empty()) return TSDF_ERR_INVALID_ARGUMENT;
+  const tsdf_status pre = retire(s, true);
+  if (pre != TSDF_OK) return pre;
   for (uint32_t i = 0; i < n; ++i) latency_ns[i] = -1.0;
   const double t0 = now_ns();
   double last = t0;

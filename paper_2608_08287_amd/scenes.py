@@ -378,8 +378,10 @@ class ServingWorkload:
 
     From ``default_rng(seed)``: per session a frame size uniform over
     ``sizes``, a voxel edge uniform over 5..10 mm and a pool exponent e
-    uniform over ``log2_pools[0]..log2_pools[1]``; the exponents are dealt in
-    the reverse order of the voxel edges, as in ``MultiVolumeWorkload``.  Pool
+    uniform over ``log2_pools[0]..log2_pools[1]``; the exponents are dealt
+    largest first to the sessions ordered by voxel edge, then by frame area
+    from the largest (the finest voxels and, among equal voxels, the largest
+    frames touch the most blocks), which keeps every marginal uniform.  Pool
     2^e blocks, table twice the pool (the paper's sizing), truncation 4 voxels,
     an own room scene and orbit start.  Arrivals form one Poisson process of
     ``rate`` frames/s (exponential gaps), each arrival going to a session drawn
@@ -397,8 +399,9 @@ class ServingWorkload:
         exps = rng.integers(log2_pools[0], log2_pools[1] + 1, size=n_sessions)
         scene_seeds = rng.integers(1, 1 << 30, size=n_sessions)
         offsets = rng.integers(0, n_orbit, size=n_sessions)
+        area = np.array([sizes[int(k)][0] * sizes[int(k)][1] for k in size_idx])
         exp_of = np.empty(n_sessions, dtype=np.int64)
-        exp_of[np.argsort(voxel_mm, kind="stable")] = np.sort(exps)[::-1]
+        exp_of[np.lexsort((-area, voxel_mm))] = np.sort(exps)[::-1]
         self.specs: List[VolumeSpec] = []
         for i in range(n_sessions):
             w, h = sizes[int(size_idx[i])]

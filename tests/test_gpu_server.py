@@ -173,6 +173,9 @@ def test_a_failing_session_is_isolated():
     weak_frames = [(torch.from_numpy(w.depth(0, k)).cuda(), w.camera(0, k)) for k in range(3)]
     assert server.submit(weak, *weak_frames[0], 10_000) == T.OK
     drain(server, 1)
+    t0 = time.monotonic()
+    while server.session(weak)[1] == T.OK and time.monotonic() - t0 < 30:
+        server.step()  # the status copy behind the launch lands after the frame
     assert server.session(weak)[1] == T.ERR_POOL_EXHAUSTED
     assert server.submit(weak, *weak_frames[1], 10_001) == T.ERR_POOL_EXHAUSTED
     for j, (si, d, c) in enumerate(zip(w.session_of, depths, cams)):
