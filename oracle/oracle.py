@@ -49,6 +49,9 @@ def lib():
         L.ora_home_slot.argtypes = [U64, U32]
         L.ora_probe_model.restype = U64
         L.ora_probe_model.argtypes = [P, U64, U32, P, P, P]
+        L.ora_set_block.argtypes = [P, U64, P, P]
+        L.ora_extract_mesh.restype = U64
+        L.ora_extract_mesh.argtypes = [P, P, P, P, U64]
         _lib = L
     return _lib
 
@@ -61,6 +64,13 @@ def _cam_arrays(cam):
     intr = np.asarray([cam.fx, cam.fy, cam.cx, cam.cy], dtype=np.float32)
     pose = np.ascontiguousarray(np.asarray(cam.pose, dtype=np.float32).reshape(3, 4))
     return intr, pose
+
+
+@dataclass
+class OracleMesh:
+    ids: np.ndarray    # (T, 2) uint64: block key, cube << 4 | tetrahedron << 1 | triangle
+    verts: np.ndarray  # (T, 3, 3) float64 vertex positions (metres)
+    edges: np.ndarray  # (T, 3, 2, 3) int64: per vertex, the grid edge's two corners
 
 
 @dataclass
@@ -106,6 +116,22 @@ class OracleVolume:
         names = ["points_valid", "pairs", "pairs_dropped", "coord_out_of_range", "blocks",
                  "pool_overflow_keys", "frames", "pool_capacity"]
         return {n: int(v) for n, v in zip(names, out)}
+
+    def set_block(self, key: int, sums: np.ndarray, weights: np.ndarray) -> None:
+        """Replace (or create) one block's 512 sums and weights (x fastest)."""
+        sm = np.ascontiguousarray(sums, dtype=np.float64).reshape(512)
+        w = np.ascontiguousarray(weights, dtype=np.uint32).reshape(512)
+        lib().ora_set_block(self._h, int(key), _ptr(sm), _ptr(w))
+
+    def mesh(self) -> "OracleMesh":
+        """Marching-tetrahedra surface of the volume (see ora_extract_mesh)."""
+        L = lib()
+        n = int(L.ora_extract_mesh(self._h, None, None, None, 0))
+        ids = np.zeros((n, 2), dtype=np.uint64)
+        verts = np.zeros((n, 3, 3), dtype=np.float64)
+        edges = np.zeros((n, 3, 2, 3), dtype=np.int64)
+        L.ora_extract_mesh(self._h, _ptr(ids), _ptr(verts), _ptr(edges), n)
+        return OracleMesh(ids, verts, edges)
 
     def result(self) -> OracleResult:
         L = lib()

@@ -243,6 +243,147 @@ uint32_t home_slot(uint64_t key, uint32_t C) {
   return uint32_t((hi * uint64_t(C)) >> 32);
 }
 
+// ---------------------------------------------------------------------------
+// Surface extraction: marching tetrahedra over the voxel centres.
+//
+// The paper extracts the zero crossing of the fused field with marching
+// tetrahedra (Section 3, "What is excluded, and why") and checks the result on
+// a sphere of known radius and by vertex distances between runs (Section 5,
+// "Correctness").  It does not spell the method out; the readings:
+//   - samples are voxel centres ((i + 1/2) v per axis), values the mean TSDF
+//     sum / weight;
+//   - a cube of 8 neighbouring centres is used only when all 8 voxels have a
+//     weight, and it is skipped when its values change sign while some corner
+//     has |value| >= (1 - 2^-10) tau: a jump across the truncation limit at an
+//     occlusion edge, not a surface;
+//   - the cube is cut into the 6 tetrahedra that share its diagonal from
+//     corner 0 to corner 7 (corner c has offset (c & 1, c >> 1 & 1, c >> 2));
+//   - a corner is inside when its value is < 0; a tetrahedron with one or three
+//     inside corners gives one triangle, with two it gives two;
+//   - a vertex lies on an edge with one inside and one outside corner, at
+//     t = f_a / (f_a - f_b) from corner a, where a is the edge's corner that
+//     comes first in (x, y, z) lexicographic grid order;
+//   - each triangle is wound so that its normal points to the outside corners.
+// Triangle identity: (block key, cube << 4 | tetrahedron << 1 | triangle).
+// ---------------------------------------------------------------------------
+
+struct MeshTri {
+  uint64_t key;
+  uint32_t code;         // cube << 4 | tet << 1 | sub
+  double p[3][3];        // vertices
+  int64_t edge[3][2][3]; // per vertex: the edge's two corners (global voxel index)
+};
+
+const int kTet[6][4] = {{0, 1, 3, 7}, {0, 3, 2, 7}, {0, 2, 6, 7},
+                        {0, 6, 4, 7}, {0, 4, 5, 7}, {0, 5, 1, 7}};
+
+bool lex_less(const int64_t* a, const int64_t* b) {
+  if (a[0] != b[0]) return a[0] < b[0];
+  if (a[1] != b[1]) return a[1] < b[1];
+  return a[2] < b[2];
+}
+
+// Mean and presence of the voxel at global index g (per axis).
+bool voxel_value(const Volume& vol, const int64_t* g, double* f) {
+  const uint64_t key = pack_block_key(block_of(g[0]), block_of(g[1]), block_of(g[2]));
+  auto it = vol.blocks.find(key);
+  if (it == vol.blocks.end()) return false;
+  const int loc = int((offset_in_block(g[2]) * 8 + offset_in_block(g[1])) * 8 + offset_in_block(g[0]));
+  const uint32_t w = it->second.weight[loc];
+  if (w == 0) return false;
+  *f = it->second.sum[loc] / double(w);
+  return true;
+}
+
+void mesh_cube(const Volume& vol, uint64_t key, int64_t bx, int64_t by, int64_t bz, int loc,
+               std::vector<MeshTri>& out) {
+  const int lx = loc & 7, ly = (loc >> 3) & 7, lz = loc >> 6;
+  int64_t corner[8][3];
+  double f[8];
+  bool any_in = false, any_out = false, truncated = false;
+  const double tau_limit = (1.0 - 1.0 / 1024.0) * double(vol.p.trunc);
+  for (int c = 0; c < 8; ++c) {
+    corner[c][0] = bx * 8 + lx + (c & 1);
+    corner[c][1] = by * 8 + ly + ((c >> 1) & 1);
+    corner[c][2] = bz * 8 + lz + ((c >> 2) & 1);
+    if (!voxel_value(vol, corner[c], &f[c])) return;
+    (f[c] < 0.0 ? any_in : any_out) = true;
+    if (std::fabs(f[c]) >= tau_limit) truncated = true;
+  }
+  if (!(any_in && any_out) || truncated) return;
+  const double v = double(vol.p.v);
+  for (int t = 0; t < 6; ++t) {
+    const int* q = kTet[t];
+    int ins[4], outs[4], ni = 0, no = 0;
+    for (int k = 0; k < 4; ++k) (f[q[k]] < 0.0 ? ins[ni++] : outs[no++]) = q[k];
+    if (ni == 0 || no == 0) continue;
+    // the crossing edges, as (inside corner, outside corner)
+    int e[4][2];
+    int ne = 0;
+    if (ni == 1) {
+      for (int k = 0; k < 3; ++k) e[ne][0] = ins[0], e[ne++][1] = outs[k];
+    } else if (ni == 3) {
+      for (int k = 0; k < 3; ++k) e[ne][0] = ins[k], e[ne++][1] = outs[0];
+    } else {  // two and two: the quad i0-o0, i0-o1, i1-o1, i1-o0
+      e[0][0] = ins[0], e[0][1] = outs[0];
+      e[1][0] = ins[0], e[1][1] = outs[1];
+      e[2][0] = ins[1], e[2][1] = outs[1];
+      e[3][0] = ins[1], e[3][1] = outs[0];
+      ne = 4;
+    }
+    double P[4][3];
+    int64_t E[4][2][3];
+    for (int k = 0; k < ne; ++k) {
+      int a = e[k][0], b = e[k][1];
+      if (lex_less(corner[b], corner[a])) std::swap(a, b);
+      const double tt = f[a] / (f[a] - f[b]);
+      for (int d = 0; d < 3; ++d) {
+        const double pa = (double(corner[a][d]) + 0.5) * v, pb = (double(corner[b][d]) + 0.5) * v;
+        P[k][d] = pa + tt * (pb - pa);
+        E[k][0][d] = corner[a][d];
+        E[k][1][d] = corner[b][d];
+      }
+    }
+    // outward reference: from an inside corner to an outside corner
+    double g[3];
+    for (int d = 0; d < 3; ++d) g[d] = double(corner[outs[0]][d] - corner[ins[0]][d]);
+    const int tris[2][3] = {{0, 1, 2}, {0, 2, 3}};
+    const int ntri = ne == 4 ? 2 : 1;
+    for (int k = 0; k < ntri; ++k) {
+      int i0 = tris[k][0], i1 = tris[k][1], i2 = tris[k][2];
+      double u[3], w[3], n[3];
+      for (int d = 0; d < 3; ++d) u[d] = P[i1][d] - P[i0][d], w[d] = P[i2][d] - P[i0][d];
+      n[0] = u[1] * w[2] - u[2] * w[1];
+      n[1] = u[2] * w[0] - u[0] * w[2];
+      n[2] = u[0] * w[1] - u[1] * w[0];
+      if (n[0] * g[0] + n[1] * g[1] + n[2] * g[2] < 0.0) std::swap(i1, i2);
+      MeshTri m;
+      m.key = key;
+      m.code = uint32_t(loc) << 4 | uint32_t(t) << 1 | uint32_t(k);
+      const int idx[3] = {i0, i1, i2};
+      for (int j = 0; j < 3; ++j)
+        for (int d = 0; d < 3; ++d) {
+          m.p[j][d] = P[idx[j]][d];
+          m.edge[j][0][d] = E[idx[j]][0][d];
+          m.edge[j][1][d] = E[idx[j]][1][d];
+        }
+      out.push_back(m);
+    }
+  }
+}
+
+std::vector<MeshTri> extract_mesh(const Volume& vol) {
+  std::vector<MeshTri> out;
+  for (const auto& kv : vol.blocks) {
+    const uint64_t key = kv.first;
+    const int64_t bx = int64_t(key >> 42) - kAxisBias;
+    const int64_t by = int64_t((key >> 21) & ((1u << 21) - 1)) - kAxisBias;
+    const int64_t bz = int64_t(key & ((1u << 21) - 1)) - kAxisBias;
+    for (int loc = 0; loc < 512; ++loc) mesh_cube(vol, key, bx, by, bz, loc, out);
+  }
+  return out;
+}
+
 }  // namespace
 
 extern "C" {
@@ -333,6 +474,38 @@ uint64_t ora_export(void* h, uint64_t* keys, double* sums, double* means, uint32
     ++i;
   }
   return vol.blocks.size();
+}
+
+// Replace (or create) the block `key` with the given sums and weights (512 of
+// each): lets tests build a field directly.
+void ora_set_block(void* h, uint64_t key, const double* sums, const uint32_t* weights) {
+  Volume& vol = *static_cast<Volume*>(h);
+  Block& b = vol.blocks[key];
+  for (int l = 0; l < 512; ++l) {
+    b.sum[l] = sums[l];
+    b.weight[l] = weights[l];
+  }
+}
+
+// Marching-tetrahedra mesh of the volume, triangles in block-key order, then
+// cube, tetrahedron, triangle.  Per triangle: ids[2] = {key, code}, verts[9],
+// edges[18] (per vertex the two corners of its edge, global voxel indices).
+// Returns the triangle count; writes at most `cap`.  Any output may be NULL.
+uint64_t ora_extract_mesh(void* h, uint64_t* ids, double* verts, int64_t* edges, uint64_t cap) {
+  const std::vector<MeshTri> tris = extract_mesh(*static_cast<Volume*>(h));
+  for (uint64_t i = 0; i < tris.size() && i < cap; ++i) {
+    const MeshTri& m = tris[i];
+    if (ids) ids[2 * i] = m.key, ids[2 * i + 1] = m.code;
+    for (int j = 0; j < 3; ++j)
+      for (int d = 0; d < 3; ++d) {
+        if (verts) verts[9 * i + 3 * j + d] = m.p[j][d];
+        if (edges) {
+          edges[18 * i + 6 * j + d] = m.edge[j][0][d];
+          edges[18 * i + 6 * j + 3 + d] = m.edge[j][1][d];
+        }
+      }
+  }
+  return tris.size();
 }
 
 uint64_t ora_export_overflow_keys(void* h, uint64_t* keys, uint64_t cap) {
