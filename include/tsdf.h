@@ -204,6 +204,32 @@ tsdf_status tsdf_extract_blocks(tsdf_volume* vol, void* hip_stream, uint32_t max
                                 uint64_t* keys_dev, float* tsdf_dev, float* weight_dev,
                                 uint32_t* n_blocks_out);
 
+/* Surface extraction: the zero crossing of the mean TSDF as a triangle mesh,
+ * by marching tetrahedra over the voxel centres (the extraction the paper
+ * runs after fusion, Section 3, "What is excluded, and why"; Section 5,
+ * "Correctness" checks its output).
+ *   - Samples are voxel centres ((i + 1/2) * voxel_size per axis, metres) with
+ *     value sum / weight.  A cube of 8 neighbouring centres is meshed only
+ *     when all 8 voxels have a weight, and is skipped when it changes sign
+ *     while a corner's |value| >= (1 - 2^-10) * trunc (a jump at an occlusion
+ *     edge, not a surface).
+ *   - Each cube is cut into the 6 tetrahedra around its corner-0 to corner-7
+ *     diagonal (corner c has offset (c & 1, (c >> 1) & 1, c >> 2)).  A corner
+ *     is inside when its value is < 0.  Vertices are interpolated linearly on
+ *     crossing edges; triangles are wound with the normal towards positive
+ *     values (free space).
+ * Waits for `hip_stream` twice (block count, triangle count).  Triangle i
+ * writes vertices_dev[9i .. 9i+8] (three x, y, z vertices, float32) and, if
+ * ids_dev is not NULL, ids_dev[2i] = its block's packed key and
+ * ids_dev[2i+1] = cube << 4 | tetrahedron << 1 | triangle (cube = the
+ * in-block index of its lowest corner, as for voxels).  Triangles come in no
+ * particular order; their identities are unique.  *n_triangles_out = the
+ * number of triangles found; if it exceeds max_triangles, only max_triangles
+ * are written and TSDF_ERR_BUFFER_TOO_SMALL is returned.  vertices_dev may be
+ * NULL only when max_triangles is 0 (a count). */
+tsdf_status tsdf_extract_mesh(tsdf_volume* vol, void* hip_stream, uint32_t max_triangles,
+                              float* vertices_dev, uint64_t* ids_dev, uint32_t* n_triangles_out);
+
 /* Allocate pool blocks for `n` block coordinates (device array of n rows of
  * int32 bx, by, bz, each in [-2^20, 2^20)) through the same insertion protocol
  * as fusion, as if a frame had touched them.  Used to pre-fill a table to a

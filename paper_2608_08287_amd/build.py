@@ -20,7 +20,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libtsdf.so")
 SOURCES = ([os.path.join(CSRC, n) for n in ("tsdf_api.cpp", "tsdf_batch.cpp", "tsdf_arena.cpp",
-                                             "tsdf_server.cpp", "tsdf_kernels.hip")]
+                                             "tsdf_server.cpp", "tsdf_kernels.hip", "tsdf_mesh.hip")]
            + sorted(glob.glob(os.path.join(CSRC, "tsdf_fuse_k*.hip"))))
 BUILD_DIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

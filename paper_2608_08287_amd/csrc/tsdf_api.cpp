@@ -250,6 +250,30 @@ tsdf_status tsdf_extract_blocks(tsdf_volume* vol, void* hip_stream, uint32_t max
                                          tsdf_dev, weight_dev, s));
 }
 
+tsdf_status tsdf_extract_mesh(tsdf_volume* vol, void* hip_stream, uint32_t max_triangles,
+                              float* vertices_dev, uint64_t* ids_dev, uint32_t* n_triangles_out) {
+  if (!vol || !n_triangles_out || (max_triangles > 0 && !vertices_dev))
+    return TSDF_ERR_INVALID_ARGUMENT;
+  hipStream_t s = as_stream(hip_stream);
+  unsigned count = 0;
+  if (hipMemcpyAsync(&count, &vol->dev.ctr->block_count, sizeof(count), hipMemcpyDeviceToHost,
+                     s) != hipSuccess)
+    return TSDF_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return TSDF_ERR_HIP;
+  const uint32_t n_blocks = count < vol->layout.pool_capacity ? count : vol->layout.pool_capacity;
+  unsigned* counter = &vol->dev.ctr->mesh_triangles;
+  hipError_t e = tsdf::launch_fill_u32(counter, 0u, 1, s);
+  if (e == hipSuccess)
+    e = tsdf::launch_mesh(vol->dev, walk_params(vol), n_blocks, counter, max_triangles,
+                          vertices_dev, reinterpret_cast<unsigned long long*>(ids_dev), s);
+  unsigned tris = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&tris, counter, sizeof(tris), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return TSDF_ERR_HIP;
+  *n_triangles_out = tris;
+  return tris > max_triangles ? TSDF_ERR_BUFFER_TOO_SMALL : TSDF_OK;
+}
+
 tsdf_status tsdf_insert_blocks(tsdf_volume* vol, const int32_t* block_coords_dev, uint32_t n,
                                void* hip_stream) {
   if (!vol || (n > 0 && !block_coords_dev)) return TSDF_ERR_INVALID_ARGUMENT;

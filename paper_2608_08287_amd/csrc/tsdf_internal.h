@@ -34,7 +34,8 @@ struct DevCounters {
   unsigned table_full_events;
   unsigned max_probe;
   unsigned lookup_misses;
-  unsigned pad0[26];
+  unsigned mesh_triangles;      // surface extraction: triangles found
+  unsigned pad0[25];
   // line 1: losses
   unsigned long long pairs_dropped;
   unsigned long long coord_out_of_range;
@@ -150,6 +151,11 @@ const void* multi_kernel_band8(int pixels_per_thread, int acc_blocks);
 // out[i] = the sticky status bits of the volume whose counters ctrs[i] points
 // to (0 for a null pointer), i < n.  ctrs and out may be host-mapped memory.
 hipError_t launch_gather_status(DevCounters* const* ctrs, unsigned n, unsigned* out, hipStream_t s);
+// Marching-tetrahedra surface of the first n_blocks pool blocks; counter
+// (zeroed by the caller) receives the triangle count; at most max_tris
+// triangles are written (9 floats in verts, 2 ids in ids, ids may be null).
+hipError_t launch_mesh(VolumeDev vol, const WalkParams& wp, unsigned n_blocks, unsigned* counter,
+                       unsigned max_tris, float* verts, unsigned long long* ids, hipStream_t s);
 hipError_t launch_insert_blocks(VolumeDev vol, const int* coords, unsigned n, hipStream_t s);
 hipError_t launch_extract(VolumeDev vol, unsigned n_blocks, unsigned long long* keys,
                           float* tsdf, float* weight, hipStream_t s);

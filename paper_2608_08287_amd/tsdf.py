@@ -37,7 +37,7 @@ EXPORTED_SYMBOLS = (
     "tsdf_volume_bytes", "tsdf_volume_layout", "tsdf_create_volume", "tsdf_destroy_volume",
     "tsdf_reset_volume", "tsdf_fuse_frame", "tsdf_fuse_frame_ex", "tsdf_fuse_frames",
     "tsdf_query_status",
-    "tsdf_extract_blocks", "tsdf_insert_blocks", "tsdf_status_str",
+    "tsdf_extract_blocks", "tsdf_extract_mesh", "tsdf_insert_blocks", "tsdf_status_str",
     "tsdf_batch_workspace_bytes", "tsdf_batch_create", "tsdf_batch_destroy",
     "tsdf_batch_set_config", "tsdf_batch_autotune", "tsdf_batch_get_config",
     "tsdf_batch_candidates", "tsdf_batch_fuse",
@@ -135,6 +135,8 @@ def lib() -> C.CDLL:
         L.tsdf_query_status.argtypes = [P, P, C.POINTER(StatsC)]
         L.tsdf_extract_blocks.restype = I
         L.tsdf_extract_blocks.argtypes = [P, P, U32, P, P, P, C.POINTER(U32)]
+        L.tsdf_extract_mesh.restype = I
+        L.tsdf_extract_mesh.argtypes = [P, P, U32, P, P, C.POINTER(U32)]
         L.tsdf_insert_blocks.restype = I
         L.tsdf_insert_blocks.argtypes = [P, P, U32, P]
         L.tsdf_status_str.restype = C.c_char_p
@@ -288,6 +290,28 @@ class _VolumeCalls:
 
 
 
+@dataclass
+class Mesh:
+    verts: torch.Tensor  # (T, 3, 3) float32 vertex positions (metres), wound outwards
+    ids: torch.Tensor    # (T, 2) int64: block key, cube << 4 | tetrahedron << 1 | triangle
+
+
+def _extract_mesh(h, stream, device, guess: int) -> Mesh:
+    L = lib()
+    n = C.c_uint32(0)
+    cap = max(guess, 1)
+    while True:
+        verts = torch.empty((cap, 3, 3), dtype=torch.float32, device=device)
+        ids = torch.empty((cap, 2), dtype=torch.int64, device=device)
+        st = L.tsdf_extract_mesh(h, _stream_ptr(stream), cap, C.c_void_p(verts.data_ptr()),
+                                 C.c_void_p(ids.data_ptr()), C.byref(n))
+        if st == OK:
+            return Mesh(verts[:n.value], ids[:n.value])
+        if st != ERR_BUFFER_TOO_SMALL:
+            raise TsdfError(st, "tsdf_extract_mesh")
+        cap = n.value
+
+
 class Volume(_VolumeCalls):
     """One resident TSDF volume in a device arena owned by this object."""
 
@@ -363,6 +387,10 @@ class Volume(_VolumeCalls):
         st = lib().tsdf_insert_blocks(self._h, C.c_void_p(coords.data_ptr()), n, _stream_ptr(stream))
         if st != OK:
             raise TsdfError(st, "tsdf_insert_blocks")
+
+    def extract_mesh(self, stream=None) -> Mesh:
+        """Marching-tetrahedra surface (tsdf_extract_mesh)."""
+        return _extract_mesh(self._h, stream, self.device, 64 * max(self.stats(stream).blocks_total, 1))
 
     # Zero-copy views of the carved regions (for invariant checks and consumers).
     def table_view(self) -> torch.Tensor:
