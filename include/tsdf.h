@@ -66,6 +66,19 @@ typedef enum tsdf_status {
 #define TSDF_MAX_POOL_BLOCKS ((1u << 22) - 1u) /* keeps voxel indices below 2^31 */
 #define TSDF_MAX_BAND_HALF 8 /* round(trunc / voxel_size) must lie in [1, 8] */
 
+/* Volume variants (tsdf_volume_params.flags), both from Section 6:
+ *   TSDF_VOLUME_SLOT_INDEX  a block's pool index is its hash-table slot
+ *       ("Deriving the location from the slot"): no pool counter to win and
+ *       no index to wait for, at the cost of a pool as large as the table.
+ *       pool_capacity must equal the table capacity; table_capacity 0 means
+ *       "equal to pool_capacity" here.  The pool cannot run out.
+ *   TSDF_VOLUME_COLOUR  three more accumulators per voxel, the red, green and
+ *       blue sums of the colour of every contribution (Section 2.1: five
+ *       parallel arrays); frames then come with a colour image
+ *       (tsdf_fuse_frame_rgb, tsdf_fuse_item.rgba_dev). */
+#define TSDF_VOLUME_SLOT_INDEX 0x1u
+#define TSDF_VOLUME_COLOUR 0x2u
+
 typedef struct tsdf_volume_params {
   float voxel_size;        /* voxel edge in metres, finite and > 0 */
   float trunc;             /* truncation distance tau in metres, finite; the band
@@ -75,6 +88,7 @@ typedef struct tsdf_volume_params {
                               of two); 0 selects the paper's sizing, the next power
                               of two >= 2 * pool_capacity (Section 2.1) */
   uint32_t pool_capacity;  /* voxel blocks P, 1 .. TSDF_MAX_POOL_BLOCKS */
+  uint32_t flags;          /* TSDF_VOLUME_* (0: the paper's main design) */
 } tsdf_volume_params;
 
 typedef struct tsdf_camera {
@@ -107,7 +121,10 @@ typedef struct tsdf_stats {
  *   table      : table_capacity entries of 16 bytes: {uint64 key; int32 block;
  *                uint32 pad}, key TSDF_EMPTY_KEY when free; block >= 0 is a pool
  *                index, -1 = being published, -2 = the pool was full
- *   block_keys : pool_capacity uint64, the key of each allocated pool block
+ *   block_keys : pool_capacity uint64, the key of the i-th allocated block
+ *   alloc_list : (TSDF_VOLUME_SLOT_INDEX only) pool_capacity uint32, the pool
+ *                index (= table slot) of the i-th allocated block; without the
+ *                flag the i-th allocated block is pool block i
  *   voxels     : pool_capacity * 1024 float, the voxel pool.  Voxel (lx, ly, lz)
  *                of block b has in-block index loc = (lz * 8 + ly) * 8 + lx
  *                (x fastest) and lies in x-row r = loc / 8; each row is one
@@ -115,10 +132,15 @@ typedef struct tsdf_stats {
  *                  TSDF sum : voxels[b * 1024 + r * 16 + lx]
  *                  weight   : voxels[b * 1024 + r * 16 + 8 + lx]
  *                Weights count contributions; TSDF values are sums (the mean is
- *                sum / weight).  tsdf_extract_blocks returns plain arrays. */
+ *                sum / weight).  tsdf_extract_blocks returns plain arrays.
+ *   colour     : (TSDF_VOLUME_COLOUR only) pool_capacity * 1536 float: per
+ *                block 64 rows of 24 floats, the row's 8 red, 8 green, 8 blue
+ *                sums (colour values 0..255):
+ *                  red sum : colour[b * 1536 + r * 24 + lx], green + 8, blue + 16
+ *                Regions a volume does not use have size 0. */
 typedef struct tsdf_layout {
-  uint64_t counters, table, block_keys, voxels, total_bytes;
-  uint32_t table_capacity, pool_capacity;
+  uint64_t counters, table, block_keys, alloc_list, voxels, colour, total_bytes;
+  uint32_t table_capacity, pool_capacity, flags, reserved;
 } tsdf_layout;
 
 typedef struct tsdf_volume tsdf_volume;
@@ -167,6 +189,17 @@ tsdf_status tsdf_fuse_frame(tsdf_volume* vol, const float* depth_dev, const tsdf
 tsdf_status tsdf_fuse_frame_ex(tsdf_volume* vol, const float* depth_dev, const tsdf_camera* cam,
                                uint32_t flags, void* hip_stream);
 
+/* As tsdf_fuse_frame_ex, for a TSDF_VOLUME_COLOUR volume: `rgba_dev` is a
+ * height x width array of packed 8-bit colours (red | green << 8 |
+ * blue << 16; the top byte is ignored) registered with the depth image; every
+ * contribution also adds its pixel's red, green and blue values to the
+ * voxel's colour sums.  Colour volumes take frames only through this call and
+ * through tsdf_batch_fuse; tsdf_fuse_frame, _ex and tsdf_fuse_frames refuse
+ * them (TSDF_ERR_INVALID_ARGUMENT).  rgba_dev may be NULL only for an empty
+ * frame. */
+tsdf_status tsdf_fuse_frame_rgb(tsdf_volume* vol, const float* depth_dev, const uint32_t* rgba_dev,
+                                const tsdf_camera* cam, uint32_t flags, void* hip_stream);
+
 /* Fuse `n_frames` depth frames into the volume, up to 16 frames per launch:
  * the tiles of all frames of a launch share one grid, so one frame's start-up
  * overlaps another's pool updates.  Each workgroup takes the same 16x16 pixel
@@ -203,6 +236,13 @@ tsdf_status tsdf_query_status(tsdf_volume* vol, void* hip_stream, tsdf_stats* ou
 tsdf_status tsdf_extract_blocks(tsdf_volume* vol, void* hip_stream, uint32_t max_blocks,
                                 uint64_t* keys_dev, float* tsdf_dev, float* weight_dev,
                                 uint32_t* n_blocks_out);
+
+/* Colour volumes: as tsdf_extract_blocks, the mean colour of every allocated
+ * block in the same order: rgb_dev[(i * 512 + loc) * 3 + c] = colour sum c /
+ * weight (0 where the weight is 0), c = 0, 1, 2 for red, green, blue, values
+ * in 0..255.  TSDF_ERR_INVALID_ARGUMENT for a volume without colour. */
+tsdf_status tsdf_extract_colour(tsdf_volume* vol, void* hip_stream, uint32_t max_blocks,
+                                float* rgb_dev, uint32_t* n_blocks_out);
 
 /* Surface extraction: the zero crossing of the mean TSDF as a triangle mesh,
  * by marching tetrahedra over the voxel centres (the extraction the paper
@@ -260,6 +300,8 @@ typedef struct tsdf_batch tsdf_batch;
 typedef struct tsdf_fuse_item {
   tsdf_volume* volume;      /* target volume */
   const float* depth_dev;   /* height x width float32, as for tsdf_fuse_frame */
+  const uint32_t* rgba_dev; /* colour volumes: height x width packed colours, as
+                               for tsdf_fuse_frame_rgb; ignored otherwise */
   tsdf_camera camera;
 } tsdf_fuse_item;
 
@@ -393,7 +435,8 @@ tsdf_status tsdf_server_destroy(tsdf_server* server);
 
 /* Admit a session: carve tsdf_volume_bytes(params) from the budget and
  * enqueue the volume's initialisation.  TSDF_ERR_BUDGET if the budget (or
- * the session table) has no room. */
+ * the session table) has no room.  Colour volumes are not served
+ * (TSDF_ERR_INVALID_ARGUMENT). */
 tsdf_status tsdf_server_open(tsdf_server* server, const tsdf_volume_params* params,
                              uint32_t* session_out);
 

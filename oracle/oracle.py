@@ -50,6 +50,9 @@ def lib():
         L.ora_probe_model.restype = U64
         L.ora_probe_model.argtypes = [P, U64, U32, P, P, P]
         L.ora_set_block.argtypes = [P, U64, P, P]
+        L.ora_fuse_rgb.argtypes = [P, P, P, U32, U32, P, P, C.c_int]
+        L.ora_export_colour.restype = U64
+        L.ora_export_colour.argtypes = [P, P, U64]
         L.ora_extract_mesh.restype = U64
         L.ora_extract_mesh.argtypes = [P, P, P, P, U64]
         _lib = L
@@ -109,6 +112,27 @@ class OracleVolume:
         H, W = d.shape
         if lib().ora_fuse(self._h, _ptr(d), W, H, _ptr(intr), _ptr(pose), int(reverse)) != 0:
             raise ValueError("invalid frame")
+
+    def fuse_rgb(self, depth: np.ndarray, rgba: np.ndarray, cam, reverse: bool = False) -> None:
+        """As fuse, also adding each contribution's pixel colour (packed uint32
+        red | green << 8 | blue << 16) to the voxel's colour sums."""
+        d = np.ascontiguousarray(depth, dtype=np.float32)
+        c = np.ascontiguousarray(rgba, dtype=np.uint32)
+        if c.shape != d.shape:
+            raise ValueError("colour image does not match the depth image")
+        intr, pose = _cam_arrays(cam)
+        H, W = d.shape
+        if lib().ora_fuse_rgb(self._h, _ptr(d), _ptr(c), W, H, _ptr(intr), _ptr(pose),
+                              int(reverse)) != 0:
+            raise ValueError("invalid frame")
+
+    def colour_sums(self) -> np.ndarray:
+        """(B, 3, 512) float64 red, green, blue sums, blocks in ascending key order."""
+        L = lib()
+        nb = int(L.ora_export(self._h, None, None, None, None, 0))
+        out = np.zeros((nb, 3, 512), dtype=np.float64)
+        L.ora_export_colour(self._h, _ptr(out), nb)
+        return out
 
     def stats(self) -> dict:
         out = np.zeros(8, dtype=np.uint64)

@@ -83,6 +83,7 @@ struct Pair {
   uint32_t loc;   // voxel index inside the block: (lz*8 + ly)*8 + lx
   float val;      // truncated signed distance contributed
   int32_t vx, vy, vz;
+  uint64_t pixel; // row-major index of the point's pixel
 };
 
 struct WalkCounts {
@@ -165,6 +166,7 @@ void walk_frame(const Params& p, const Frame& f, bool reverse, WalkCounts& cnt, 
       pr.vx = vx;
       pr.vy = vy;
       pr.vz = vz;
+      pr.pixel = i;
       cnt.pairs++;
       emit(pr);
     }
@@ -174,6 +176,7 @@ void walk_frame(const Params& p, const Frame& f, bool reverse, WalkCounts& cnt, 
 struct Block {
   double sum[512];
   uint32_t weight[512];
+  double colour[3][512];  // red, green, blue sums (Section 2.1: five parallel arrays)
 };
 
 struct Volume {
@@ -419,8 +422,11 @@ int ora_insert_blocks(void* h, const int32_t* coords, uint64_t n) {
 
 // Fuse one frame: PASS 1 over every pair, then PASS 2 over every pair.
 // intr4 = (fx, fy, cx, cy); pose12 = camera->world [R|t] row-major.
-int ora_fuse(void* h, const float* depth, uint32_t W, uint32_t H, const float* intr4,
-             const float* pose12, int reverse) {
+// Both passes of one frame; with `rgba` (packed red | green << 8 | blue << 16
+// per pixel) every contribution also adds its pixel's colour to the voxel's
+// three colour sums.
+static int fuse_impl(void* h, const float* depth, const uint32_t* rgba, uint32_t W, uint32_t H,
+              const float* intr4, const float* pose12, int reverse) {
   Volume& vol = *static_cast<Volume*>(h);
   Frame f;
   if (!make_frame(depth, W, H, intr4, pose12, f)) return -1;
@@ -434,12 +440,39 @@ int ora_fuse(void* h, const float* depth, uint32_t W, uint32_t H, const float* i
     }
     it->second.sum[pr.loc] += double(pr.val);
     it->second.weight[pr.loc] += 1;
+    if (rgba)
+      for (int c = 0; c < 3; ++c)
+        it->second.colour[c][pr.loc] += double((rgba[pr.pixel] >> (8 * c)) & 255u);
   });
   vol.points_valid += c2.points_valid;
   vol.pairs += c2.pairs;
   vol.coord_out_of_range += c2.coord_out_of_range;
   vol.frames++;
   return 0;
+}
+
+int ora_fuse(void* h, const float* depth, uint32_t W, uint32_t H, const float* intr4,
+             const float* pose12, int reverse) {
+  return fuse_impl(h, depth, nullptr, W, H, intr4, pose12, reverse);
+}
+
+int ora_fuse_rgb(void* h, const float* depth, const uint32_t* rgba, uint32_t W, uint32_t H,
+                 const float* intr4, const float* pose12, int reverse) {
+  if (!rgba && uint64_t(W) * H > 0) return -1;
+  return fuse_impl(h, depth, rgba, W, H, intr4, pose12, reverse);
+}
+
+// Colour sums of every block in ascending key order: sums[(i * 3 + c) * 512 + l].
+uint64_t ora_export_colour(void* h, double* sums, uint64_t cap) {
+  const Volume& vol = *static_cast<Volume*>(h);
+  uint64_t i = 0;
+  for (const auto& kv : vol.blocks) {
+    if (i >= cap) break;
+    for (int c = 0; c < 3; ++c)
+      for (int l = 0; l < 512; ++l) sums[(i * 3 + c) * 512 + l] = kv.second.colour[c][l];
+    ++i;
+  }
+  return vol.blocks.size();
 }
 
 // stats: [points_valid, pairs, pairs_dropped, coord_out_of_range, blocks,

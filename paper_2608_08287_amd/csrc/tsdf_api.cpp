@@ -28,9 +28,14 @@ bool make_layout(const tsdf_volume_params* p, tsdf_layout* out) {
   const int K = band_half(*p);
   if (K < 1 || K > TSDF_MAX_BAND_HALF) return false;
   if (p->pool_capacity < 1 || p->pool_capacity > TSDF_MAX_POOL_BLOCKS) return false;
+  if ((p->flags & ~(TSDF_VOLUME_SLOT_INDEX | TSDF_VOLUME_COLOUR)) != 0) return false;
+  const bool slot_index = (p->flags & TSDF_VOLUME_SLOT_INDEX) != 0;
+  const bool colour = (p->flags & TSDF_VOLUME_COLOUR) != 0;
   uint32_t C = p->table_capacity;
-  if (C == 0) C = next_pow2_at_least(2ull * p->pool_capacity);
+  if (C == 0) C = slot_index ? p->pool_capacity : next_pow2_at_least(2ull * p->pool_capacity);
   if (C == 0) return false;
+  if (slot_index && C != p->pool_capacity) return false;  // one block per slot
+  const uint64_t P = p->pool_capacity;
   tsdf_layout L;
   std::memset(&L, 0, sizeof(L));
   uint64_t off = 0;
@@ -39,12 +44,17 @@ bool make_layout(const tsdf_volume_params* p, tsdf_layout* out) {
   L.table = off;
   off = align_up(off + (uint64_t)C * sizeof(tsdf::TableEntry));
   L.block_keys = off;
-  off = align_up(off + (uint64_t)p->pool_capacity * 8ull);
+  off = align_up(off + P * 8ull);
+  L.alloc_list = off;
+  off = align_up(off + (slot_index ? P * 4ull : 0ull));
   L.voxels = off;
-  off = align_up(off + (uint64_t)p->pool_capacity * tsdf::kBlockFloats * 4ull);
+  off = align_up(off + P * tsdf::kBlockFloats * 4ull);
+  L.colour = off;
+  off = align_up(off + (colour ? P * tsdf::kColourFloats * 4ull : 0ull));
   L.total_bytes = off;
   L.table_capacity = C;
   L.pool_capacity = p->pool_capacity;
+  L.flags = p->flags;
   *out = L;
   return true;
 }
@@ -89,8 +99,14 @@ tsdf_status tsdf_create_volume(const tsdf_volume_params* params, void* dev_arena
   v->dev.table = reinterpret_cast<tsdf::TableEntry*>(base + L.table);
   v->dev.block_keys = reinterpret_cast<unsigned long long*>(base + L.block_keys);
   v->dev.voxels = reinterpret_cast<float*>(base + L.voxels);
+  const bool slot_index = (L.flags & TSDF_VOLUME_SLOT_INDEX) != 0;
+  const bool colour = (L.flags & TSDF_VOLUME_COLOUR) != 0;
+  v->dev.alloc_list = slot_index ? reinterpret_cast<unsigned*>(base + L.alloc_list) : nullptr;
+  v->dev.colour = colour ? reinterpret_cast<float*>(base + L.colour) : nullptr;
   v->dev.table_capacity = L.table_capacity;
   v->dev.pool_capacity = L.pool_capacity;
+  v->dev.slot_index = slot_index ? 1u : 0u;
+  v->dev.pad = 0;
   hipStream_t s = as_stream(hip_stream);
   tsdf_status st = init_table_and_counters(v, s);
   const size_t pool_words = (size_t)L.pool_capacity * tsdf::kBlockFloats;
@@ -98,6 +114,9 @@ tsdf_status tsdf_create_volume(const tsdf_volume_params* params, void* dev_arena
   if (st == TSDF_OK)
     st = hip_status(tsdf::launch_fill_u32(v->dev.block_keys, 0xFFFFFFFFu,
                                           (size_t)L.pool_capacity * 2, s));
+  if (st == TSDF_OK && v->dev.colour)
+    st = hip_status(tsdf::launch_fill_u32(v->dev.colour, 0u,
+                                          (size_t)L.pool_capacity * tsdf::kColourFloats, s));
   if (st != TSDF_OK) {
     std::free(v);
     return st;
@@ -123,14 +142,17 @@ tsdf_status tsdf_reset_volume(tsdf_volume* vol, void* hip_stream) {
   return st;
 }
 
-tsdf_status tsdf_fuse_frame_ex(tsdf_volume* vol, const float* depth_dev, const tsdf_camera* cam,
-                               uint32_t flags, void* hip_stream) {
+namespace {
+
+tsdf_status fuse_one(tsdf_volume* vol, const float* depth_dev, const uint32_t* rgba_dev,
+                     const tsdf_camera* cam, uint32_t flags, void* hip_stream) {
   if (!vol || !valid_camera(cam)) return TSDF_ERR_INVALID_ARGUMENT;
   if ((flags & ~(TSDF_FUSE_MODE_MASK | TSDF_FUSE_XCD_REMAP)) != 0)
     return TSDF_ERR_INVALID_ARGUMENT;
   const uint64_t n_pix = (uint64_t)cam->width * cam->height;
   if (n_pix > 0 && !depth_dev) return TSDF_ERR_INVALID_ARGUMENT;
-  const tsdf::FrameDev f = frame_dev(depth_dev, cam);
+  if (n_pix > 0 && vol->dev.colour && !rgba_dev) return TSDF_ERR_INVALID_ARGUMENT;
+  const tsdf::FrameDev f = frame_dev(depth_dev, cam, vol->dev.colour ? rgba_dev : nullptr);
   const tsdf::WalkParams wp = walk_params(vol);
   const bool remap = (flags & TSDF_FUSE_XCD_REMAP) != 0;
   hipStream_t s = as_stream(hip_stream);
@@ -158,10 +180,25 @@ tsdf_status tsdf_fuse_frame_ex(tsdf_volume* vol, const float* depth_dev, const t
   return TSDF_OK;
 }
 
+}  // namespace
+
+tsdf_status tsdf_fuse_frame_ex(tsdf_volume* vol, const float* depth_dev, const tsdf_camera* cam,
+                               uint32_t flags, void* hip_stream) {
+  if (vol && vol->dev.colour) return TSDF_ERR_INVALID_ARGUMENT;  // colour needs an image
+  return fuse_one(vol, depth_dev, nullptr, cam, flags, hip_stream);
+}
+
+tsdf_status tsdf_fuse_frame_rgb(tsdf_volume* vol, const float* depth_dev, const uint32_t* rgba_dev,
+                                const tsdf_camera* cam, uint32_t flags, void* hip_stream) {
+  if (vol && !vol->dev.colour) return TSDF_ERR_INVALID_ARGUMENT;
+  return fuse_one(vol, depth_dev, rgba_dev, cam, flags, hip_stream);
+}
+
 tsdf_status tsdf_fuse_frames(tsdf_volume* vol, uint32_t n_frames, const float* const* depth_devs,
                              const tsdf_camera* cams, uint32_t flags, void* hip_stream) {
   if (!vol || (n_frames > 0 && (!depth_devs || !cams))) return TSDF_ERR_INVALID_ARGUMENT;
   if ((flags & ~(TSDF_FUSE_XCD_REMAP | TSDF_FUSE_BATCH_MASK)) != 0) return TSDF_ERR_INVALID_ARGUMENT;
+  if (vol->dev.colour) return TSDF_ERR_INVALID_ARGUMENT;  // colour frames: _rgb or batches
   for (uint32_t i = 0; i < n_frames; ++i) {
     if (!valid_camera(&cams[i])) return TSDF_ERR_INVALID_ARGUMENT;
     if ((uint64_t)cams[i].width * cams[i].height > 0 && !depth_devs[i])
@@ -248,6 +285,22 @@ tsdf_status tsdf_extract_blocks(tsdf_volume* vol, void* hip_stream, uint32_t max
   if (n > max_blocks) return TSDF_ERR_BUFFER_TOO_SMALL;
   return hip_status(tsdf::launch_extract(vol->dev, n, reinterpret_cast<unsigned long long*>(keys_dev),
                                          tsdf_dev, weight_dev, s));
+}
+
+tsdf_status tsdf_extract_colour(tsdf_volume* vol, void* hip_stream, uint32_t max_blocks,
+                                float* rgb_dev, uint32_t* n_blocks_out) {
+  if (!vol || !n_blocks_out || !vol->dev.colour) return TSDF_ERR_INVALID_ARGUMENT;
+  hipStream_t s = as_stream(hip_stream);
+  unsigned count = 0;
+  if (hipMemcpyAsync(&count, &vol->dev.ctr->block_count, sizeof(count), hipMemcpyDeviceToHost,
+                     s) != hipSuccess)
+    return TSDF_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return TSDF_ERR_HIP;
+  const uint32_t n = count < vol->layout.pool_capacity ? count : vol->layout.pool_capacity;
+  *n_blocks_out = n;
+  if (n > max_blocks) return TSDF_ERR_BUFFER_TOO_SMALL;
+  if (n > 0 && !rgb_dev) return TSDF_ERR_INVALID_ARGUMENT;
+  return hip_status(tsdf::launch_extract_colour(vol->dev, n, rgb_dev, s));
 }
 
 tsdf_status tsdf_extract_mesh(tsdf_volume* vol, void* hip_stream, uint32_t max_triangles,

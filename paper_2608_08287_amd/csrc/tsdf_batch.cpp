@@ -25,7 +25,8 @@ namespace {
 
 constexpr int kRingSlots = 4;
 constexpr int kMaxGraphs = 4;
-constexpr uint64_t kHeaderBytes = 256;  // k_begin[kBatchKSlots], padded
+constexpr uint64_t kHeaderBytes = 256;  // k_begin[kBatchGroups], padded
+static_assert(4 * (tsdf::kBatchGroups + 1) <= kHeaderBytes, "group ranges fit the header");
 constexpr int kAccChoices[3] = {4, 8, 16};
 constexpr uint32_t kTileWidths[3] = {16, 32, 64};
 constexpr int kMaxPixelsPerThread = 2;
@@ -54,7 +55,7 @@ bool valid_config(const tsdf_batch_config* c) {
   if (!c || !(c->tile_width == 16 || c->tile_width == 32 || c->tile_width == 64)) return false;
   if (c->pixels_per_thread < 1 || c->pixels_per_thread > (uint32_t)kMaxPixelsPerThread) return false;
   if (acc_index(c->acc_blocks) < 0 || c->groups_per_cu > 64) return false;
-  return tsdf::multi_kernel(1, (int)c->pixels_per_thread, (int)c->acc_blocks) != nullptr;
+  return tsdf::multi_kernel(1, (int)c->pixels_per_thread, (int)c->acc_blocks, false) != nullptr;
 }
 
 bool same_config(const tsdf_batch_config& a, const tsdf_batch_config& b) {
@@ -83,8 +84,9 @@ struct tsdf_batch {
   char* ws;
   WorkLayout L;
   int n_cu;
-  // resident workgroups per CU by [K][pixels per thread - 1][acc index]; 0 = not yet asked
-  int occupancy[TSDF_MAX_BAND_HALF + 1][kMaxPixelsPerThread][3];
+  // resident workgroups per CU by [K][pixels per thread - 1][acc index][colour];
+  // 0 = not yet asked
+  int occupancy[TSDF_MAX_BAND_HALF + 1][kMaxPixelsPerThread][3][2];
   // staging ring
   char* ring;
   hipEvent_t ring_done[kRingSlots];
@@ -109,11 +111,24 @@ struct tsdf_batch {
 
 namespace {
 
-int occupancy(tsdf_batch* b, int K, int ppt, int ai) {
-  int& o = b->occupancy[K][ppt - 1][ai];
+// A group's kernel shape: the configuration's, except for colour volumes,
+// which have one (1 pixel per thread, 4 LDS blocks).
+struct Shape {
+  int K, ppt, ab;
+  bool colour;
+};
+
+Shape shape_of(int group, const tsdf_batch_config& c) {
+  const bool colour = group >= tsdf::batch_group(0, true);
+  const int K = colour ? group - tsdf::batch_group(0, true) : group;
+  return colour ? Shape{K, 1, 4, true} : Shape{K, (int)c.pixels_per_thread, (int)c.acc_blocks, false};
+}
+
+int occupancy(tsdf_batch* b, int K, int ppt, int ai, bool colour = false) {
+  int& o = b->occupancy[K][ppt - 1][ai][colour ? 1 : 0];
   if (o == 0) {
     int n = 0;
-    const void* fn = tsdf::multi_kernel(K, ppt, kAccChoices[ai]);
+    const void* fn = tsdf::multi_kernel(K, ppt, kAccChoices[ai], colour);
     if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, 256, 0) != hipSuccess || n < 1)
       n = 1;
     o = n;
@@ -121,9 +136,8 @@ int occupancy(tsdf_batch* b, int K, int ppt, int ai) {
   return o;
 }
 
-unsigned grid_for(tsdf_batch* b, int K, const tsdf_batch_config& c) {
-  const int ai = acc_index(c.acc_blocks);
-  int per_cu = occupancy(b, K, (int)c.pixels_per_thread, ai);
+unsigned grid_for(tsdf_batch* b, const Shape& sh, const tsdf_batch_config& c) {
+  int per_cu = occupancy(b, sh.K, sh.ppt, acc_index((uint32_t)sh.ab), sh.colour);
   if (c.groups_per_cu != 0 && (int)c.groups_per_cu < per_cu) per_cu = (int)c.groups_per_cu;
   return (unsigned)per_cu * (unsigned)b->n_cu;
 }
@@ -136,7 +150,7 @@ void build_candidates(tsdf_batch* b) {
   for (int ppt = 1; ppt <= kMaxPixelsPerThread; ++ppt)
     for (uint32_t tw : kTileWidths)
       for (int ab : kAccChoices)
-        if (tsdf::multi_kernel(4, ppt, ab))
+        if (tsdf::multi_kernel(4, ppt, ab, false))
           b->cands.push_back(tsdf_batch_config{tw, (uint32_t)ppt, (uint32_t)ab, 0u});
   for (int ppt = 1; ppt <= kMaxPixelsPerThread; ++ppt) {
     const int full = occupancy(b, 4, ppt, acc_index(8));
@@ -206,18 +220,18 @@ tsdf::BatchWork device_work(const tsdf_batch* b) {
   return w;
 }
 
-hipError_t launch_direct(tsdf_batch* b, uint32_t k_mask, const tsdf_batch_config& c,
-                         const uint32_t* k_tiles, hipStream_t s) {
+hipError_t launch_direct(tsdf_batch* b, uint32_t g_mask, const tsdf_batch_config& c,
+                         const uint32_t* g_tiles, hipStream_t s) {
   tsdf::BatchWork w = device_work(b);
   unsigned tw_log2 = log2_u32(c.tile_width);
   void* args[] = {&w, &tw_log2};
-  for (int K = 1; K <= TSDF_MAX_BAND_HALF; ++K) {
-    if (!(k_mask & (1u << K))) continue;
-    unsigned grid = grid_for(b, K, c);
-    if (k_tiles[K] < grid) grid = k_tiles[K];
-    const hipError_t e =
-        hipLaunchKernel(tsdf::multi_kernel(K, (int)c.pixels_per_thread, (int)c.acc_blocks),
-                        dim3(grid), dim3(256), args, 0, s);
+  for (int g = 0; g < tsdf::kBatchGroups; ++g) {
+    if (!(g_mask & (1u << g))) continue;
+    const Shape sh = shape_of(g, c);
+    unsigned grid = grid_for(b, sh, c);
+    if (g_tiles[g] < grid) grid = g_tiles[g];
+    const hipError_t e = hipLaunchKernel(tsdf::multi_kernel(sh.K, sh.ppt, sh.ab, sh.colour),
+                                         dim3(grid), dim3(256), args, 0, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -228,8 +242,9 @@ void destroy_graph(GraphEntry& g) {
   (void)hipGraphDestroy(g.graph);
 }
 
-// The instantiated graph of one kernel node per K in k_mask for configuration
-// c (no memory nodes: the work list arrives by the copy before the launch).
+// The instantiated graph of one kernel node per group in k_mask (band width
+// and colour) for configuration c (no memory nodes: the work list arrives by
+// the copy before the launch).
 hipError_t graph_for(tsdf_batch* b, uint32_t k_mask, const tsdf_batch_config& c, hipStream_t s,
                      hipGraphExec_t* out) {
   for (int i = 0; i < b->n_graphs; ++i) {
@@ -246,12 +261,13 @@ hipError_t graph_for(tsdf_batch* b, uint32_t k_mask, const tsdf_batch_config& c,
   tsdf::BatchWork w = device_work(b);
   unsigned tw_log2 = log2_u32(c.tile_width);
   void* args[] = {&w, &tw_log2};
-  for (int K = 1; K <= TSDF_MAX_BAND_HALF && e == hipSuccess; ++K) {
-    if (!(k_mask & (1u << K))) continue;
+  for (int g = 0; g < tsdf::kBatchGroups && e == hipSuccess; ++g) {
+    if (!(k_mask & (1u << g))) continue;
+    const Shape sh = shape_of(g, c);
     hipKernelNodeParams p;
     std::memset(&p, 0, sizeof(p));
-    p.func = const_cast<void*>(tsdf::multi_kernel(K, (int)c.pixels_per_thread, (int)c.acc_blocks));
-    p.gridDim = dim3(grid_for(b, K, c));
+    p.func = const_cast<void*>(tsdf::multi_kernel(sh.K, sh.ppt, sh.ab, sh.colour));
+    p.gridDim = dim3(grid_for(b, sh, c));
     p.blockDim = dim3(256);
     p.sharedMemBytes = 0;
     p.kernelParams = args;
@@ -409,15 +425,16 @@ tsdf_status tsdf_batch_fuse(tsdf_batch* b, const tsdf_fuse_item* items, uint32_t
   for (uint32_t i = 0; i < n_items; ++i) {
     const tsdf_fuse_item& it = items[i];
     if (!it.volume || !valid_camera(&it.camera)) return TSDF_ERR_INVALID_ARGUMENT;
-    if ((uint64_t)it.camera.width * it.camera.height > 0 && !it.depth_dev)
-      return TSDF_ERR_INVALID_ARGUMENT;
+    const bool pixels = (uint64_t)it.camera.width * it.camera.height > 0;
+    if (pixels && !it.depth_dev) return TSDF_ERR_INVALID_ARGUMENT;
+    if (pixels && it.volume->dev.colour && !it.rgba_dev) return TSDF_ERR_INVALID_ARGUMENT;
   }
   if (n_items == 0) return TSDF_OK;
   hipStream_t s = as_stream(hip_stream);
   poll_tuner(b);
   int cand = -1;
   const tsdf_batch_config c = next_config(b, &cand);
-  const uint32_t tw = c.tile_width, th = c.pixels_per_thread * (256u / tw);
+  const uint32_t tw = c.tile_width;
 
   // the ring slot: wait until the copy that last read it has run
   const int slot = b->next_slot;
@@ -430,42 +447,48 @@ tsdf_status tsdf_batch_fuse(tsdf_batch* b, const tsdf_fuse_item* items, uint32_t
   unsigned* tile_start = reinterpret_cast<unsigned*>(host + b->L.tile_start);
   tsdf::BatchItem* out = reinterpret_cast<tsdf::BatchItem*>(host + b->L.items);
 
-  // counting sort by K
-  uint32_t count[tsdf::kBatchKSlots] = {0};
-  for (uint32_t i = 0; i < n_items; ++i) ++count[band_half(items[i].volume->params)];
+  // counting sort by group (band width, colour)
+  auto group_of = [](const tsdf_fuse_item& it) {
+    return tsdf::batch_group(band_half(it.volume->params), it.volume->dev.colour != nullptr);
+  };
+  uint32_t count[tsdf::kBatchGroups] = {0};
+  for (uint32_t i = 0; i < n_items; ++i) ++count[group_of(items[i])];
   uint32_t k_mask = 0, acc = 0;
-  for (int K = 0; K < tsdf::kBatchKSlots; ++K) {
-    k_begin[K] = acc;
-    acc += count[K];
-    if (count[K]) k_mask |= 1u << K;
+  for (int g = 0; g < tsdf::kBatchGroups; ++g) {
+    k_begin[g] = acc;
+    acc += count[g];
+    if (count[g]) k_mask |= 1u << g;
   }
-  uint32_t cursor[tsdf::kBatchKSlots];
-  for (int K = 0; K < tsdf::kBatchKSlots; ++K) cursor[K] = k_begin[K];
+  k_begin[tsdf::kBatchGroups] = acc;
+  uint32_t cursor[tsdf::kBatchGroups];
+  for (int g = 0; g < tsdf::kBatchGroups; ++g) cursor[g] = k_begin[g];
   b->order.resize(n_items);
-  for (uint32_t i = 0; i < n_items; ++i) b->order[cursor[band_half(items[i].volume->params)]++] = i;
+  for (uint32_t i = 0; i < n_items; ++i) b->order[cursor[group_of(items[i])]++] = i;
 
   uint64_t tiles = 0;
   double pixels = 0.0;
-  uint32_t k_tiles[tsdf::kBatchKSlots] = {0};
+  uint32_t k_tiles[tsdf::kBatchGroups] = {0};
   for (uint32_t j = 0; j < n_items; ++j) {
     const tsdf_fuse_item& it = items[b->order[j]];
+    const int g = group_of(it);
+    const uint32_t th = (uint32_t)shape_of(g, c).ppt * (256u / tw);
     tsdf::BatchItem& bi = out[j];
     std::memset(&bi, 0, sizeof(bi));
     bi.vol = it.volume->dev;
     bi.wp = walk_params(it.volume);
-    bi.fr = frame_dev(it.depth_dev, &it.camera);
+    bi.fr = frame_dev(it.depth_dev, &it.camera, it.volume->dev.colour ? it.rgba_dev : nullptr);
     const uint32_t tx = (it.camera.width + tw - 1) / tw;
     const uint32_t ty = (it.camera.height + th - 1) / th;
     bi.tiles_x = tx;
     tile_start[j] = (uint32_t)tiles;
     tiles += (uint64_t)tx * ty;
-    k_tiles[bi.wp.K] += tx * ty;
+    k_tiles[g] += tx * ty;
     pixels += (double)it.camera.width * it.camera.height;
     if (tiles > 0x7FFFFFFFull) return TSDF_ERR_INVALID_ARGUMENT;  // tile indices stay in 31 bits
   }
   tile_start[n_items] = (uint32_t)tiles;
-  for (int K = 0; K <= TSDF_MAX_BAND_HALF; ++K)
-    if (k_tiles[K] == 0) k_mask &= ~(1u << K);
+  for (int g = 0; g < tsdf::kBatchGroups; ++g)
+    if (k_tiles[g] == 0) k_mask &= ~(1u << g);
 
   const size_t bytes = (size_t)b->L.items + (size_t)n_items * sizeof(tsdf::BatchItem);
   if (hipMemcpyAsync(b->ws, host, bytes, hipMemcpyHostToDevice, s) != hipSuccess) return TSDF_ERR_HIP;

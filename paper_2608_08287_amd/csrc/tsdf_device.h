@@ -160,7 +160,10 @@ __device__ __forceinline__ void set_flag(DevCounters* c, unsigned f) {
 // ---------------------------------------------------------------------------
 // Section 2.3: find or insert one key.  Converged step loop over the busy lanes.
 // Returns the pool index, kBlockPoolFull, kBlockTableFull, or (lookup only)
-// kBlockTableFull for a key that is absent.
+// kBlockTableFull for a key that is absent.  In a slot-index volume (Section 6,
+// "Deriving the location from the slot") the pool index is the slot where the
+// key sits, so a lane that finds its key, or loses the exchange to it, is done
+// at once; the winner still counts the block and lists it for extraction.
 // ---------------------------------------------------------------------------
 
 template <bool kInsert>
@@ -226,7 +229,10 @@ __device__ int resolve_key(const VolumeDev& vol, unsigned long long want, bool a
         slot = at_slot;
         e = vol.table + slot;
         if (is_key) {
-          if (at_block != kBlockPublishing) {
+          if (vol.slot_index) {  // the slot is the block: nothing to wait for
+            result = (int)slot;
+            busy = false;
+          } else if (at_block != kBlockPublishing) {
             result = at_block;
             busy = false;
           } else {
@@ -237,7 +243,12 @@ __device__ int resolve_key(const VolumeDev& vol, unsigned long long want, bool a
           if (prev == kEmptyKey) {
             won = true;
           } else if (prev == want) {
-            waiting = true;
+            if (vol.slot_index) {
+              result = (int)slot;
+              busy = false;
+            } else {
+              waiting = true;
+            }
           } else {  // another key took the slot: keep probing after it
             ++probes;
             slot = (slot + 1 == C) ? 0u : slot + 1;
@@ -263,8 +274,10 @@ __device__ int resolve_key(const VolumeDev& vol, unsigned long long want, bool a
         const unsigned idx = base + rank_in(wmask);
         int pub;
         if (idx < vol.pool_capacity) {
-          vol.block_keys[idx] = want;  // read only after the launch: no fence needed
-          pub = (int)idx;
+          // read only after the launch: no fence needed
+          vol.block_keys[idx] = want;
+          if (vol.slot_index) vol.alloc_list[idx] = slot;
+          pub = vol.slot_index ? (int)slot : (int)idx;
         } else {
           pub = kBlockPoolFull;
           add_u32(&vol.ctr->keys_pool_overflow, 1u);
@@ -373,16 +386,22 @@ __device__ __forceinline__ FrameDev pick_frame(const FrameBatch<NB>& fb, unsigne
 // for 4 waves per SIMD costs a few spilled dwords and measures faster.
 constexpr int waves_per_eu_for(int F) { return F == 2 ? 4 : 1; }
 
+// Accumulator floats per block: sums and counts in the pool's row layout,
+// then (colour volumes) the red, green and blue sums in the colour layout.
+constexpr unsigned acc_block_floats(bool colour) {
+  return colour ? kBlockFloats + kColourFloats : kBlockFloats;
+}
+
 // LDS of one tile: the key set (phases 1-2) shares its space with the
 // accumulator of AB blocks (phase 3).
-template <int AB>
+template <int AB, bool kColour = false>
 struct TileShared {
   union {
     struct {
       unsigned long long keys[kSetCap];
       unsigned n;  // distinct keys in the set
     } set;
-    float acc[AB * kBlockFloats];
+    float acc[AB * acc_block_floats(kColour)];
   } u;
   int blockd[kSetCap];
   unsigned short dense[kSetCap];
@@ -395,11 +414,11 @@ struct TileShared {
 // Frames with width 0 are empty.  Every thread of the workgroup must call it;
 // it begins with a workgroup barrier, so a persistent workgroup may call it
 // tile after tile.
-template <int K, int F, int AB, FuseMode kMode>
+template <int K, int F, int AB, FuseMode kMode, bool kColour = false>
 __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams& wp,
                                           const FrameDev (&frs)[F], const unsigned (&px)[F],
                                           const unsigned (&py)[F], unsigned shard,
-                                          TileShared<AB>& sh) {
+                                          TileShared<AB, kColour>& sh) {
   constexpr int NS = 2 * K + 1;
   constexpr bool kInsert = kMode != FuseMode::kIntegrate;
   constexpr bool kAccumulate = kMode != FuseMode::kAllocate;
@@ -410,7 +429,8 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
   unsigned short* const s_dense = sh.dense;   // dense block id per set slot
   unsigned short* const s_list = sh.list;     // set slot per dense block id
   float* const s_acc = sh.u.acc;              // AB blocks in the pool's own layout
-  constexpr unsigned kAccSlots = AB * kBlockFloats;
+  constexpr unsigned kAccStride = acc_block_floats(kColour);
+  constexpr unsigned kAccSlots = AB * kAccStride;
 
   const unsigned tid = threadIdx.x;
   __syncthreads();  // the previous tile of a persistent workgroup is done with the LDS
@@ -418,11 +438,14 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
   if (tid == 0) *s_n = 0;
 
   float d[F];
+  unsigned rgb[F];  // colour volumes: the pixel's packed colour
 #pragma unroll
   for (int fi = 0; fi < F; ++fi) {
     const FrameDev& fr = frs[fi];
     const bool inside = px[fi] < fr.width && py[fi] < fr.height;
-    d[fi] = inside ? fr.depth[(size_t)py[fi] * fr.width + px[fi]] : 0.0f;
+    const size_t pix = (size_t)py[fi] * fr.width + px[fi];
+    d[fi] = inside ? fr.depth[pix] : 0.0f;
+    rgb[fi] = (kColour && inside) ? fr.rgba[pix] : 0u;
   }
   __syncthreads();
 
@@ -557,6 +580,12 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
           float* bp = vol.voxels + (size_t)blk * kBlockFloats;
           add_f32(bp + pool_tsdf_index(loc), smp.val);
           add_f32(bp + pool_weight_index(loc), 1.0f);
+          if (kColour) {
+            float* cp = vol.colour + (size_t)blk * kColourFloats;
+#pragma unroll
+            for (unsigned c = 0; c < 3; ++c)
+              add_f32(cp + colour_index(loc, c), (float)((rgb[fi] >> (8 * c)) & 255u));
+          }
         } else {
           ++n_drop;
         }
@@ -581,11 +610,18 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
             float dk = d[fi];
             asm volatile("" : "+v"(dk));
             const float v = walk_sample(fr, wp, dk, a, b, s - K).val;
-            float* ab = &s_acc[db * kBlockFloats];
+            float* ab = &s_acc[db * kAccStride];
             __hip_atomic_fetch_add(ab + pool_tsdf_index(w & 511u), v, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
             __hip_atomic_fetch_add(ab + pool_weight_index(w & 511u), 1.0f, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (kColour) {
+#pragma unroll
+              for (unsigned c = 0; c < 3; ++c)
+                __hip_atomic_fetch_add(ab + kBlockFloats + colour_index(w & 511u, c),
+                                       (float)((rgb[fi] >> (8 * c)) & 255u), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
           }
         }
       }
@@ -597,7 +633,7 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
       // flush pays one LDS latency per block rather than one per float.
       for (unsigned bb = 0; bb < AB && lo + bb < n_keys; ++bb) {
         const int blk = s_blockd[lo + bb];  // uniform across the workgroup
-        float* ab = &s_acc[bb * kBlockFloats];
+        float* ab = &s_acc[bb * kAccStride];
         float v[4], cn[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -605,11 +641,23 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
           v[q] = ab[i];
           cn[q] = ab[(i & ~15u) + 8u + (i & 7u)];  // this voxel's count
         }
+        // colour sums: six floats per thread; a zero sum (a black or untouched
+        // voxel) needs no update, so no count is needed to decide
+        constexpr int kCq = kColour ? (int)(kColourFloats / kThreads) : 0;
+        float cv[kCq > 0 ? kCq : 1];
+#pragma unroll
+        for (int q = 0; q < kCq; ++q) cv[q] = ab[kBlockFloats + q * kThreads + tid];
         if (blk >= 0) {
           float* bp = vol.voxels + (size_t)blk * kBlockFloats;
 #pragma unroll
           for (int q = 0; q < 4; ++q)
             if (cn[q] != 0.0f) add_f32(bp + q * kThreads + tid, v[q]);
+          if (kColour) {
+            float* cp = vol.colour + (size_t)blk * kColourFloats;
+#pragma unroll
+            for (int q = 0; q < kCq; ++q)
+              if (cv[q] != 0.0f) add_f32(cp + q * kThreads + tid, cv[q]);
+          }
         } else if (tid & 8u) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) n_drop += (unsigned)cn[q];
@@ -618,6 +666,9 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
 #pragma unroll
         for (int q = 0; q < 4; ++q)
           if (cn[q] != 0.0f) ab[q * kThreads + tid] = 0.0f;
+#pragma unroll
+        for (int q = 0; q < kCq; ++q)
+          if (cv[q] != 0.0f) ab[kBlockFloats + q * kThreads + tid] = 0.0f;
       }
       __syncthreads();
     }
@@ -658,11 +709,17 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
 // (frames past the batch are empty).  F > 1 sums the frames' contributions to a
 // tile before they reach the pool; NB > F puts several frames in one grid so
 // one frame's start-up overlaps another's pool updates.
-template <int K, int F, int NB, FuseMode kMode>
+// Colour volumes accumulate 2.5x the floats per block in LDS: 4 blocks per
+// pass keep the tile's LDS at 48 KiB.
+constexpr int kColourAccBlocks = 4;
+constexpr int acc_blocks_for(bool colour) { return colour ? kColourAccBlocks : kAccBlocks; }
+
+template <int K, int F, int NB, FuseMode kMode, bool kColour>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(waves_per_eu_for(F))))
 void fuse_kernel(VolumeDev vol, WalkParams wp, FrameBatch<NB> fb, unsigned n_frames,
                  unsigned tiles_x, unsigned n_tiles, int remap) {
-  __shared__ TileShared<kAccBlocks> sh;
+  constexpr int AB = acc_blocks_for(kColour);
+  __shared__ TileShared<AB, kColour> sh;
   const unsigned group = blockIdx.x / n_tiles;
   const unsigned tile = tile_of_group(blockIdx.x % n_tiles, n_tiles, remap != 0);
   const unsigned x = (tile % tiles_x) * kTileW + (threadIdx.x % kTileW);
@@ -677,7 +734,7 @@ void fuse_kernel(VolumeDev vol, WalkParams wp, FrameBatch<NB> fb, unsigned n_fra
     px[fi] = x;
     py[fi] = y;
   }
-  fuse_tile<K, F, kAccBlocks, kMode>(vol, wp, frs, px, py, blockIdx.x, sh);
+  fuse_tile<K, F, AB, kMode, kColour>(vol, wp, frs, px, py, blockIdx.x, sh);
 }
 
 // Many volumes, one frame each, in one persistent launch.  The grid is a
@@ -701,14 +758,15 @@ using ConstPtr = const __attribute__((address_space(4))) T*;
 // spill).  A 16-block accumulator allows two workgroups per CU: no cap.
 constexpr int multi_waves_per_eu(int ppt, int ab) { return ppt == 2 && ab <= 8 ? 4 : 1; }
 
-template <int K, int PPT, int AB>
+template <int K, int PPT, int AB, bool kColour>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(multi_waves_per_eu(PPT, AB))))
 void fuse_multi_kernel(BatchWork w, unsigned tw_log2) {
-  __shared__ TileShared<AB> sh;
+  __shared__ TileShared<AB, kColour> sh;
   const ConstPtr<unsigned> k_begin = (ConstPtr<unsigned>)w.k_begin;
   const ConstPtr<unsigned> tile_start = (ConstPtr<unsigned>)w.tile_start;
   const ConstPtr<BatchItem> items = (ConstPtr<BatchItem>)w.items;
-  const unsigned first = k_begin[K], last = k_begin[K + 1];
+  constexpr int kGroup = batch_group(K, kColour);
+  const unsigned first = k_begin[kGroup], last = k_begin[kGroup + 1];
   if (first >= last) return;
   const unsigned t_end = tile_start[last];
   const unsigned lx = threadIdx.x & ((1u << tw_log2) - 1u);
@@ -734,24 +792,28 @@ void fuse_multi_kernel(BatchWork w, unsigned tw_log2) {
       px[p] = x;
       py[p] = y0 + p * rows;
     }
-    fuse_tile<K, PPT, AB, FuseMode::kFused>(it.vol, it.wp, frs, px, py, blockIdx.x, sh);
+    fuse_tile<K, PPT, AB, FuseMode::kFused, kColour>(it.vol, it.wp, frs, px, py, blockIdx.x, sh);
   }
 }
 
 template <int K>
-const void* multi_kernel_k(int pixels_per_thread, int acc_blocks) {
+const void* multi_kernel_k(int pixels_per_thread, int acc_blocks, bool colour) {
+  if (colour)  // one shape: 16x16 tiles' single pixels, 4 blocks per LDS pass
+    return pixels_per_thread == 1 && acc_blocks == kColourAccBlocks
+               ? reinterpret_cast<const void*>(&fuse_multi_kernel<K, 1, kColourAccBlocks, true>)
+               : nullptr;
   if (pixels_per_thread == 1) {
     switch (acc_blocks) {
-      case 4: return reinterpret_cast<const void*>(&fuse_multi_kernel<K, 1, 4>);
-      case 8: return reinterpret_cast<const void*>(&fuse_multi_kernel<K, 1, 8>);
-      case 16: return reinterpret_cast<const void*>(&fuse_multi_kernel<K, 1, 16>);
+      case 4: return reinterpret_cast<const void*>(&fuse_multi_kernel<K, 1, 4, false>);
+      case 8: return reinterpret_cast<const void*>(&fuse_multi_kernel<K, 1, 8, false>);
+      case 16: return reinterpret_cast<const void*>(&fuse_multi_kernel<K, 1, 16, false>);
       default: return nullptr;
     }
   }
   if (pixels_per_thread == 2) {
     switch (acc_blocks) {
-      case 8: return reinterpret_cast<const void*>(&fuse_multi_kernel<K, 2, 8>);
-      case 16: return reinterpret_cast<const void*>(&fuse_multi_kernel<K, 2, 16>);
+      case 8: return reinterpret_cast<const void*>(&fuse_multi_kernel<K, 2, 8, false>);
+      case 16: return reinterpret_cast<const void*>(&fuse_multi_kernel<K, 2, 16, false>);
       default: return nullptr;
     }
   }
@@ -762,7 +824,7 @@ const void* multi_kernel_k(int pixels_per_thread, int acc_blocks) {
 // (F x (2K+1) registers) in registers: 4 for bands of up to 9 samples, 2 above.
 constexpr int max_frames_for(int K) { return 2 * K + 1 <= 9 ? 4 : 2; }
 
-template <int K, int F, int NB>
+template <int K, int F, int NB, bool kColour>
 hipError_t launch_fuse_kf(VolumeDev vol, const WalkParams& wp, const FrameDev* frames, int n,
                           FuseMode mode, bool remap, hipStream_t s) {
   FrameBatch<NB> fb;
@@ -783,22 +845,23 @@ hipError_t launch_fuse_kf(VolumeDev vol, const WalkParams& wp, const FrameDev* f
   if constexpr (F == 1 && NB == 1) {
     switch (mode) {
       case FuseMode::kFused:
-        hipLaunchKernelGGL((fuse_kernel<K, 1, 1, FuseMode::kFused>), grid, block, 0, s, vol, wp, fb,
-                           (unsigned)n, tx, n_tiles, (int)remap);
+        hipLaunchKernelGGL((fuse_kernel<K, 1, 1, FuseMode::kFused, kColour>), grid, block, 0, s,
+                           vol, wp, fb, (unsigned)n, tx, n_tiles, (int)remap);
         break;
-      case FuseMode::kAllocate:
-        hipLaunchKernelGGL((fuse_kernel<K, 1, 1, FuseMode::kAllocate>), grid, block, 0, s, vol, wp,
-                           fb, (unsigned)n, tx, n_tiles, (int)remap);
+      case FuseMode::kAllocate:  // allocation touches no accumulator
+        hipLaunchKernelGGL((fuse_kernel<K, 1, 1, FuseMode::kAllocate, false>), grid, block, 0, s,
+                           vol, wp, fb, (unsigned)n, tx, n_tiles, (int)remap);
         break;
       case FuseMode::kIntegrate:
-        hipLaunchKernelGGL((fuse_kernel<K, 1, 1, FuseMode::kIntegrate>), grid, block, 0, s, vol,
-                           wp, fb, (unsigned)n, tx, n_tiles, (int)remap);
+        hipLaunchKernelGGL((fuse_kernel<K, 1, 1, FuseMode::kIntegrate, kColour>), grid, block, 0,
+                           s, vol, wp, fb, (unsigned)n, tx, n_tiles, (int)remap);
         break;
     }
   } else {
     (void)mode;
-    hipLaunchKernelGGL((fuse_kernel<K, F, NB, FuseMode::kFused>), grid, block, 0, s, vol, wp, fb,
-                       (unsigned)n, tx, n_tiles, (int)remap);
+    static_assert(!kColour, "colour frames are fused one per launch or through batches");
+    hipLaunchKernelGGL((fuse_kernel<K, F, NB, FuseMode::kFused, false>), grid, block, 0, s, vol,
+                       wp, fb, (unsigned)n, tx, n_tiles, (int)remap);
   }
   return hipGetLastError();
 }
@@ -810,13 +873,17 @@ hipError_t launch_fuse_k(VolumeDev vol, const WalkParams& wp, const FrameDev* fr
                          int frames_per_group, FuseMode mode, bool remap, hipStream_t s) {
   if (n < 1 || n > kMaxBatchFrames) return hipErrorInvalidValue;
   if (mode != FuseMode::kFused && n != 1) return hipErrorInvalidValue;
-  if (n == 1) return launch_fuse_kf<K, 1, 1>(vol, wp, frames, 1, mode, remap, s);
+  const bool colour = vol.colour != nullptr;
+  if (n == 1)
+    return colour ? launch_fuse_kf<K, 1, 1, true>(vol, wp, frames, 1, mode, remap, s)
+                  : launch_fuse_kf<K, 1, 1, false>(vol, wp, frames, 1, mode, remap, s);
+  if (colour) return hipErrorInvalidValue;
   switch (frames_per_group) {
-    case 1: return launch_fuse_kf<K, 1, kMaxBatchFrames>(vol, wp, frames, n, mode, remap, s);
-    case 2: return launch_fuse_kf<K, 2, kMaxBatchFrames>(vol, wp, frames, n, mode, remap, s);
+    case 1: return launch_fuse_kf<K, 1, kMaxBatchFrames, false>(vol, wp, frames, n, mode, remap, s);
+    case 2: return launch_fuse_kf<K, 2, kMaxBatchFrames, false>(vol, wp, frames, n, mode, remap, s);
     case 4:
       if constexpr (max_frames_for(K) >= 4)
-        return launch_fuse_kf<K, 4, kMaxBatchFrames>(vol, wp, frames, n, mode, remap, s);
+        return launch_fuse_kf<K, 4, kMaxBatchFrames, false>(vol, wp, frames, n, mode, remap, s);
       return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }

@@ -8,8 +8,8 @@ hipError_t launch_fuse_band3(VolumeDev vol, const WalkParams& wp, const FrameDev
   return launch_fuse_k<3>(vol, wp, frames, n, frames_per_group, mode, remap, s);
 }
 
-const void* multi_kernel_band3(int pixels_per_thread, int acc_blocks) {
-  return multi_kernel_k<3>(pixels_per_thread, acc_blocks);
+const void* multi_kernel_band3(int pixels_per_thread, int acc_blocks, bool colour) {
+  return multi_kernel_k<3>(pixels_per_thread, acc_blocks, colour);
 }
 
 }  // namespace tsdf

@@ -8,8 +8,8 @@ hipError_t launch_fuse_band6(VolumeDev vol, const WalkParams& wp, const FrameDev
   return launch_fuse_k<6>(vol, wp, frames, n, frames_per_group, mode, remap, s);
 }
 
-const void* multi_kernel_band6(int pixels_per_thread, int acc_blocks) {
-  return multi_kernel_k<6>(pixels_per_thread, acc_blocks);
+const void* multi_kernel_band6(int pixels_per_thread, int acc_blocks, bool colour) {
+  return multi_kernel_k<6>(pixels_per_thread, acc_blocks, colour);
 }
 
 }  // namespace tsdf

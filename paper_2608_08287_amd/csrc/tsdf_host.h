@@ -46,9 +46,11 @@ inline bool valid_camera(const tsdf_camera* c) {
   return true;
 }
 
-inline tsdf::FrameDev frame_dev(const float* depth_dev, const tsdf_camera* cam) {
+inline tsdf::FrameDev frame_dev(const float* depth_dev, const tsdf_camera* cam,
+                                const uint32_t* rgba_dev = nullptr) {
   tsdf::FrameDev f;
   f.depth = depth_dev;
+  f.rgba = rgba_dev;
   f.width = cam->width;
   f.height = cam->height;
   f.cx = cam->cx;

@@ -61,17 +61,33 @@ __host__ __device__ constexpr unsigned pool_weight_index(unsigned loc) {
   return (loc >> 3) * 16u + 8u + (loc & 7u);
 }
 
+// Colour volumes: per block 64 rows of 24 floats (8 red, 8 green, 8 blue sums).
+constexpr unsigned kColourFloats = 1536;
+__host__ __device__ constexpr unsigned colour_index(unsigned loc, unsigned channel) {
+  return (loc >> 3) * 24u + channel * 8u + (loc & 7u);
+}
+
 struct VolumeDev {
   DevCounters* ctr;
   TableEntry* table;
-  unsigned long long* block_keys;
-  float* voxels;  // pool_capacity * kBlockFloats
+  unsigned long long* block_keys;  // key of the i-th allocated block
+  float* voxels;                   // pool_capacity * kBlockFloats
+  unsigned* alloc_list;            // slot-index volumes: pool index of the i-th allocated block
+  float* colour;                   // colour volumes: pool_capacity * kColourFloats
   unsigned table_capacity;
   unsigned pool_capacity;
+  unsigned slot_index;             // 1: a block's pool index is its table slot
+  unsigned pad;
 };
+
+// Pool index of the i-th allocated block.
+__host__ __device__ inline unsigned allocated_block(const VolumeDev& vol, unsigned i) {
+  return vol.slot_index ? vol.alloc_list[i] : i;
+}
 
 struct FrameDev {
   const float* depth;
+  const unsigned* rgba;    // colour volumes: packed 8-bit red | green << 8 | blue << 16
   unsigned width, height;
   float cx, cy, ifx, ify;  // 1/fx, 1/fy rounded once to float32
   float R[9];              // camera->world rotation, row-major
@@ -100,10 +116,12 @@ struct BatchItem {
 static_assert(sizeof(BatchItem) % 16 == 0, "items stay 16-byte aligned");
 
 // The work list of one batch launch, in the device workspace.  Items are
-// sorted by band half-width K; the items of K are k_begin[K] .. k_begin[K+1]-1
-// and their tiles are the global tile indices tile_start[first] ..
-// tile_start[last]-1 (tile_start is the exclusive prefix sum of tile counts).
-constexpr int kBatchKSlots = 16;  // k_begin entries (K = 0 .. 9 used)
+// sorted by group g = batch_group(K, colour) (band half-width K, colour or
+// not); the items of g are k_begin[g] .. k_begin[g+1]-1 and their tiles are
+// the global tile indices tile_start[first] .. tile_start[last]-1 (tile_start
+// is the exclusive prefix sum of tile counts).
+constexpr int kBatchGroups = 32;  // k_begin entries (groups 0 .. 19 used)
+__host__ __device__ constexpr int batch_group(int K, bool colour) { return K + (colour ? 10 : 0); }
 struct BatchWork {
   const unsigned* k_begin;
   const unsigned* tile_start;
@@ -138,16 +156,17 @@ hipError_t launch_fuse_band8(VolumeDev vol, const WalkParams& wp, const FrameDev
 // pixels_per_thread (1 or 2) pixels per thread and accumulating acc_blocks
 // (4, 8 or 16; 8 or 16 with 2 pixels) blocks in LDS per pass, as a host
 // function pointer for hipLaunchKernel / graph kernel nodes; nullptr for
-// other values.  Its arguments are (BatchWork work, unsigned tile_width_log2).
-const void* multi_kernel(int K, int pixels_per_thread, int acc_blocks);
-const void* multi_kernel_band1(int pixels_per_thread, int acc_blocks);
-const void* multi_kernel_band2(int pixels_per_thread, int acc_blocks);
-const void* multi_kernel_band3(int pixels_per_thread, int acc_blocks);
-const void* multi_kernel_band4(int pixels_per_thread, int acc_blocks);
-const void* multi_kernel_band5(int pixels_per_thread, int acc_blocks);
-const void* multi_kernel_band6(int pixels_per_thread, int acc_blocks);
-const void* multi_kernel_band7(int pixels_per_thread, int acc_blocks);
-const void* multi_kernel_band8(int pixels_per_thread, int acc_blocks);
+// other values.  Colour volumes have one shape: 1 pixel, 4 blocks.  Its
+// arguments are (BatchWork work, unsigned tile_width_log2).
+const void* multi_kernel(int K, int pixels_per_thread, int acc_blocks, bool colour);
+const void* multi_kernel_band1(int pixels_per_thread, int acc_blocks, bool colour);
+const void* multi_kernel_band2(int pixels_per_thread, int acc_blocks, bool colour);
+const void* multi_kernel_band3(int pixels_per_thread, int acc_blocks, bool colour);
+const void* multi_kernel_band4(int pixels_per_thread, int acc_blocks, bool colour);
+const void* multi_kernel_band5(int pixels_per_thread, int acc_blocks, bool colour);
+const void* multi_kernel_band6(int pixels_per_thread, int acc_blocks, bool colour);
+const void* multi_kernel_band7(int pixels_per_thread, int acc_blocks, bool colour);
+const void* multi_kernel_band8(int pixels_per_thread, int acc_blocks, bool colour);
 // out[i] = the sticky status bits of the volume whose counters ctrs[i] points
 // to (0 for a null pointer), i < n.  ctrs and out may be host-mapped memory.
 hipError_t launch_gather_status(DevCounters* const* ctrs, unsigned n, unsigned* out, hipStream_t s);
@@ -159,5 +178,6 @@ hipError_t launch_mesh(VolumeDev vol, const WalkParams& wp, unsigned n_blocks, u
 hipError_t launch_insert_blocks(VolumeDev vol, const int* coords, unsigned n, hipStream_t s);
 hipError_t launch_extract(VolumeDev vol, unsigned n_blocks, unsigned long long* keys,
                           float* tsdf, float* weight, hipStream_t s);
+hipError_t launch_extract_colour(VolumeDev vol, unsigned n_blocks, float* rgb, hipStream_t s);
 
 }  // namespace tsdf

@@ -38,15 +38,23 @@ __global__ __launch_bounds__(256) void fill_u32_kernel(unsigned* p, unsigned val
   for (size_t i = n4 * 4 + blockIdx.x * 256u + threadIdx.x; i < n; i += stride) p[i] = value;
 }
 
-// Zero the pool blocks handed out since the last reset (the others are zero).
+// Zero the pool blocks handed out since the last reset (the others are zero),
+// and their colour sums.
 __global__ __launch_bounds__(256) void reset_used_kernel(VolumeDev vol) {
   unsigned used = *(volatile unsigned*)&vol.ctr->block_count;
   used = used < vol.pool_capacity ? used : vol.pool_capacity;
-  const size_t n4 = (size_t)used * (kBlockFloats / 4);
+  constexpr unsigned kQuads = kBlockFloats / 4, kColourQuads = kColourFloats / 4;
   const size_t stride = (size_t)gridDim.x * 256u;
-  float4* v4 = reinterpret_cast<float4*>(vol.voxels);
   const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-  for (size_t i = blockIdx.x * 256u + threadIdx.x; i < n4; i += stride) v4[i] = z;
+  float4* v4 = reinterpret_cast<float4*>(vol.voxels);
+  for (size_t i = blockIdx.x * 256u + threadIdx.x; i < (size_t)used * kQuads; i += stride)
+    v4[(size_t)allocated_block(vol, (unsigned)(i / kQuads)) * kQuads + i % kQuads] = z;
+  if (vol.colour) {
+    float4* c4 = reinterpret_cast<float4*>(vol.colour);
+    for (size_t i = blockIdx.x * 256u + threadIdx.x; i < (size_t)used * kColourQuads; i += stride)
+      c4[(size_t)allocated_block(vol, (unsigned)(i / kColourQuads)) * kColourQuads +
+         i % kColourQuads] = z;
+  }
 }
 
 // One thread per x-row of 8 voxels: read the row's 64-byte segment, write the
@@ -58,7 +66,9 @@ __global__ __launch_bounds__(256) void extract_kernel(VolumeDev vol, unsigned n_
   const size_t stride = (size_t)gridDim.x * 256u;
   const float4* v4 = reinterpret_cast<const float4*>(vol.voxels);
   for (size_t r = blockIdx.x * 256u + threadIdx.x; r < n_rows; r += stride) {
-    const float4 s0 = v4[4 * r], s1 = v4[4 * r + 1], w0 = v4[4 * r + 2], w1 = v4[4 * r + 3];
+    const size_t src = (size_t)allocated_block(vol, (unsigned)(r / 64)) * 64 + r % 64;
+    const float4 s0 = v4[4 * src], s1 = v4[4 * src + 1], w0 = v4[4 * src + 2],
+                 w1 = v4[4 * src + 3];
     if (tsdf) {
       float4 m0, m1;
       m0.x = w0.x > 0.f ? s0.x / w0.x : 0.f;
@@ -80,6 +90,22 @@ __global__ __launch_bounds__(256) void extract_kernel(VolumeDev vol, unsigned n_
   if (keys)
     for (size_t i = blockIdx.x * 256u + threadIdx.x; i < n_blocks; i += stride)
       keys[i] = vol.block_keys[i];
+}
+
+// One thread per voxel: its mean colour = colour sums / weight, 3 floats.
+__global__ __launch_bounds__(256) void extract_colour_kernel(VolumeDev vol, unsigned n_blocks,
+                                                             float* rgb) {
+  const size_t n = (size_t)n_blocks * TSDF_BLOCK_VOXELS;
+  const size_t stride = (size_t)gridDim.x * 256u;
+  for (size_t v = blockIdx.x * 256u + threadIdx.x; v < n; v += stride) {
+    const unsigned loc = (unsigned)(v % TSDF_BLOCK_VOXELS);
+    const size_t blk = allocated_block(vol, (unsigned)(v / TSDF_BLOCK_VOXELS));
+    const float w = vol.voxels[blk * kBlockFloats + pool_weight_index(loc)];
+    const float* cp = vol.colour + blk * kColourFloats;
+#pragma unroll
+    for (unsigned c = 0; c < 3; ++c)
+      rgb[v * 3 + c] = w > 0.f ? cp[colour_index(loc, c)] / w : 0.f;
+  }
 }
 
 unsigned grid_for(size_t work, unsigned cap) {
@@ -137,16 +163,16 @@ hipError_t launch_gather_status(DevCounters* const* ctrs, unsigned n, unsigned* 
   return hipGetLastError();
 }
 
-const void* multi_kernel(int K, int pixels_per_thread, int acc_blocks) {
+const void* multi_kernel(int K, int pixels_per_thread, int acc_blocks, bool colour) {
   switch (K) {
-    case 1: return multi_kernel_band1(pixels_per_thread, acc_blocks);
-    case 2: return multi_kernel_band2(pixels_per_thread, acc_blocks);
-    case 3: return multi_kernel_band3(pixels_per_thread, acc_blocks);
-    case 4: return multi_kernel_band4(pixels_per_thread, acc_blocks);
-    case 5: return multi_kernel_band5(pixels_per_thread, acc_blocks);
-    case 6: return multi_kernel_band6(pixels_per_thread, acc_blocks);
-    case 7: return multi_kernel_band7(pixels_per_thread, acc_blocks);
-    case 8: return multi_kernel_band8(pixels_per_thread, acc_blocks);
+    case 1: return multi_kernel_band1(pixels_per_thread, acc_blocks, colour);
+    case 2: return multi_kernel_band2(pixels_per_thread, acc_blocks, colour);
+    case 3: return multi_kernel_band3(pixels_per_thread, acc_blocks, colour);
+    case 4: return multi_kernel_band4(pixels_per_thread, acc_blocks, colour);
+    case 5: return multi_kernel_band5(pixels_per_thread, acc_blocks, colour);
+    case 6: return multi_kernel_band6(pixels_per_thread, acc_blocks, colour);
+    case 7: return multi_kernel_band7(pixels_per_thread, acc_blocks, colour);
+    case 8: return multi_kernel_band8(pixels_per_thread, acc_blocks, colour);
     default: return nullptr;
   }
 }
@@ -154,6 +180,13 @@ const void* multi_kernel(int K, int pixels_per_thread, int acc_blocks) {
 hipError_t launch_insert_blocks(VolumeDev vol, const int* coords, unsigned n, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(insert_blocks_kernel, dim3((n + 255) / 256), dim3(256), 0, s, vol, coords, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_extract_colour(VolumeDev vol, unsigned n_blocks, float* rgb, hipStream_t s) {
+  if (n_blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(extract_colour_kernel, dim3(grid_for((size_t)n_blocks * 512, 8192)),
+                     dim3(256), 0, s, vol, n_blocks, rgb);
   return hipGetLastError();
 }
 

@@ -128,8 +128,8 @@ __global__ __launch_bounds__(256) void mesh_kernel(VolumeDev vol, float v, float
   __shared__ unsigned s_scan[256];
   __shared__ unsigned s_base;
   const unsigned tid = threadIdx.x;
-  const unsigned blk = blockIdx.x;
-  const unsigned long long key = vol.block_keys[blk];
+  const unsigned blk = allocated_block(vol, blockIdx.x);
+  const unsigned long long key = vol.block_keys[blockIdx.x];
   const int bx = (int)(key >> 42) - (1 << 20);
   const int by = (int)((key >> 21) & ((1u << 21) - 1)) - (1 << 20);
   const int bz = (int)(key & ((1u << 21) - 1)) - (1 << 20);

@@ -168,7 +168,7 @@ tsdf_status launch_one(tsdf_server* s, uint32_t* launched) {
       s->done.emplace_back(q.tag, ss.failure);
       continue;
     }
-    s->items.push_back(tsdf_fuse_item{ss.vol, q.depth, q.cam});
+    s->items.push_back(tsdf_fuse_item{ss.vol, q.depth, nullptr, q.cam});
     L.sessions.push_back(q.session);
     L.tags.push_back(q.tag);
   }
@@ -280,7 +280,7 @@ tsdf_status tsdf_server_open(tsdf_server* s, const tsdf_volume_params* params,
                              uint32_t* session_out) {
   if (!s || !session_out) return TSDF_ERR_INVALID_ARGUMENT;
   const size_t bytes = tsdf_volume_bytes(params);
-  if (bytes == 0) return TSDF_ERR_INVALID_ARGUMENT;
+  if (bytes == 0 || (params->flags & TSDF_VOLUME_COLOUR)) return TSDF_ERR_INVALID_ARGUMENT;
   uint32_t id = 0;
   while (id < s->p.max_sessions && s->sessions[id].open) ++id;
   if (id == s->p.max_sessions) return TSDF_ERR_BUDGET;

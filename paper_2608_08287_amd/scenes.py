@@ -174,6 +174,42 @@ def render_depth(cam: Camera, scene: Sequence[object], noise_sigma=None,
     return depth.astype(np.float32).reshape(cam.height, cam.width)
 
 
+def render_rgbd(cam: Camera, scene: Sequence[object], colours: Sequence[Tuple[int, int, int]],
+                noise_sigma=None, seed: Optional[int] = None,
+                device="cpu") -> Tuple[np.ndarray, np.ndarray]:
+    """Depth as ``render_depth`` (same noise stream) and a registered colour
+    image: each pixel takes the 8-bit colour ``colours[i]`` of the primitive
+    its ray hits first, darkened to 5/8 on alternate cells of a 10 cm checker
+    in world coordinates (so colour varies across a surface).  Colour is
+    packed as uint32 red | green << 8 | blue << 16; rays that hit nothing are
+    black."""
+    d, o = _ray_dirs(cam, device)
+    t = torch.full((d.shape[0],), math.inf, dtype=torch.float64, device=device)
+    which = torch.full((d.shape[0],), -1, dtype=torch.int64, device=device)
+    for i, prim in enumerate(scene):
+        ti = _HITTERS[type(prim)](o, d, prim)
+        closer = ti < t
+        which = torch.where(closer, torch.full_like(which, i), which)
+        t = torch.minimum(t, ti)
+    depth = render_depth(cam, scene, noise_sigma, seed, device)
+    hit = torch.isfinite(t)
+    p = o + d * torch.where(hit, t, torch.zeros_like(t))[:, None]
+    cell = torch.floor(p / 0.1).sum(dim=1).remainder(2).cpu().numpy()
+    which = which.cpu().numpy()
+    hit = hit.cpu().numpy()
+    table = np.asarray(colours, dtype=np.int64).reshape(-1, 3)
+    rgb = np.where(hit[:, None], table[np.maximum(which, 0)], 0)
+    rgb = np.where(cell[:, None] == 1, (rgb * 5) // 8, rgb)
+    packed = (rgb[:, 0] | (rgb[:, 1] << 8) | (rgb[:, 2] << 16)).astype(np.uint32)
+    return depth, packed.reshape(cam.height, cam.width)
+
+
+def scene_colours(n: int, seed: int) -> List[Tuple[int, int, int]]:
+    """``n`` seeded 8-bit colours, channels uniform on 32..255."""
+    rng = np.random.default_rng(seed)
+    return [tuple(int(c) for c in rng.integers(32, 256, size=3)) for _ in range(n)]
+
+
 # ---------------------------------------------------------------------------
 # The workloads.  Each returns (cameras, depth frames) plus the volume sizes.
 # ---------------------------------------------------------------------------
@@ -248,6 +284,25 @@ def room_trajectory_workload(n_frames: int = 300, frames: Optional[Sequence[int]
         cams.append(cam)
         depth.append(render_depth(cam, scene, lambda z: 0.002 * z * z, 1000 + k, device))
     return Workload("room_orbit_640x480", 0.005, 0.02, table_capacity, pool_capacity, cams, depth)
+
+
+def room_trajectory_rgbd(n_frames: int = 300, frames: Optional[Sequence[int]] = None,
+                         device="cpu") -> Tuple[Workload, List[np.ndarray]]:
+    """The room orbit of ``room_trajectory_workload`` with a colour image per
+    frame (``render_rgbd``, object colours from ``scene_colours(21, 77)``);
+    the depth frames are the same arrays."""
+    scene = room_scene(1)
+    colours = scene_colours(len(scene), 77)
+    ks = range(n_frames) if frames is None else frames
+    cams, depth, rgba = [], [], []
+    for k in ks:
+        cam = orbit_camera(k, n_frames)
+        d, c = render_rgbd(cam, scene, colours, lambda z: 0.002 * z * z, 1000 + k, device)
+        cams.append(cam)
+        depth.append(d)
+        rgba.append(c)
+    w = Workload("room_orbit_rgbd_640x480", 0.005, 0.02, 1 << 20, 1 << 18, cams, depth)
+    return w, rgba
 
 
 def random_block_coords(n: int, seed: int, exclude_radius: int = 1 << 10) -> np.ndarray:

@@ -25,6 +25,7 @@ OK, ERR_INVALID_ARGUMENT, ERR_BUFFER_TOO_SMALL, ERR_POOL_EXHAUSTED, ERR_TABLE_FU
 FLAG_POOL_EXHAUSTED, FLAG_TABLE_FULL, FLAG_COORD_RANGE, FLAG_INTERNAL = 1, 2, 4, 8
 FUSE_DEFAULT, FUSE_TWO_PASS, FUSE_ALLOCATE_ONLY, FUSE_INTEGRATE_ONLY = 0, 1, 2, 3
 FUSE_XCD_REMAP = 0x100
+VOLUME_SLOT_INDEX, VOLUME_COLOUR = 0x1, 0x2
 
 
 def FUSE_BATCH(m: int) -> int:
@@ -38,6 +39,7 @@ EXPORTED_SYMBOLS = (
     "tsdf_reset_volume", "tsdf_fuse_frame", "tsdf_fuse_frame_ex", "tsdf_fuse_frames",
     "tsdf_query_status",
     "tsdf_extract_blocks", "tsdf_extract_mesh", "tsdf_insert_blocks", "tsdf_status_str",
+    "tsdf_fuse_frame_rgb", "tsdf_extract_colour",
     "tsdf_batch_workspace_bytes", "tsdf_batch_create", "tsdf_batch_destroy",
     "tsdf_batch_set_config", "tsdf_batch_autotune", "tsdf_batch_get_config",
     "tsdf_batch_candidates", "tsdf_batch_fuse",
@@ -54,7 +56,8 @@ BATCH_MAX_ITEMS = 65536
 
 class VolumeParams(C.Structure):
     _fields_ = [("voxel_size", C.c_float), ("trunc", C.c_float),
-                ("table_capacity", C.c_uint32), ("pool_capacity", C.c_uint32)]
+                ("table_capacity", C.c_uint32), ("pool_capacity", C.c_uint32),
+                ("flags", C.c_uint32)]
 
 
 class CameraC(C.Structure):
@@ -74,12 +77,14 @@ class StatsC(C.Structure):
 
 class LayoutC(C.Structure):
     _fields_ = [("counters", C.c_uint64), ("table", C.c_uint64), ("block_keys", C.c_uint64),
-                ("voxels", C.c_uint64), ("total_bytes", C.c_uint64),
-                ("table_capacity", C.c_uint32), ("pool_capacity", C.c_uint32)]
+                ("alloc_list", C.c_uint64), ("voxels", C.c_uint64), ("colour", C.c_uint64),
+                ("total_bytes", C.c_uint64), ("table_capacity", C.c_uint32),
+                ("pool_capacity", C.c_uint32), ("flags", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class FuseItemC(C.Structure):
-    _fields_ = [("volume", C.c_void_p), ("depth_dev", C.c_void_p), ("camera", CameraC)]
+    _fields_ = [("volume", C.c_void_p), ("depth_dev", C.c_void_p), ("rgba_dev", C.c_void_p),
+                ("camera", CameraC)]
 
 
 class BatchConfigC(C.Structure):
@@ -135,6 +140,10 @@ def lib() -> C.CDLL:
         L.tsdf_query_status.argtypes = [P, P, C.POINTER(StatsC)]
         L.tsdf_extract_blocks.restype = I
         L.tsdf_extract_blocks.argtypes = [P, P, U32, P, P, P, C.POINTER(U32)]
+        L.tsdf_fuse_frame_rgb.restype = I
+        L.tsdf_fuse_frame_rgb.argtypes = [P, P, P, C.POINTER(CameraC), U32, P]
+        L.tsdf_extract_colour.restype = I
+        L.tsdf_extract_colour.argtypes = [P, P, U32, P, C.POINTER(U32)]
         L.tsdf_extract_mesh.restype = I
         L.tsdf_extract_mesh.argtypes = [P, P, U32, P, P, C.POINTER(U32)]
         L.tsdf_insert_blocks.restype = I
@@ -206,8 +215,8 @@ def status_str(status: int) -> str:
 
 
 def volume_params(voxel_size: float, trunc: float, table_capacity: int,
-                  pool_capacity: int) -> VolumeParams:
-    return VolumeParams(voxel_size, trunc, table_capacity, pool_capacity)
+                  pool_capacity: int, flags: int = 0) -> VolumeParams:
+    return VolumeParams(voxel_size, trunc, table_capacity, pool_capacity, flags)
 
 
 def volume_bytes(p: VolumeParams) -> int:
@@ -316,8 +325,9 @@ class Volume(_VolumeCalls):
     """One resident TSDF volume in a device arena owned by this object."""
 
     def __init__(self, voxel_size: float, trunc: float, table_capacity: int, pool_capacity: int,
-                 device: str | torch.device = "cuda", stream: Optional[torch.cuda.Stream] = None):
-        self.params = volume_params(voxel_size, trunc, table_capacity, pool_capacity)
+                 device: str | torch.device = "cuda", stream: Optional[torch.cuda.Stream] = None,
+                 flags: int = 0):
+        self.params = volume_params(voxel_size, trunc, table_capacity, pool_capacity, flags)
         nbytes = volume_bytes(self.params)
         if nbytes == 0:
             raise TsdfError(ERR_INVALID_ARGUMENT, "volume parameters")
@@ -362,6 +372,24 @@ class Volume(_VolumeCalls):
         if st != OK:
             raise TsdfError(st, "tsdf_fuse_frame")
 
+    def fuse_rgb(self, depth: torch.Tensor, rgba: torch.Tensor, cam, flags: int = FUSE_DEFAULT,
+                 stream=None) -> None:
+        """Colour volumes: fuse a depth frame and its packed colour image
+        ((H, W) int32/uint32 holding red | green << 8 | blue << 16)."""
+        if depth.dtype != torch.float32 or not depth.is_cuda or not depth.is_contiguous():
+            raise TypeError("depth must be a contiguous float32 device tensor")
+        if rgba.dtype not in (torch.int32, torch.uint32) or not rgba.is_cuda or \
+                not rgba.is_contiguous() or rgba.shape != depth.shape:
+            raise TypeError("rgba must be a contiguous 32-bit device tensor shaped like depth")
+        c = cam if isinstance(cam, CameraC) else camera_struct(cam)
+        if depth.numel() != c.width * c.height:
+            raise ValueError("depth size does not match the camera")
+        st = lib().tsdf_fuse_frame_rgb(self._h, C.c_void_p(depth.data_ptr()),
+                                       C.c_void_p(rgba.data_ptr()), C.byref(c), flags,
+                                       _stream_ptr(stream))
+        if st != OK:
+            raise TsdfError(st, "tsdf_fuse_frame_rgb")
+
     def fuse_frames(self, depths: Sequence[torch.Tensor], cams, flags: int = 0, stream=None) -> None:
         """Enqueue the fusion of several frames with as few launches as possible."""
         n = len(depths)
@@ -387,6 +415,20 @@ class Volume(_VolumeCalls):
         st = lib().tsdf_insert_blocks(self._h, C.c_void_p(coords.data_ptr()), n, _stream_ptr(stream))
         if st != OK:
             raise TsdfError(st, "tsdf_insert_blocks")
+
+    def extract_colour(self, stream=None) -> torch.Tensor:
+        """Colour volumes: (n, 512, 3) float32 mean colours, blocks in extraction order."""
+        n = C.c_uint32(0)
+        L = lib()
+        st = L.tsdf_extract_colour(self._h, _stream_ptr(stream), 0, None, C.byref(n))
+        if st not in (OK, ERR_BUFFER_TOO_SMALL):
+            raise TsdfError(st, "tsdf_extract_colour")
+        out = torch.empty((n.value, BLOCK_VOXELS, 3), dtype=torch.float32, device=self.device)
+        st = L.tsdf_extract_colour(self._h, _stream_ptr(stream), n.value,
+                                   C.c_void_p(out.data_ptr()), C.byref(n))
+        if st != OK:
+            raise TsdfError(st, "tsdf_extract_colour")
+        return out
 
     def extract_mesh(self, stream=None) -> Mesh:
         """Marching-tetrahedra surface (tsdf_extract_mesh)."""
@@ -414,8 +456,24 @@ class Volume(_VolumeCalls):
         return self.pool_view()[:, :, 1, :]
 
     def block_keys_view(self) -> torch.Tensor:
+        """(P,) int64: the key of the i-th allocated block."""
         L = self.layout
         return self.arena[L.block_keys:L.block_keys + 8 * L.pool_capacity].view(torch.int64)
+
+    def alloc_list_view(self) -> torch.Tensor:
+        """(P,) int32: pool index of the i-th allocated block (slot-index volumes)."""
+        L = self.layout
+        if not (L.flags & VOLUME_SLOT_INDEX):
+            raise ValueError("not a slot-index volume")
+        return self.arena[L.alloc_list:L.alloc_list + 4 * L.pool_capacity].view(torch.int32)
+
+    def colour_view(self) -> torch.Tensor:
+        """(P, 64, 3, 8) float32 colour sums: [block, x-row, (r | g | b), x]."""
+        L = self.layout
+        if not (L.flags & VOLUME_COLOUR):
+            raise ValueError("not a colour volume")
+        return self.arena[L.colour:L.colour + 6144 * L.pool_capacity].view(torch.float32).view(
+            L.pool_capacity, 64, 3, 8)
 
 
 def fuse_frames(vol: Volume, depths: Sequence[torch.Tensor], cams: Sequence, flags: int = FUSE_DEFAULT,
@@ -492,10 +550,11 @@ class Batch:
                  float(t)) for c, t in zip(cfgs[:n.value], ns[:n.value])]
 
     def fuse(self, volumes: Sequence[Volume], depths: Sequence[torch.Tensor], cams,
-             flags: int = 0, stream=None) -> None:
-        """Enqueue one frame into each listed volume (a volume may repeat)."""
+             flags: int = 0, stream=None, rgbas: Optional[Sequence[torch.Tensor]] = None) -> None:
+        """Enqueue one frame into each listed volume (a volume may repeat);
+        colour volumes take their colour image from ``rgbas``."""
         n = len(volumes)
-        if len(depths) != n or len(cams) != n:
+        if len(depths) != n or len(cams) != n or (rgbas is not None and len(rgbas) != n):
             raise ValueError("one depth frame and one camera per item")
         if n > self.max_items:
             raise ValueError("more items than the batch was made for")
@@ -508,6 +567,7 @@ class Batch:
             it = self._items[i]
             it.volume = v.handle.value
             it.depth_dev = d.data_ptr()
+            it.rgba_dev = rgbas[i].data_ptr() if rgbas is not None and rgbas[i] is not None else None
             it.camera = c
         st = lib().tsdf_batch_fuse(self._h, self._items, n, flags, _stream_ptr(stream))
         if st != OK:

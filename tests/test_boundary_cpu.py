@@ -45,6 +45,24 @@ def test_volume_bytes_and_layout():
     # the configuration with a 2^20-slot table and a 2^18-block pool
     big = T.layout(T.volume_params(0.005, 0.02, 1 << 20, 1 << 18))
     assert big.total_bytes > (1 << 18) * 4096
+    # regions of the variants: none without flags
+    assert L.alloc_list == L.voxels and L.colour == L.total_bytes and L.flags == 0
+
+
+def test_variant_layouts():
+    P = 4096
+    slot = T.layout(T.volume_params(0.01, 0.04, P, P, T.VOLUME_SLOT_INDEX))
+    assert slot.table_capacity == P and slot.flags == T.VOLUME_SLOT_INDEX
+    assert slot.voxels - slot.alloc_list >= 4 * P and slot.alloc_list % 256 == 0
+    # table 0 means "as large as the pool" for slot-index volumes
+    assert T.layout(T.volume_params(0.01, 0.04, 0, P, T.VOLUME_SLOT_INDEX)).table_capacity == P
+    col = T.layout(T.volume_params(0.01, 0.04, 0, P, T.VOLUME_COLOUR))
+    assert col.total_bytes - col.colour == P * 1536 * 4 and col.colour % 256 == 0
+    both = T.layout(T.volume_params(0.01, 0.04, 0, P, T.VOLUME_SLOT_INDEX | T.VOLUME_COLOUR))
+    assert both.total_bytes == slot.total_bytes + P * 1536 * 4
+    for bad in (T.volume_params(0.01, 0.04, 2 * P, P, T.VOLUME_SLOT_INDEX),
+                T.volume_params(0.01, 0.04, 0, P, 0x4)):
+        assert T.volume_bytes(bad) == 0
 
 
 @pytest.mark.parametrize("vs,tr,C_,P", [
@@ -89,6 +107,10 @@ def test_null_handles_are_rejected():
     assert L.tsdf_query_status(None, None, C.byref(st)) == T.ERR_INVALID_ARGUMENT
     assert L.tsdf_extract_blocks(None, None, 0, None, None, None, C.byref(n)) == T.ERR_INVALID_ARGUMENT
     assert L.tsdf_insert_blocks(None, C.c_void_p(256), 1, None) == T.ERR_INVALID_ARGUMENT
+    assert L.tsdf_fuse_frame_rgb(None, C.c_void_p(256), C.c_void_p(256), C.byref(cam), 0,
+                                 None) == T.ERR_INVALID_ARGUMENT
+    assert L.tsdf_extract_colour(None, None, 0, None, C.byref(n)) == T.ERR_INVALID_ARGUMENT
+    assert L.tsdf_extract_mesh(None, None, 0, None, None, C.byref(n)) == T.ERR_INVALID_ARGUMENT
 
 
 def test_status_strings():
@@ -105,8 +127,8 @@ def test_batch_workspace_bytes():
     for n in (1, 2, 64, 1000, T.BATCH_MAX_ITEMS):
         b = L.tsdf_batch_workspace_bytes(n)
         assert b % 256 == 0 and b > prev
-        # k ranges + tile prefix sums + one 144-byte descriptor per item
-        assert b >= 256 + 4 * (n + 1) + 144 * n
+        # group ranges + tile prefix sums + one 176-byte descriptor per item
+        assert b >= 256 + 4 * (n + 1) + 176 * n
         prev = b
 
 

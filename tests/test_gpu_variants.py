@@ -1,0 +1,240 @@
+"""GPU parity of the paper's two design variants (Section 6): the slot-derived
+block index (a block's pool index is its table slot) and colour accumulation
+(three more sums per voxel).  Both against the oracle: keys and weights exact,
+TSDF means within 1e-5, colour sums exact (sums of 8-bit integers stay exact
+in float32), and the table and allocation invariants of the slot index.
+Every case prints its name first."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2608_08287_amd import scenes as S
+from paper_2608_08287_amd import tsdf as T
+
+from parity import EMPTY, assert_parity, assert_same_volume, log, result_of, table_arrays
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible: the HIP path has no CPU fallback")
+    T.lib()
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    log(f"[gpu] {request.node.name}")
+    yield
+    torch.cuda.synchronize()
+
+
+@pytest.fixture(scope="module")
+def room():
+    w, rgba = S.room_trajectory_rgbd(frames=[0, 1, 2, 150])
+    return w, rgba
+
+
+def slot_volume(w, P, flags=0):
+    return T.Volume(w.voxel_size, w.trunc, P, P, flags=T.VOLUME_SLOT_INDEX | flags)
+
+
+def assert_slot_invariants(vol: T.Volume, n_blocks: int):
+    keys, blocks = table_arrays(vol)
+    occ = np.nonzero(keys != EMPTY)[0]
+    assert np.array_equal(blocks[occ], occ.astype(np.int32)), "a block index is not its slot"
+    alloc = vol.alloc_list_view()[:n_blocks].cpu().numpy()
+    assert np.array_equal(np.sort(alloc), occ), "the allocation list is not the occupied slots"
+    bk = vol.block_keys_view()[:n_blocks].cpu().numpy().view(np.uint64)
+    assert np.array_equal(bk, keys[alloc]), "listed keys differ from the table"
+
+
+# ---------------------------------------------------------------------------
+# slot-derived block index
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("flags", [T.FUSE_DEFAULT, T.FUSE_TWO_PASS])
+def test_slot_index_single_frame(flags):
+    w = S.single_frame_workload()
+    o = O.fuse_workload(w)
+    vol = slot_volume(w, 8192)
+    vol.fuse(torch.from_numpy(w.depth[0]).cuda(), w.cameras[0], flags)
+    g = result_of(vol)
+    assert_parity(g, o)
+    assert g.stats.status == T.OK and g.stats.keys_pool_overflow == 0
+    assert_slot_invariants(vol, o.keys.size)
+
+
+def test_slot_index_room_frames_batched_and_multi(room):
+    w, _ = room
+    o = O.fuse_frames(w.voxel_size, w.trunc, 1 << 20, w.depth, w.cameras)
+    dev = [torch.from_numpy(d).cuda() for d in w.depth]
+    a = slot_volume(w, 1 << 18)
+    a.fuse_frames(dev, w.cameras)
+    assert_parity(result_of(a), o)
+    assert_slot_invariants(a, o.keys.size)
+    b = slot_volume(w, 1 << 18)
+    batch = T.Batch(4)
+    batch.set_config(T.BatchConfig(16, 2, 8, 0))
+    batch.fuse([b] * len(dev), dev, w.cameras)
+    assert_parity(result_of(b), o)
+    assert_slot_invariants(b, o.keys.size)
+
+
+def test_slot_index_reset_and_insert():
+    w = S.single_frame_workload()
+    o = O.fuse_workload(w)
+    vol = slot_volume(w, 8192)
+    d = torch.from_numpy(w.depth[0]).cuda()
+    vol.fuse(d, w.cameras[0])
+    vol.reset()
+    st = vol.stats()
+    assert st.blocks_total == 0 and st.points_valid == 0
+    assert float(vol.pool_view().abs().sum()) == 0.0, "reset left pool values behind"
+    vol.fuse(d, w.cameras[0])
+    assert_parity(result_of(vol), o)
+    # pre-inserted blocks take their slots too
+    coords = S.random_block_coords(500, seed=9)
+    v2 = slot_volume(w, 8192)
+    v2.insert_blocks(torch.from_numpy(coords).cuda())
+    v2.fuse(d, w.cameras[0])
+    o2 = O.fuse_frames(w.voxel_size, w.trunc, 8192, w.depth, w.cameras, coords)
+    assert_parity(result_of(v2), o2)
+    assert_slot_invariants(v2, o2.keys.size)
+
+
+def test_slot_index_mesh_equals_the_main_design():
+    w = S.single_frame_workload()
+    d = torch.from_numpy(w.depth[0]).cuda()
+    a = T.Volume(w.voxel_size, w.trunc, 8192, 4096)
+    b = slot_volume(w, 8192)
+    a.fuse(d, w.cameras[0])
+    b.fuse(d, w.cameras[0])
+    ma, mb = a.extract_mesh(), b.extract_mesh()
+
+    def ordered(m):
+        ids = m.ids.cpu().numpy().view(np.uint64)
+        o = np.lexsort((ids[:, 1], ids[:, 0]))
+        return ids[o], m.verts.cpu().numpy()[o]
+
+    ia, va = ordered(ma)
+    ib, vb = ordered(mb)
+    assert np.array_equal(ia, ib) and ia.shape[0] > 1000
+    assert np.max(np.abs(va - vb)) < 1e-6
+
+
+def test_slot_index_table_full_is_reported():
+    """With one block per slot the pool cannot run out, the table can."""
+    w = S.single_frame_workload()
+    vol = slot_volume(w, 256)
+    vol.fuse(torch.from_numpy(w.depth[0]).cuda(), w.cameras[0])
+    st = vol.stats()
+    assert st.status == T.ERR_TABLE_FULL and st.blocks_total == 256
+    assert st.pairs_dropped > 0 and st.keys_pool_overflow == 0
+
+
+# ---------------------------------------------------------------------------
+# colour
+# ---------------------------------------------------------------------------
+
+def gpu_colour_sums(vol: T.Volume, n_blocks: int, slot: bool):
+    """(B, 3, 512) colour sums in ascending key order, and the keys."""
+    keys = vol.block_keys_view()[:n_blocks].cpu().numpy().view(np.uint64)
+    pool = vol.alloc_list_view()[:n_blocks].cpu().numpy() if slot else np.arange(n_blocks)
+    cv = vol.colour_view()[torch.from_numpy(pool.astype(np.int64)).cuda()].cpu().numpy()
+    # (B, 64 rows, 3, 8 x) -> (B, 3, 512) with loc = row * 8 + x
+    sums = cv.transpose(0, 2, 1, 3).reshape(n_blocks, 3, 512).astype(np.float64)
+    order = np.argsort(keys)
+    return keys[order], sums[order]
+
+
+@pytest.mark.parametrize("variant", ["colour", "colour+slot", "colour two-pass"])
+def test_colour_matches_the_oracle(room, variant):
+    w, rgba = room
+    slot = "slot" in variant
+    flags = T.FUSE_TWO_PASS if "two-pass" in variant else T.FUSE_DEFAULT
+    ov = O.OracleVolume(w.voxel_size, w.trunc, 1 << 18)
+    for d, c, cam in zip(w.depth, rgba, w.cameras):
+        ov.fuse_rgb(d, c, cam)
+    o = ov.result()
+    P = 1 << 18
+    vol = T.Volume(w.voxel_size, w.trunc, P if slot else 0, P,
+                   flags=T.VOLUME_COLOUR | (T.VOLUME_SLOT_INDEX if slot else 0))
+    for d, c, cam in zip(w.depth, rgba, w.cameras):
+        vol.fuse_rgb(torch.from_numpy(d).cuda(), torch.from_numpy(c.view(np.int32)).cuda(), cam,
+                     flags)
+    g = result_of(vol)
+    assert_parity(g, o)
+    keys, sums = gpu_colour_sums(vol, o.keys.size, slot)
+    assert np.array_equal(keys, o.keys)
+    assert np.array_equal(sums, ov.colour_sums()), "colour sums differ"
+    # mean colours through the extraction call
+    mean = vol.extract_colour().cpu().numpy().astype(np.float64)   # (B, 512, 3), extraction order
+    ek = vol.extract().keys.cpu().numpy().view(np.uint64)
+    order = np.argsort(ek)
+    want = np.where(o.weights[:, None, :] > 0, ov.colour_sums() / np.maximum(o.weights, 1)[:, None, :],
+                    0.0).transpose(0, 2, 1)
+    assert np.max(np.abs(mean[order] - want)) < 1e-3
+    log(f"  {variant}: {o.keys.size} blocks, colour sums exact")
+
+
+def test_colour_in_a_mixed_batch(room):
+    """One batch call with colour and plain volumes and two band widths: one
+    kernel per group, each volume as if fused alone."""
+    w, rgba = room
+    dev = [torch.from_numpy(d).cuda() for d in w.depth]
+    cols = [torch.from_numpy(c.view(np.int32)).cuda() for c in rgba]
+    kinds = [(T.VOLUME_COLOUR, 0.02), (0, 0.02), (T.VOLUME_COLOUR, 0.01), (0, 0.015)]
+    batch = T.Batch(8)
+    for mode in ("tune", "graph"):
+        if mode == "graph":
+            batch.set_config(T.BatchConfig(32, 1, 8, 0))
+        a = [T.Volume(w.voxel_size, tr, 0, 1 << 17, flags=f) for f, tr in kinds]
+        b = [T.Volume(w.voxel_size, tr, 0, 1 << 17, flags=f) for f, tr in kinds]
+        for k in range(len(dev)):
+            batch.fuse(a, [dev[k]] * 4, [w.cameras[k]] * 4, rgbas=[cols[k]] * 4)
+            for v, (f, _) in zip(b, kinds):
+                if f:
+                    v.fuse_rgb(dev[k], cols[k], w.cameras[k])
+                else:
+                    v.fuse(dev[k], w.cameras[k])
+        for i, (f, _) in enumerate(kinds):
+            st = assert_same_volume(a[i], b[i])
+            if f:
+                n = st.blocks_total
+                ka, sa = gpu_colour_sums(a[i], n, False)
+                kb, sb = gpu_colour_sums(b[i], n, False)
+                assert np.array_equal(ka, kb) and np.array_equal(sa, sb)
+
+
+def test_colour_calls_are_checked():
+    w = S.single_frame_workload()
+    d = torch.from_numpy(w.depth[0]).cuda()
+    c = torch.zeros(d.shape, dtype=torch.int32, device="cuda")
+    colour = T.Volume(w.voxel_size, w.trunc, 0, 4096, flags=T.VOLUME_COLOUR)
+    plain = T.Volume(w.voxel_size, w.trunc, 0, 4096)
+    L = T.lib()
+    cam = T.camera_struct(w.cameras[0])
+    s = T._stream_ptr(None)
+    dp, cp = T.C.c_void_p(d.data_ptr()), T.C.c_void_p(c.data_ptr())
+    assert L.tsdf_fuse_frame_ex(colour.handle, dp, T.C.byref(cam), 0, s) == T.ERR_INVALID_ARGUMENT
+    assert L.tsdf_fuse_frame_rgb(colour.handle, dp, None, T.C.byref(cam), 0, s) == \
+        T.ERR_INVALID_ARGUMENT
+    assert L.tsdf_fuse_frame_rgb(plain.handle, dp, cp, T.C.byref(cam), 0, s) == \
+        T.ERR_INVALID_ARGUMENT
+    ptrs = (T.C.c_void_p * 1)(d.data_ptr())
+    cams = (T.CameraC * 1)(cam)
+    assert L.tsdf_fuse_frames(colour.handle, 1, ptrs, cams, 0, s) == T.ERR_INVALID_ARGUMENT
+    n = T.C.c_uint32()
+    assert L.tsdf_extract_colour(plain.handle, s, 0, None, T.C.byref(n)) == T.ERR_INVALID_ARGUMENT
+    batch = T.Batch(2)
+    with pytest.raises(T.TsdfError):
+        batch.fuse([colour], [d], [w.cameras[0]])  # no colour image
+    server = T.Server(1 << 28, max_sessions=2)
+    p = T.volume_params(w.voxel_size, w.trunc, 0, 4096, T.VOLUME_COLOUR)
+    sid = T.C.c_uint32()
+    assert L.tsdf_server_open(server._h, T.C.byref(p), T.C.byref(sid)) == T.ERR_INVALID_ARGUMENT
+    torch.cuda.synchronize()
+    assert colour.stats().frames == 0
