@@ -48,13 +48,16 @@ def kernel_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(n_pix: int, touched_blocks: int, new_blocks: int, touched_voxels: int) -> int:
+def algorithmic_bytes(n_pix: int, touched_blocks: int, new_blocks: int, touched_voxels: int,
+                      colour_channels: int = 0) -> int:
     """Bytes one fused frame must move at least.
 
     depth read (4 per pixel) + one 16-byte table entry per touched block + a new
     block's entry write and key (16 + 8) + read and write of 4-byte TSDF and weight
-    per touched voxel (16)."""
-    return 4 * n_pix + 16 * touched_blocks + 24 * new_blocks + 16 * touched_voxels
+    per touched voxel (16); colour frames add the colour image (4 per pixel) and
+    the read and write of each colour sum per touched voxel (8 per channel)."""
+    extra = (4 * n_pix + 8 * colour_channels * touched_voxels) if colour_channels else 0
+    return 4 * n_pix + 16 * touched_blocks + 24 * new_blocks + 16 * touched_voxels + extra
 
 
 def tick_accounting(vols, before_blocks, before_w, n_pix) -> tuple[int, dict]:
@@ -486,6 +489,9 @@ def main() -> int:
     ap.add_argument("--profile-copy-bytes", type=int, default=0,
                     help="after the run, copy this many bytes device-to-device three times "
                          "(a kernel of known traffic for scaling hardware byte counters)")
+    ap.add_argument("--variant", choices=["main", "slot", "colour"], default="main",
+                    help="trajectory: the volume design (main; slot: block index = table slot, "
+                         "pool = table; colour: three colour sums per voxel)")
     ap.add_argument("--workload", choices=["trajectory", "multi", "serve"], default="trajectory",
                     help="trajectory: one volume, the 300-frame orbit (default); multi: many "
                          "volumes, one frame each per tick, through the batch API; serve: "
@@ -527,18 +533,29 @@ def main() -> int:
 
     # ---- inputs, resident in HBM ---------------------------------------------
     t0 = time.time()
-    w = S.room_trajectory_workload(n_frames=300, frames=range(args.frames), device="cuda")
+    colour = args.variant == "colour"
+    slot = args.variant == "slot"
+    if colour:
+        w, rgba_np = S.room_trajectory_rgbd(n_frames=300, frames=range(args.frames), device="cuda")
+        rgba = [torch.from_numpy(c.view(np.int32)).cuda() for c in rgba_np]
+    else:
+        w = S.room_trajectory_workload(n_frames=300, frames=range(args.frames), device="cuda")
+        rgba = None
     depth = [torch.from_numpy(d).cuda() for d in w.depth]
     cams = [T.camera_struct(c) for c in w.cameras]
     n_pix = w.depth[0].size
     log(f"[bench] generated {len(depth)} frames in {time.time() - t0:.1f}s")
 
-    vol = T.Volume(w.voxel_size, w.trunc, w.table_capacity, w.pool_capacity)
+    vflags = (T.VOLUME_COLOUR if colour else 0) | (T.VOLUME_SLOT_INDEX if slot else 0)
+    table = w.table_capacity
+    pool = w.table_capacity if slot else w.pool_capacity  # one block per slot
+    vol = T.Volume(w.voxel_size, w.trunc, table, pool, flags=vflags)
     L = T.lib()
     stream = torch.cuda.current_stream()
     sp = T.C.c_void_p(stream.cuda_stream)
     h = vol.handle
     ptrs = [T.C.c_void_p(d.data_ptr()) for d in depth]
+    rgba_ptrs = [T.C.c_void_p(c.data_ptr()) for c in rgba] if colour else None
     cam_refs = [T.C.byref(c) for c in cams]
 
     def fuse_all(events=None):
@@ -548,7 +565,9 @@ def main() -> int:
         for k in range(len(ptrs)):
             if events is not None:
                 events[k].record(stream)
-            if L.tsdf_fuse_frame_ex(h, ptrs[k], cam_refs[k], flags, sp) != T.OK:
+            st = (L.tsdf_fuse_frame_rgb(h, ptrs[k], rgba_ptrs[k], cam_refs[k], flags, sp) if colour
+                  else L.tsdf_fuse_frame_ex(h, ptrs[k], cam_refs[k], flags, sp))
+            if st != T.OK:
                 raise RuntimeError("fuse failed")
         if events is not None:
             events[len(ptrs)].record(stream)
@@ -559,17 +578,35 @@ def main() -> int:
     cam_arr = (T.CameraC * len(cams))(*cams)
     bflags = T.FUSE_BATCH(args.per_group)
 
+    if colour:
+        # colour frames go through the batch path: fpl items of the one volume
+        cbatch = T.Batch(fpl)
+        cbatch.set_config(T.BatchConfig(16, 1, 4, 0))
+        items = (T.FuseItemC * len(ptrs))()
+        for k in range(len(ptrs)):
+            items[k].volume = h.value
+            items[k].depth_dev = depth[k].data_ptr()
+            items[k].rgba_dev = rgba[k].data_ptr()
+            items[k].camera = cams[k]
+
     def fuse_batched(events=None):
-        """The headline path: tsdf_fuse_frames, `fpl` frames per launch."""
+        """The headline path: `fpl` frames per launch (tsdf_fuse_frames, or
+        tsdf_batch_fuse for colour frames)."""
         if L.tsdf_reset_volume(h, sp) != T.OK:
             raise RuntimeError("reset failed")
         for j, (i0, n) in enumerate(chunks):
             if events is not None:
                 events[j].record(stream)
-            p = T.C.cast(T.C.byref(ptr_arr, i0 * T.C.sizeof(T.C.c_void_p)), T.C.c_void_p)
-            c = T.C.cast(T.C.byref(cam_arr, i0 * T.C.sizeof(T.CameraC)), T.C.c_void_p)
-            if L.tsdf_fuse_frames(h, n, p, c, bflags, sp) != T.OK:
-                raise RuntimeError("fuse_frames failed")
+            if colour:
+                it = T.C.cast(T.C.byref(items, i0 * T.C.sizeof(T.FuseItemC)),
+                              T.C.POINTER(T.FuseItemC))
+                st = L.tsdf_batch_fuse(cbatch._h, it, n, 0, sp)
+            else:
+                p = T.C.cast(T.C.byref(ptr_arr, i0 * T.C.sizeof(T.C.c_void_p)), T.C.c_void_p)
+                c = T.C.cast(T.C.byref(cam_arr, i0 * T.C.sizeof(T.CameraC)), T.C.c_void_p)
+                st = L.tsdf_fuse_frames(h, n, p, c, bflags, sp)
+            if st != T.OK:
+                raise RuntimeError("batched fusion failed")
         if events is not None:
             events[len(chunks)].record(stream)
 
@@ -578,17 +615,28 @@ def main() -> int:
     acc_bytes, acc = [], {"V": 0, "Bt": 0, "Bn": 0}
     prev_blocks = 0
     wv = vol.weight_view()
+
+    def listed_weights(nb):
+        """(nb, 512) weights of the allocated blocks, in allocation order."""
+        if slot:
+            idx = vol.alloc_list_view()[:nb].long()
+            return wv[idx].reshape(nb, 512)
+        return wv[:nb].reshape(nb, 512)
+
     for k in range(len(ptrs)):
-        before = wv[:prev_blocks].reshape(prev_blocks, 512).clone()
-        vol.fuse(depth[k], cams[k], flags)
+        before = listed_weights(prev_blocks).clone()
+        if colour:
+            vol.fuse_rgb(depth[k], rgba[k], cams[k], flags)
+        else:
+            vol.fuse(depth[k], cams[k], flags)
         st = vol.stats()
         nb = st.blocks_total
-        after = wv[:nb].reshape(nb, 512)
+        after = listed_weights(nb)
         changed = after != torch.nn.functional.pad(before, (0, 0, 0, nb - prev_blocks))
         V = int(changed.sum())
         Bt = int(changed.any(dim=1).sum())
         Bn = nb - prev_blocks
-        acc_bytes.append(algorithmic_bytes(n_pix, Bt, Bn, V))
+        acc_bytes.append(algorithmic_bytes(n_pix, Bt, Bn, V, 3 if colour else 0))
         acc["V"] += V
         acc["Bt"] += Bt
         acc["Bn"] += Bn
@@ -635,7 +683,7 @@ def main() -> int:
     achieved = bytes_per_launch / (mean_launch_ms * 1e-3) / 1e9
     mean_frame_ms = float(frame_ms.mean())
     traffic = None
-    if os.path.exists(TRAFFIC_FILE):
+    if os.path.exists(TRAFFIC_FILE) and args.variant == "main":
         tr = json.load(open(TRAFFIC_FILE))
         if tr.get("kernel_sha") == kernel_sha() and tr.get("batch") == fpl and \
                 tr.get("per_group") == args.per_group:
@@ -650,7 +698,10 @@ def main() -> int:
         pts = 0
         k = 0
         while k < len(w.depth) and (k < n_cpu or time.perf_counter() - t_c0 < args.cpu_seconds):
-            ov.fuse(w.depth[k], w.cameras[k])
+            if colour:
+                ov.fuse_rgb(w.depth[k], rgba_np[k], w.cameras[k])
+            else:
+                ov.fuse(w.depth[k], w.cameras[k])
             k += 1
         t_c = time.perf_counter() - t_c0
         pts = ov.stats()["points_valid"]
@@ -682,9 +733,14 @@ def main() -> int:
         "data": "synthetic",
         "config": {
             "workload": f"room orbit, {len(ptrs)} frames of 640x480, voxel 5 mm, truncation 2 cm, "
-                        f"table 2^20 slots, pool 2^18 blocks",
-            "path": f"batched: tsdf_fuse_frames, {fpl} frames per launch, "
-                    f"{args.per_group} frame(s) per workgroup",
+                        f"table 2^20 slots, pool {'2^20' if slot else '2^18'} blocks"
+                        + (", colour images" if colour else ""),
+            "path": (f"batched: tsdf_batch_fuse, {fpl} frames of the volume per launch"
+                     if colour else
+                     f"batched: tsdf_fuse_frames, {fpl} frames per launch, "
+                     f"{args.per_group} frame(s) per workgroup"),
+            "variant": {"main": "main design", "slot": "block index = table slot",
+                        "colour": "TSDF, weight and three colour sums"}[args.variant],
             "frames_per_step": len(ptrs), "points_per_step": points_per_step,
             "parallelism": "single GPU",
         },
@@ -709,7 +765,8 @@ def main() -> int:
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": f"fuse_kernel<4, {args.per_group}, 16, fused>",
+            "kernel": ("fuse_multi_kernel<4, 1, 4, colour>" if colour
+                       else f"fuse_kernel<4, {args.per_group}, 16, fused>"),
             "algorithmic_bytes_per_launch": bytes_per_launch,
             "mean_launch_ms": mean_launch_ms,
             "touched_voxels_per_frame": acc["V"] / len(ptrs),
