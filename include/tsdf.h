@@ -313,7 +313,7 @@ typedef struct tsdf_fuse_item {
 typedef struct tsdf_batch_config {
   uint32_t tile_width;         /* 16, 32 or 64 */
   uint32_t pixels_per_thread;  /* 1 or 2 */
-  uint32_t acc_blocks;         /* 4, 8 or 16 (8 or 16 with 2 pixels per thread) */
+  uint32_t acc_blocks;         /* 4 or 8 (8 with 2 pixels per thread) */
   uint32_t groups_per_cu;      /* workgroups of the persistent grid per compute
                                   unit; 0 = as many as can be resident */
 } tsdf_batch_config;

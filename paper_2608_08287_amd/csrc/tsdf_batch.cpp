@@ -27,7 +27,7 @@ constexpr int kRingSlots = 4;
 constexpr int kMaxGraphs = 4;
 constexpr uint64_t kHeaderBytes = 256;  // k_begin[kBatchGroups], padded
 static_assert(4 * (tsdf::kBatchGroups + 1) <= kHeaderBytes, "group ranges fit the header");
-constexpr int kAccChoices[3] = {4, 8, 16};
+constexpr int kAccChoices[2] = {4, 8};
 constexpr uint32_t kTileWidths[3] = {16, 32, 64};
 constexpr int kMaxPixelsPerThread = 2;
 
@@ -43,7 +43,7 @@ WorkLayout work_layout(uint32_t max_items) {
   return L;
 }
 
-int acc_index(uint32_t ab) { return ab == 4 ? 0 : ab == 8 ? 1 : ab == 16 ? 2 : -1; }
+int acc_index(uint32_t ab) { return ab == 4 ? 0 : ab == 8 ? 1 : -1; }
 
 unsigned log2_u32(uint32_t x) {
   unsigned l = 0;
@@ -86,7 +86,7 @@ struct tsdf_batch {
   int n_cu;
   // resident workgroups per CU by [K][pixels per thread - 1][acc index][colour];
   // 0 = not yet asked
-  int occupancy[TSDF_MAX_BAND_HALF + 1][kMaxPixelsPerThread][3][2];
+  int occupancy[TSDF_MAX_BAND_HALF + 1][kMaxPixelsPerThread][2][2];
   // staging ring
   char* ring;
   hipEvent_t ring_done[kRingSlots];

@@ -26,16 +26,21 @@
 //                publication" means "look again next iteration"), so a waiter
 //                never spins while a publisher in its own wave is masked off.
 //   3. integrate -- the tile's contributions (of all its frames) are first summed
-//                in LDS, kAccBlocks blocks at a time, in a dense accumulator laid
-//                out exactly like a pool block; each pass then flushes it with
-//                agent-scope float atomics, four 8-voxel rows per wave
-//                instruction.  Device-scope float atomics on gfx950 are performed
-//                beyond L2 at about 20 G requests/s, one request per touched
-//                64-byte segment per instruction whatever its lane count, so the
-//                cost is the number of (tile, row) pairs: a voxel gets one update
-//                per tile (and per launch), not one per contribution, and the
-//                row's TSDF sums and weights share a segment (see the pool layout
-//                in tsdf_internal.h).
+//                in LDS, one slot per touched voxel: each dense block marks the
+//                voxels its pairs touch in a 512-bit mask, a prefix sum over the
+//                masks' counts gives each touched voxel a slot in block and
+//                voxel order, and the slots (a sum and a count) are summed in
+//                one pass when the LDS region holds them all, which is the
+//                common case, else in passes of as many as it holds.  The slots
+//                are then flushed with agent-scope float atomics, two lanes per
+//                voxel (its sum and its count, which share a 64-byte pool row),
+//                so that a wave instruction touches a few rows.  Device-scope
+//                float atomics on gfx950 are performed beyond L2, one request
+//                per touched 64-byte segment per instruction whatever its lane
+//                count, so the cost is the number of (tile, row) pairs: a voxel
+//                gets one update per tile (and per launch), not one per
+//                contribution, and the row's TSDF sums and weights share a
+//                segment (see the pool layout in tsdf_internal.h).
 //
 // A workgroup only ever accumulates into blocks whose indices it resolved itself,
 // so one launch needs no grid-wide barrier.  The two-pass structure of Section
@@ -61,9 +66,8 @@ constexpr int kThreads = kTileW * kTileH;  // 256 = 4 x wave64
 constexpr int kWave = 64;
 constexpr unsigned kSetCap = 1024;          // LDS key-set slots per workgroup
 constexpr unsigned kSetNone = 0x7FFu;       // "no LDS slot" (set full)
-constexpr unsigned kAccBlocks = 8;          // blocks aggregated in LDS per pass
+constexpr unsigned kAccBlocks = 8;          // phase-3 LDS region, in blocks' worth of floats
 constexpr int kProbeAhead = 4;              // table slots read per probe step
-constexpr unsigned kAccSlots = kAccBlocks * kBlockFloats;  // sums and counts
 // A publication is one store after the winner's compare-exchange, so a wait is a
 // handful of steps.  A wait this long means the invariant broke: report it as
 // INTERNAL instead of spinning forever.
@@ -117,6 +121,17 @@ __device__ __forceinline__ unsigned long long readlane64(unsigned long long v, i
 __device__ __forceinline__ unsigned wave_sum(unsigned v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += (unsigned)__shfl_xor((int)v, off, kWave);
+  return v;
+}
+
+// Inclusive prefix sum over the lanes of the wave.
+__device__ __forceinline__ unsigned wave_inclusive_scan(unsigned v) {
+  const unsigned lane = lane_id();
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const unsigned o = (unsigned)__shfl_up((int)v, (unsigned)off, kWave);
+    v += lane >= (unsigned)off ? o : 0u;
+  }
   return v;
 }
 
@@ -392,11 +407,25 @@ constexpr unsigned acc_block_floats(bool colour) {
   return colour ? kBlockFloats + kColourFloats : kBlockFloats;
 }
 
-// LDS of one tile: the key set (phases 1-2) shares its space with the
-// accumulator of AB blocks (phase 3).
+// Phase 3 sums a tile's contributions per voxel in LDS before they reach the
+// pool.  The dense blocks are taken in windows of kWin (one window unless the
+// tile touches more blocks); per window, each block has a 512-bit mask of the
+// voxels its pairs touch (eight 64-bit words) and per word the first voxel
+// slot of its bits, and the slots hold, as arrays: the TSDF sum; a tagged
+// count (window block << 21 | voxel << 12 | count); and for colour volumes the
+// red, green and blue sums.
+constexpr unsigned slot_floats(bool colour) { return colour ? 5u : 2u; }
+constexpr unsigned window_blocks(unsigned region_floats) {
+  // the masks and word bases (24 floats per block) take at most half the region
+  return region_floats / 48u < 128u ? region_floats / 48u : 128u;
+}
+
+// LDS of one tile.  The key set (phases 1-2) shares its space with the
+// phase-3 region of AB blocks' worth of floats (masks, word bases, voxel
+// slots); the dense-id map (phases 1-3) with the scan's per-wave totals.
 template <int AB, bool kColour = false>
-struct TileShared {
-  union {
+struct alignas(16) TileShared {
+  union alignas(16) {
     struct {
       unsigned long long keys[kSetCap];
       unsigned n;  // distinct keys in the set
@@ -404,8 +433,19 @@ struct TileShared {
     float acc[AB * acc_block_floats(kColour)];
   } u;
   int blockd[kSetCap];
-  unsigned short dense[kSetCap];
-  unsigned short list[kSetCap];
+  union {
+    struct {
+      unsigned short dense[kSetCap];
+      unsigned short list[kSetCap];
+    } map;
+    unsigned wsum[kThreads / kWave];
+  } v;
+  static constexpr unsigned kRegion = AB * acc_block_floats(kColour);
+  static constexpr unsigned kWin = window_blocks(kRegion);
+  static constexpr unsigned kCap = (kRegion - 24u * kWin) / slot_floats(kColour);
+  static_assert(kWin >= 32 && kWin <= 128, "a window's block index fits the tag's 7 bits");
+  static_assert(kWin <= (unsigned)kThreads, "one thread per block of a window in the scan");
+  static_assert(kCap >= 512, "a pass holds at least one block's voxels");
 };
 
 // One tile of F pixel slots per thread: the three phases.  Slot fi of the
@@ -426,11 +466,8 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
   unsigned long long* const s_keys = sh.u.set.keys;
   unsigned* const s_n = &sh.u.set.n;
   int* const s_blockd = sh.blockd;            // pool index per dense block id
-  unsigned short* const s_dense = sh.dense;   // dense block id per set slot
-  unsigned short* const s_list = sh.list;     // set slot per dense block id
-  float* const s_acc = sh.u.acc;              // AB blocks in the pool's own layout
-  constexpr unsigned kAccStride = acc_block_floats(kColour);
-  constexpr unsigned kAccSlots = AB * kAccStride;
+  unsigned short* const s_dense = sh.v.map.dense;  // dense block id per set slot
+  unsigned short* const s_list = sh.v.map.list;    // set slot per dense block id
 
   const unsigned tid = threadIdx.x;
   __syncthreads();  // the previous tile of a persistent workgroup is done with the LDS
@@ -591,86 +628,180 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
         }
       }
     }
-    for (unsigned i = tid; i < kAccSlots; i += kThreads) s_acc[i] = 0.0f;
-    __syncthreads();
-    for (unsigned lo = 0; lo < n_keys; lo += AB) {
+
+    // Voxel slots, window by window of dense blocks.
+    using Shared = TileShared<AB, kColour>;
+    constexpr unsigned kWin = Shared::kWin, kCap = Shared::kCap;
+    constexpr unsigned kInWin = 1u << 30;  // st: the pair's slot of this window, not its block
+    unsigned long long* const s_mark = reinterpret_cast<unsigned long long*>(sh.u.acc);
+    unsigned* const s_wbase = reinterpret_cast<unsigned*>(sh.u.acc) + 16u * kWin;
+    float* const s_sum = sh.u.acc + 24u * kWin;
+    unsigned* const s_tag = reinterpret_cast<unsigned*>(s_sum + kCap);
+    float* const s_col = s_sum + 2u * kCap;  // colour: [3][kCap]
+    unsigned* const s_wsum = sh.v.wsum;
+    for (unsigned k0 = 0; k0 < n_keys; k0 += kWin) {
+      const unsigned kn = n_keys - k0 < kWin ? n_keys - k0 : kWin;
+      for (unsigned i = tid; i < kn * 8u; i += kThreads) s_mark[i] = 0ull;
+      __syncthreads();
 #pragma unroll
-      for (int fi = 0; fi < F; ++fi) {
-        const FrameDev& fr = frs[fi];
-        const float a = ((float)px[fi] - fr.cx) * fr.ifx;
-        const float b = ((float)py[fi] - fr.cy) * fr.ify;
+      for (int fi = 0; fi < F; ++fi)
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
           const unsigned w = st[fi][s];
-          const unsigned db = ((w >> 9) & 0x7FFu) - lo;
-          if ((w & kPairValid) && db < AB) {
-            // the empty asm makes the depth opaque to the optimiser so the
-            // recomputation stays inside this pass instead of being hoisted out
-            // of the loop (which would hold every pair's value in registers)
-            float dk = d[fi];
-            asm volatile("" : "+v"(dk));
-            const float v = walk_sample(fr, wp, dk, a, b, s - K).val;
-            float* ab = &s_acc[db * kAccStride];
-            __hip_atomic_fetch_add(ab + pool_tsdf_index(w & 511u), v, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP);
-            __hip_atomic_fetch_add(ab + pool_weight_index(w & 511u), 1.0f, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (kColour) {
+          const unsigned db = ((w >> 9) & 0x7FFu) - k0;
+          if ((w & kPairValid) && db < kn)
+            atomicOr(&s_mark[db * 8u + ((w & 511u) >> 6)], 1ull << (w & 63u));
+        }
+      __syncthreads();
+      // word bases: one thread per block sums its words, a scan over the
+      // blocks places them; every thread keeps the window's total
+      unsigned total = 0;
+      {
+        unsigned cnt[8], key_total = 0;
+        if (tid < kn) {
 #pragma unroll
-              for (unsigned c = 0; c < 3; ++c)
-                __hip_atomic_fetch_add(ab + kBlockFloats + colour_index(w & 511u, c),
-                                       (float)((rgb[fi] >> (8 * c)) & 255u), __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+          for (int q = 0; q < 8; ++q) {
+            cnt[q] = (unsigned)__popcll(s_mark[tid * 8u + q]);
+            key_total += cnt[q];
+          }
+        }
+        const unsigned incl = wave_inclusive_scan(key_total);
+        if (lane_id() == kWave - 1) s_wsum[tid / kWave] = incl;
+        __syncthreads();
+        unsigned before = 0;
+#pragma unroll
+        for (unsigned wv = 0; wv < kThreads / kWave; ++wv) {
+          const unsigned ws = s_wsum[wv];
+          before += wv < tid / kWave ? ws : 0u;
+          total += ws;
+        }
+        if (tid < kn) {
+          unsigned at = before + incl - key_total;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            s_wbase[tid * 8u + q] = at;
+            at += cnt[q];
+          }
+        }
+        __syncthreads();
+      }
+      // a pair of this window trades its block for its slot
+#pragma unroll
+      for (int fi = 0; fi < F; ++fi)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const unsigned w = st[fi][s];
+          const unsigned db = ((w >> 9) & 0x7FFu) - k0;
+          if ((w & kPairValid) && !(w & kInWin) && db < kn) {
+            const unsigned item = db * 8u + ((w & 511u) >> 6);
+            const unsigned slot = s_wbase[item] +
+                                  (unsigned)__popcll(s_mark[item] & ((1ull << (w & 63u)) - 1ull));
+            st[fi][s] = kPairValid | kInWin | (slot << 9) | (w & 511u);
+          }
+        }
+
+      for (unsigned lo = 0; lo < total; lo += kCap) {
+        const unsigned n_here = total - lo < kCap ? total - lo : kCap;
+        // this pass's slots start from zero sums and tagged zero counts
+        for (unsigned item = tid; item < kn * 8u; item += kThreads) {
+          unsigned at = s_wbase[item];
+          const unsigned tag = (item >> 3) << 21 | (item & 7u) << 18;  // block, voxel bits 6..8
+          for (unsigned long long m = s_mark[item]; m != 0ull && at < lo + n_here;
+               m &= m - 1ull, ++at) {
+            if (at >= lo) {
+              s_sum[at - lo] = 0.0f;
+              s_tag[at - lo] = tag | (unsigned)__builtin_ctzll(m) << 12;
+              if (kColour) {
+#pragma unroll
+                for (unsigned c = 0; c < 3; ++c) s_col[c * kCap + at - lo] = 0.0f;
+              }
             }
           }
         }
-      }
-      __syncthreads();
-      // flush: per block, each thread owns floats tid + 256q (q = 0..3) of the
-      // block's 1024; a wave instruction covers 64 consecutive floats = 4 rows,
-      // one 64-byte memory-side atomic request per touched row.  All LDS reads
-      // of a block are issued before any atomic or clearing write, so the
-      // flush pays one LDS latency per block rather than one per float.
-      for (unsigned bb = 0; bb < AB && lo + bb < n_keys; ++bb) {
-        const int blk = s_blockd[lo + bb];  // uniform across the workgroup
-        float* ab = &s_acc[bb * kAccStride];
-        float v[4], cn[4];
+        __syncthreads();
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const unsigned i = q * kThreads + tid;
-          v[q] = ab[i];
-          cn[q] = ab[(i & ~15u) + 8u + (i & 7u)];  // this voxel's count
-        }
-        // colour sums: six floats per thread; a zero sum (a black or untouched
-        // voxel) needs no update, so no count is needed to decide
-        constexpr int kCq = kColour ? (int)(kColourFloats / kThreads) : 0;
-        float cv[kCq > 0 ? kCq : 1];
+        for (int fi = 0; fi < F; ++fi) {
+          const FrameDev& fr = frs[fi];
+          const float a = ((float)px[fi] - fr.cx) * fr.ifx;
+          const float b = ((float)py[fi] - fr.cy) * fr.ify;
 #pragma unroll
-        for (int q = 0; q < kCq; ++q) cv[q] = ab[kBlockFloats + q * kThreads + tid];
-        if (blk >= 0) {
-          float* bp = vol.voxels + (size_t)blk * kBlockFloats;
+          for (int s = 0; s < NS; ++s) {
+            const unsigned w = st[fi][s];
+            const unsigned sl = ((w >> 9) & 0x1FFFFu) - lo;
+            if ((w & kInWin) && sl < n_here) {
+              // the empty asm makes the depth opaque to the optimiser so the
+              // recomputation stays inside this pass instead of being hoisted
+              // out of the loop (which would hold every pair's value in registers)
+              float dk = d[fi];
+              asm volatile("" : "+v"(dk));
+              const float v = walk_sample(fr, wp, dk, a, b, s - K).val;
+              __hip_atomic_fetch_add(s_sum + sl, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+              __hip_atomic_fetch_add(s_tag + sl, 1u, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_WORKGROUP);
+              if (kColour) {
 #pragma unroll
-          for (int q = 0; q < 4; ++q)
-            if (cn[q] != 0.0f) add_f32(bp + q * kThreads + tid, v[q]);
-          if (kColour) {
-            float* cp = vol.colour + (size_t)blk * kColourFloats;
-#pragma unroll
-            for (int q = 0; q < kCq; ++q)
-              if (cv[q] != 0.0f) add_f32(cp + q * kThreads + tid, cv[q]);
+                for (unsigned c = 0; c < 3; ++c)
+                  __hip_atomic_fetch_add(s_col + c * kCap + sl,
+                                         (float)((rgb[fi] >> (8 * c)) & 255u), __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_WORKGROUP);
+              }
+            }
           }
-        } else if (tid & 8u) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q) n_drop += (unsigned)cn[q];
         }
-        // every lane of a wave has read its rows before any lane clears them
+        __syncthreads();
+        // flush: two lanes per voxel slot, its sum and its count; slots are in
+        // block and voxel order, so a wave instruction's 32 voxels fall in a
+        // few 64-byte pool rows, one memory-side atomic request per row.  Four
+        // slots per lane are read before any atomic is issued.
+        const unsigned half = tid & 1u;
+        for (unsigned j0 = tid >> 1; j0 < n_here; j0 += 4u * (kThreads / 2u)) {
+          unsigned tg[4];
+          float sm[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (cn[q] != 0.0f) ab[q * kThreads + tid] = 0.0f;
+          for (int q = 0; q < 4; ++q) {
+            const unsigned j = j0 + (unsigned)q * (kThreads / 2u);
+            const bool ok = j < n_here;
+            tg[q] = ok ? s_tag[j] : 0u;
+            sm[q] = ok ? s_sum[j] : 0.0f;
+          }
 #pragma unroll
-        for (int q = 0; q < kCq; ++q)
-          if (cv[q] != 0.0f) ab[kBlockFloats + q * kThreads + tid] = 0.0f;
+          for (int q = 0; q < 4; ++q) {
+            const unsigned cnt = tg[q] & 0xFFFu;
+            if (cnt == 0u) continue;  // past the pass's slots
+            const int blk = s_blockd[k0 + (tg[q] >> 21)];
+            const unsigned loc = (tg[q] >> 12) & 511u;
+            if (blk >= 0)
+              add_f32(vol.voxels + (size_t)blk * kBlockFloats + (loc >> 3) * 16u + half * 8u +
+                          (loc & 7u),
+                      half ? (float)cnt : sm[q]);
+            else if (half)
+              n_drop += cnt;  // the pool had no block for this key
+          }
+        }
+        if (kColour) {
+          // colour sums: one lane per slot, a zero sum needs no update
+          for (unsigned j = tid; j < n_here; j += kThreads) {
+            const unsigned tg = s_tag[j];
+            const int blk = s_blockd[k0 + (tg >> 21)];
+            if (blk < 0) continue;
+            const unsigned loc = (tg >> 12) & 511u;
+#pragma unroll
+            for (unsigned c = 0; c < 3; ++c) {
+              const float cv = s_col[c * kCap + j];
+              if (cv != 0.0f) add_f32(vol.colour + (size_t)blk * kColourFloats + colour_index(loc, c), cv);
+            }
+          }
+        }
+        if (lo + kCap < total || k0 + kWin < n_keys) __syncthreads();
       }
-      __syncthreads();
+      // this window's pairs are done
+      if (k0 + kWin < n_keys) {
+#pragma unroll
+        for (int fi = 0; fi < F; ++fi)
+#pragma unroll
+          for (int s = 0; s < NS; ++s)
+            if (st[fi][s] & kInWin) st[fi][s] = 0u;
+      }
     }
   }
 
@@ -753,13 +884,13 @@ void fuse_kernel(VolumeDev vol, WalkParams wp, FrameBatch<NB> fb, unsigned n_fra
 template <typename T>
 using ConstPtr = const __attribute__((address_space(4))) T*;
 
-// Two pixels per thread need ~146 VGPRs; with an 8-block accumulator four
-// workgroups fit a CU's LDS, so registers are capped to match (a few dwords
-// spill).  A 16-block accumulator allows two workgroups per CU: no cap.
-constexpr int multi_waves_per_eu(int ppt, int ab) { return ppt == 2 && ab <= 8 ? 4 : 1; }
+// Four workgroups of a plain volume fit a CU's LDS, so registers are capped to
+// match: 128 VGPRs (two pixels per thread need ~146, and spill a few dwords).
+// Colour workgroups take more LDS, three per CU: no cap.
+constexpr int multi_waves_per_eu(bool colour) { return colour ? 1 : 4; }
 
 template <int K, int PPT, int AB, bool kColour>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(multi_waves_per_eu(PPT, AB))))
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(multi_waves_per_eu(kColour))))
 void fuse_multi_kernel(BatchWork w, unsigned tw_log2) {
   __shared__ TileShared<AB, kColour> sh;
   const ConstPtr<unsigned> k_begin = (ConstPtr<unsigned>)w.k_begin;
@@ -806,14 +937,12 @@ const void* multi_kernel_k(int pixels_per_thread, int acc_blocks, bool colour) {
     switch (acc_blocks) {
       case 4: return reinterpret_cast<const void*>(&fuse_multi_kernel<K, 1, 4, false>);
       case 8: return reinterpret_cast<const void*>(&fuse_multi_kernel<K, 1, 8, false>);
-      case 16: return reinterpret_cast<const void*>(&fuse_multi_kernel<K, 1, 16, false>);
       default: return nullptr;
     }
   }
   if (pixels_per_thread == 2) {
     switch (acc_blocks) {
       case 8: return reinterpret_cast<const void*>(&fuse_multi_kernel<K, 2, 8, false>);
-      case 16: return reinterpret_cast<const void*>(&fuse_multi_kernel<K, 2, 16, false>);
       default: return nullptr;
     }
   }

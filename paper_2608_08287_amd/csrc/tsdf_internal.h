@@ -154,7 +154,7 @@ hipError_t launch_fuse_band8(VolumeDev vol, const WalkParams& wp, const FrameDev
                              int frames_per_group, FuseMode mode, bool remap, hipStream_t s);
 // The persistent multi-volume kernel for band half-width K taking
 // pixels_per_thread (1 or 2) pixels per thread and accumulating acc_blocks
-// (4, 8 or 16; 8 or 16 with 2 pixels) blocks in LDS per pass, as a host
+// (4 or 8; 8 with 2 pixels) blocks in LDS per pass, as a host
 // function pointer for hipLaunchKernel / graph kernel nodes; nullptr for
 // other values.  Colour volumes have one shape: 1 pixel, 4 blocks.  Its
 // arguments are (BatchWork work, unsigned tile_width_log2).

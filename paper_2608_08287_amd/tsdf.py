@@ -487,7 +487,7 @@ def fuse_frames(vol: Volume, depths: Sequence[torch.Tensor], cams: Sequence, fla
 class BatchConfig:
     tile_width: int         # 16, 32 or 64 pixels
     pixels_per_thread: int  # 1 or 2 (tile height pixels_per_thread * 256 / tile_width)
-    acc_blocks: int         # LDS accumulator blocks per pass: 4, 8 or 16 (8, 16 with 2 pixels)
+    acc_blocks: int         # LDS accumulator blocks per pass: 4 or 8 (8 with 2 pixels)
     groups_per_cu: int      # persistent workgroups per CU, 0 = all that fit
 
 

@@ -4,6 +4,7 @@ table and pool invariants)."""
 from __future__ import annotations
 
 import dataclasses
+import math
 import sys
 from typing import Optional, Sequence
 
@@ -11,6 +12,7 @@ import numpy as np
 import torch
 
 from oracle import oracle as O
+from paper_2608_08287_amd import scenes as S
 from paper_2608_08287_amd import tsdf as T
 
 # TSDF means: float32 sums on the GPU in a racy order against float64 sums in the
@@ -162,3 +164,36 @@ def assert_table_invariants(vol: T.Volume, expect_keys: np.ndarray, n_blocks: in
     cum = np.concatenate([[0], np.cumsum(np.concatenate([empty, empty]).astype(np.int64))])
     starts, ends = homes, homes + disp
     assert np.all(cum[ends] - cum[starts] == 0), "empty slot inside a probe path"
+
+
+def rotation(a, b, c):
+    """Rz(a) Ry(b) Rx(c)."""
+    ca, sa, cb, sb, cc, sc = (math.cos(a), math.sin(a), math.cos(b), math.sin(b), math.cos(c),
+                              math.sin(c))
+    return (np.array([[ca, -sa, 0], [sa, ca, 0], [0, 0, 1]])
+            @ np.array([[cb, 0, sb], [0, 1, 0], [-sb, 0, cb]])
+            @ np.array([[1, 0, 0], [0, cc, -sc], [0, sc, cc]]))
+
+
+def scattered_frames(n, W=64, H=48, seed=0, focal=30.0, lo=0.3, hi=3.0, jitter=0.1):
+    """n frames of depths uniform in [lo, hi] from cameras near the origin
+    (rotations and offsets scaled by `jitter`): every pixel's band lands
+    apart from its neighbours', so a tile touches as many voxels as it has
+    samples."""
+    rng = np.random.default_rng(seed)
+    cams, depths = [], []
+    for i in range(n):
+        pose = np.concatenate([rotation(*rng.uniform(-0.3, 0.3, 3) * jitter / 0.1),
+                               rng.uniform(-jitter, jitter, (3, 1))], 1)
+        cams.append(S.Camera(W, H, focal, focal * 0.95, W / 2 - 0.5, H / 2 + 0.5,
+                             pose.astype(np.float32)))
+        depths.append(rng.uniform(lo, hi, (H, W)).astype(np.float32))
+    return depths, cams
+
+
+# name: (voxel, truncation, frame options)
+SCATTER = {
+    "sparse_4mm_K4": (0.004, 0.016, {}),
+    "sparse_1mm_K8": (0.001, 0.008, {}),
+    "dense_1mm_K8": (0.001, 0.008, dict(W=32, H=32, focal=1000.0, lo=1.0, hi=1.12, jitter=0.001)),
+}

@@ -17,10 +17,9 @@ from parity import assert_parity, assert_same_volume, log, result_of
 pytestmark = pytest.mark.gpu
 
 SMALL = ((160, 120), (320, 240))
-CONFIGS = ([T.BatchConfig(tw, 1, ab, gpc) for tw in (16, 32, 64) for ab in (4, 8, 16)
+CONFIGS = ([T.BatchConfig(tw, 1, ab, gpc) for tw in (16, 32, 64) for ab in (4, 8)
             for gpc in (0, 1)]
-           + [T.BatchConfig(tw, 2, ab, gpc) for tw in (16, 32, 64) for ab in (8, 16)
-              for gpc in (0, 1)])
+           + [T.BatchConfig(tw, 2, 8, gpc) for tw in (16, 32, 64) for gpc in (0, 1)])
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -125,7 +124,7 @@ def test_mixed_band_widths_in_one_call():
     batch = T.Batch(8)
     for mode in ("tune", "graph"):
         if mode == "graph":
-            batch.set_config(T.BatchConfig(32, 2, 16, 0))
+            batch.set_config(T.BatchConfig(32, 2, 8, 0))
         a = [T.Volume(*p) for p in vol_params]
         b = [T.Volume(*p) for p in vol_params]
         for k in range(2):
@@ -170,11 +169,11 @@ def test_autotuner_settles_and_stays_correct():
         ticks += 1
         torch.cuda.synchronize()
         cfg, tuned = batch.config()
-    assert cfg.tile_width in (16, 32, 64) and cfg.acc_blocks in (4, 8, 16)
+    assert cfg.tile_width in (16, 32, 64) and cfg.acc_blocks in (4, 8)
     assert cfg.pixels_per_thread in (1, 2)
     log(f"  tuned after {ticks} calls: {cfg}")
     cands = batch.candidates()
-    assert len(cands) >= 15 and all(np.isfinite(t) and t > 0 for _, t in cands)
+    assert len(cands) >= 11 and all(np.isfinite(t) and t > 0 for _, t in cands)
     assert cfg == min(cands, key=lambda ct: ct[1])[0]
     ref = fuse_alone(w, ticks)
     for i in range(len(w)):
@@ -211,7 +210,7 @@ def test_batch_argument_errors():
     assert L.tsdf_batch_fuse(batch._h, items, 1, 0, None) == T.ERR_INVALID_ARGUMENT  # null volume
     assert L.tsdf_batch_fuse(batch._h, None, 0, 0x2, None) == T.ERR_INVALID_ARGUMENT  # unknown flag
     for bad in (T.BatchConfigC(8, 1, 8, 0), T.BatchConfigC(16, 1, 5, 0), T.BatchConfigC(16, 1, 8, 65),
-                T.BatchConfigC(16, 0, 8, 0), T.BatchConfigC(16, 3, 8, 0), T.BatchConfigC(16, 2, 4, 0)):
+                T.BatchConfigC(16, 0, 8, 0), T.BatchConfigC(16, 3, 8, 0), T.BatchConfigC(16, 2, 4, 0), T.BatchConfigC(16, 1, 16, 0)):
         assert L.tsdf_batch_set_config(batch._h, bad) == T.ERR_INVALID_ARGUMENT
     assert L.tsdf_batch_autotune(batch._h, 0) == T.ERR_INVALID_ARGUMENT
     assert L.tsdf_batch_autotune(batch._h, 17) == T.ERR_INVALID_ARGUMENT

@@ -14,8 +14,8 @@ from oracle import oracle as O
 from paper_2608_08287_amd import scenes as S
 from paper_2608_08287_amd import tsdf as T
 
-from parity import (EMPTY, assert_parity, assert_table_invariants, log, run_gpu, run_workload,
-                    table_arrays)
+from parity import (EMPTY, SCATTER, assert_parity, assert_table_invariants, log, result_of,
+                    run_gpu, run_workload, scattered_frames, table_arrays)
 
 pytestmark = pytest.mark.gpu
 
@@ -280,6 +280,48 @@ def test_stress_C_table_full_is_reported(stress_full):
     assert g.stats.blocks_total == pre.size + 50
     _check_subset(g, full1, np.sort(scene_in))
     assert g.stats.table_full_events >= full1.keys.size - 50
+
+
+# ---------------------------------------------------------------------------
+# Tiles that touch many blocks and many voxels.  "sparse": random depths seen
+# through a short focal length put nearly every sample of a 16x16 tile in its
+# own voxel and its own block, so the LDS sums of a tile take several windows
+# of blocks (and, with 8 mm blocks and a 17-sample band, the tile's 1024-key
+# set overflows).  "dense": a long focal length and a 0.12 m depth spread put
+# thousands of voxels of a tile in one or two hundred blocks, so a window of
+# blocks takes several passes over the voxel slots.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("band", list(SCATTER))
+@pytest.mark.parametrize("path", ["plain", "batch1", "batch2", "batch4"])
+def test_scattered_tiles(band, path):
+    v, tau, opts = SCATTER[band]
+    depths, cams = scattered_frames(4, seed=31, **opts)
+    o = O.fuse_frames(v, tau, 1 << 20, depths, cams)
+    if path == "plain":
+        g = run_gpu(v, tau, 1 << 21, 1 << 20, depths, cams)
+    else:
+        g = run_gpu(v, tau, 1 << 21, 1 << 20, depths, cams, batched=True,
+                    flags=T.FUSE_BATCH(int(path[-1])))
+    log(f"  {o.keys.size} blocks, {o.stats['pairs']} pairs")
+    assert_parity(g, o)
+    assert g.stats.status == T.OK and g.stats.pairs_dropped == 0
+
+
+@pytest.mark.parametrize("band", list(SCATTER))
+@pytest.mark.parametrize("cfg", [(16, 1, 4), (16, 1, 8), (32, 2, 8)])
+def test_scattered_tiles_multi_volume(band, cfg):
+    v, tau, opts = SCATTER[band]
+    depths, cams = scattered_frames(2, seed=32, **opts)
+    o = O.fuse_frames(v, tau, 1 << 20, depths, cams)
+    vol = T.Volume(v, tau, 1 << 21, 1 << 20)
+    batch = T.Batch(2)
+    batch.set_config(T.BatchConfig(cfg[0], cfg[1], cfg[2], 0))
+    for d, c in zip(depths, cams):
+        batch.fuse([vol], [torch.from_numpy(d).cuda()], [c])
+    g = result_of(vol)
+    assert_parity(g, o)
+    assert g.stats.status == T.OK and g.stats.pairs_dropped == 0
 
 
 # ---------------------------------------------------------------------------

@@ -12,7 +12,8 @@ from oracle import oracle as O
 from paper_2608_08287_amd import scenes as S
 from paper_2608_08287_amd import tsdf as T
 
-from parity import EMPTY, assert_parity, assert_same_volume, log, result_of, table_arrays
+from parity import (EMPTY, SCATTER, assert_parity, assert_same_volume, log, result_of,
+                    scattered_frames, table_arrays)
 
 pytestmark = pytest.mark.gpu
 
@@ -178,6 +179,34 @@ def test_colour_matches_the_oracle(room, variant):
                     0.0).transpose(0, 2, 1)
     assert np.max(np.abs(mean[order] - want)) < 1e-3
     log(f"  {variant}: {o.keys.size} blocks, colour sums exact")
+
+
+@pytest.mark.parametrize("band", list(SCATTER))
+@pytest.mark.parametrize("path", ["single", "batch"])
+def test_colour_scattered_tiles(band, path):
+    """Tiles touching many blocks (several windows) and many voxels (several
+    passes over the colour accumulator's slots)."""
+    v, tau, opts = SCATTER[band]
+    depths, cams = scattered_frames(2, seed=33, **opts)
+    rng = np.random.default_rng(34)
+    rgba = [rng.integers(0, 1 << 32, d.shape, dtype=np.uint64).astype(np.uint32) for d in depths]
+    ov = O.OracleVolume(v, tau, 1 << 20)
+    for d, c, cam in zip(depths, rgba, cams):
+        ov.fuse_rgb(d, c, cam)
+    o = ov.result()
+    vol = T.Volume(v, tau, 1 << 21, 1 << 20, flags=T.VOLUME_COLOUR)
+    batch = T.Batch(2)
+    for d, c, cam in zip(depths, rgba, cams):
+        dd, cc = torch.from_numpy(d).cuda(), torch.from_numpy(c.view(np.int32)).cuda()
+        if path == "single":
+            vol.fuse_rgb(dd, cc, cam)
+        else:
+            batch.fuse([vol], [dd], [cam], rgbas=[cc])
+    g = result_of(vol)
+    assert_parity(g, o)
+    keys, sums = gpu_colour_sums(vol, o.keys.size, False)
+    assert np.array_equal(keys, o.keys)
+    assert np.array_equal(sums, ov.colour_sums()), "colour sums differ"
 
 
 def test_colour_in_a_mixed_batch(room):
