@@ -411,40 +411,35 @@ constexpr unsigned acc_block_floats(bool colour) {
 // pool.  The dense blocks are taken in windows of kWin (one window unless the
 // tile touches more blocks); per window, each block has a 512-bit mask of the
 // voxels its pairs touch (eight 64-bit words) and per word the first voxel
-// slot of its bits, and the slots hold, as arrays: the TSDF sum; a tagged
-// count (window block << 21 | voxel << 12 | count); and for colour volumes the
-// red, green and blue sums.
+// slot of its bits (16 bits: a window has at most 128 * 512 voxels), and the
+// slots hold, as arrays: the TSDF sum; a tagged count (window block << 21 |
+// voxel << 12 | count); and for colour volumes the red, green and blue sums.
 constexpr unsigned slot_floats(bool colour) { return colour ? 5u : 2u; }
-constexpr unsigned window_blocks(unsigned region_floats) {
-  // the masks and word bases (24 floats per block) take at most half the region
-  return region_floats / 48u < 128u ? region_floats / 48u : 128u;
-}
+constexpr unsigned kWin = 128;
+constexpr unsigned kMetaFloats = kWin * 8u * (8u + 2u) / 4u;  // masks, then word bases
 
-// LDS of one tile.  The key set (phases 1-2) shares its space with the
-// phase-3 region of AB blocks' worth of floats (masks, word bases, voxel
-// slots); the dense-id map (phases 1-3) with the scan's per-wave totals.
+// LDS of one tile: the pool index of each dense block, and a region shared by
+// the key set, the key list and the dense-id map (phases 1-2; the map, which
+// phase 3 reads first, sits at the end) and by phase 3's masks, word bases and
+// voxel slots.  AB sizes the region: AB blocks' worth of floats and 4 KB.
 template <int AB, bool kColour = false>
 struct alignas(16) TileShared {
+  static constexpr unsigned kRegion = AB * acc_block_floats(kColour) + kSetCap;
+  static constexpr unsigned kCap = (kRegion - kMetaFloats) / slot_floats(kColour);
   union alignas(16) {
     struct {
       unsigned long long keys[kSetCap];
       unsigned n;  // distinct keys in the set
+      unsigned pad[3];
+      unsigned short list[kSetCap];
+      unsigned short gap[(4u * kRegion - 12u * kSetCap - 16u) / 2u];
+      unsigned short dense[kSetCap];
     } set;
-    float acc[AB * acc_block_floats(kColour)];
+    float region[kRegion];
   } u;
   int blockd[kSetCap];
-  union {
-    struct {
-      unsigned short dense[kSetCap];
-      unsigned short list[kSetCap];
-    } map;
-    unsigned wsum[kThreads / kWave];
-  } v;
-  static constexpr unsigned kRegion = AB * acc_block_floats(kColour);
-  static constexpr unsigned kWin = window_blocks(kRegion);
-  static constexpr unsigned kCap = (kRegion - 24u * kWin) / slot_floats(kColour);
-  static_assert(kWin >= 32 && kWin <= 128, "a window's block index fits the tag's 7 bits");
-  static_assert(kWin <= (unsigned)kThreads, "one thread per block of a window in the scan");
+  static_assert(sizeof(u.set) == 4u * kRegion, "the dense-id map ends the region");
+  static_assert(2u * kMetaFloats <= kRegion, "the masks and word bases take at most half");
   static_assert(kCap >= 512, "a pass holds at least one block's voxels");
 };
 
@@ -466,8 +461,8 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
   unsigned long long* const s_keys = sh.u.set.keys;
   unsigned* const s_n = &sh.u.set.n;
   int* const s_blockd = sh.blockd;            // pool index per dense block id
-  unsigned short* const s_dense = sh.v.map.dense;  // dense block id per set slot
-  unsigned short* const s_list = sh.v.map.list;    // set slot per dense block id
+  unsigned short* const s_dense = sh.u.set.dense;  // dense block id per set slot
+  unsigned short* const s_list = sh.u.set.list;    // set slot per dense block id
 
   const unsigned tid = threadIdx.x;
   __syncthreads();  // the previous tile of a persistent workgroup is done with the LDS
@@ -631,14 +626,16 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
 
     // Voxel slots, window by window of dense blocks.
     using Shared = TileShared<AB, kColour>;
-    constexpr unsigned kWin = Shared::kWin, kCap = Shared::kCap;
+    constexpr unsigned kCap = Shared::kCap;
     constexpr unsigned kInWin = 1u << 30;  // st: the pair's slot of this window, not its block
-    unsigned long long* const s_mark = reinterpret_cast<unsigned long long*>(sh.u.acc);
-    unsigned* const s_wbase = reinterpret_cast<unsigned*>(sh.u.acc) + 16u * kWin;
-    float* const s_sum = sh.u.acc + 24u * kWin;
+    unsigned long long* const s_mark = reinterpret_cast<unsigned long long*>(sh.u.region);
+    unsigned short* const s_wbase = reinterpret_cast<unsigned short*>(s_mark + 8u * kWin);
+    float* const s_sum = sh.u.region + kMetaFloats;
     unsigned* const s_tag = reinterpret_cast<unsigned*>(s_sum + kCap);
     float* const s_col = s_sum + 2u * kCap;  // colour: [3][kCap]
-    unsigned* const s_wsum = sh.v.wsum;
+    // the scan's per-wave totals: the region's last words, which the map held
+    // before and the slots hold after
+    unsigned* const s_wsum = reinterpret_cast<unsigned*>(sh.u.region + Shared::kRegion) - kThreads / kWave;
     for (unsigned k0 = 0; k0 < n_keys; k0 += kWin) {
       const unsigned kn = n_keys - k0 < kWin ? n_keys - k0 : kWin;
       for (unsigned i = tid; i < kn * 8u; i += kThreads) s_mark[i] = 0ull;
@@ -679,7 +676,7 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
           unsigned at = before + incl - key_total;
 #pragma unroll
           for (int q = 0; q < 8; ++q) {
-            s_wbase[tid * 8u + q] = at;
+            s_wbase[tid * 8u + q] = (unsigned short)at;
             at += cnt[q];
           }
         }
