@@ -375,22 +375,24 @@ __device__ __forceinline__ unsigned tile_of_group(unsigned g, unsigned n_tiles, 
   return xcd * q + (xcd < r ? xcd : r) + local;
 }
 
-// The frames of one launch, passed by value in the kernel arguments.
-template <int NB>
-struct FrameBatch {
-  FrameDev f[NB];
-};
+// Read-only data of a whole launch (kernel arguments, a batch's work list) read
+// through the constant address space, where uniform loads become scalar loads
+// that may be repeated at will instead of values held in registers.
+template <typename T>
+using ConstPtr = const __attribute__((address_space(4))) T*;
 
-// Frame `idx` of the batch; idx is uniform, so this is a chain of scalar
-// selects over the kernel arguments rather than an indexed copy.
+// The arguments of one fused launch, passed by value as the kernel's only
+// argument so that they start the kernel argument segment.  A workgroup reads
+// its frames from that segment with a uniform index: scalar loads of its own
+// frames only, rather than selects over all NB frames held in registers.
 template <int NB>
-__device__ __forceinline__ FrameDev pick_frame(const FrameBatch<NB>& fb, unsigned idx) {
-  FrameDev r = fb.f[0];
-#pragma unroll
-  for (int i = 1; i < NB; ++i)
-    if (idx == (unsigned)i) r = fb.f[i];
-  return r;
-}
+struct FuseArgs {
+  VolumeDev vol;
+  WalkParams wp;
+  FrameDev f[NB];
+  unsigned n_frames, tiles_x, n_tiles;
+  int remap;
+};
 
 // One workgroup = one 16x16 tile of F consecutive frames of the launch's NB
 // frames: workgroup g covers tile g % n_tiles of frames F * (g / n_tiles) + 0..F-1
@@ -493,8 +495,6 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
     n_pts += point ? 1u : 0u;
     const float a = ((float)px[fi] - fr.cx) * fr.ifx;
     const float b = ((float)py[fi] - fr.cy) * fr.ify;
-    int hx[NS], hy[NS], hz[NS];
-    bool hv[NS];
     unsigned long long prev_key = kEmptyKey;
     unsigned prev_slot = kSetNone;
     ovf[fi] = 0u;
@@ -503,22 +503,15 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
       const Sample smp = walk_sample(fr, wp, df, a, b, s - K);
       const bool z_ok = point && (df + (float)(s - K) * wp.v > 0.0f);
       if (z_ok && !smp.in_range) ++n_oor;
-      const bool ok = point && smp.in_range;
-      // a voxel counts once per point: compare with this point's earlier samples
-      bool dup = false;
-#pragma unroll
-      for (int j = 0; j < s; ++j)
-        dup |= hv[j] && hx[j] == smp.vx && hy[j] == smp.vy && hz[j] == smp.vz;
-      hv[s] = ok;
-      hx[s] = smp.vx;
-      hy[s] = smp.vy;
-      hz[s] = smp.vz;
-      const bool pair = ok && !dup && smp.keep;
-      n_pairs += pair ? 1u : 0u;
+      // Whether a sample is kept is a function of its voxel (the centre's
+      // depth against the pixel's), so the voxel-once-per-point rule only has
+      // to compare kept samples; it does so after the key set has placed the
+      // sample's block (below).
+      const bool cand = point && smp.in_range && smp.keep;
       const unsigned long long key = pack_key(smp.vx >> 3, smp.vy >> 3, smp.vz >> 3);
       const unsigned loc = (unsigned)((((smp.vz & 7) * 8) + (smp.vy & 7)) * 8 + (smp.vx & 7));
       // consecutive samples of a point mostly share a block: reuse its slot
-      const bool need = pair && key != prev_key;
+      const bool need = cand && key != prev_key;
       unsigned slot = prev_slot;
       if (need) {
         // every lane inserts its own key; the LDS serialises lanes of one wave
@@ -540,14 +533,33 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
           h = (h + 1) & (kSetCap - 1);
         }
       }
-      if (pair) {
+      if (cand) {
         prev_key = key;
         prev_slot = slot;
       }
+      // A voxel counts once per point.  A kept sample's voxel is (its block's
+      // set slot, its in-block index): one compare with each earlier sample's
+      // state.  The set never loses a key, so a block that found the set full
+      // finds it full again: such samples compare coordinates, recomputed, with
+      // the earlier ones that also found it full (a tile of more than kSetCap
+      // blocks only).
+      const unsigned word = kPairValid | (slot << 9) | loc;
+      bool dup = false;
+      if (cand && slot != kSetNone) {
+#pragma unroll
+        for (int j = 0; j < s; ++j) dup |= st[fi][j] == word;
+      } else if (cand) {
+        for (unsigned m = ovf[fi]; m != 0u; m &= m - 1u) {
+          const Sample o = walk_sample(fr, wp, df, a, b, __builtin_ctz(m) - K);
+          dup |= o.vx == smp.vx && o.vy == smp.vy && o.vz == smp.vz;
+        }
+      }
+      const bool pair = cand && !dup;
+      n_pairs += pair ? 1u : 0u;
       // a pair whose key found the LDS set full is handled on its own in phase 3
       const bool spilled = pair && slot == kSetNone;
       ovf[fi] |= spilled ? (1u << s) : 0u;
-      st[fi][s] = (pair && !spilled) ? (kPairValid | (slot << 9) | loc) : 0u;
+      st[fi][s] = (pair && !spilled) ? word : 0u;
     }
   }
   __syncthreads();
@@ -844,12 +856,16 @@ constexpr int acc_blocks_for(bool colour) { return colour ? kColourAccBlocks : k
 
 template <int K, int F, int NB, FuseMode kMode, bool kColour>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(waves_per_eu_for(F))))
-void fuse_kernel(VolumeDev vol, WalkParams wp, FrameBatch<NB> fb, unsigned n_frames,
-                 unsigned tiles_x, unsigned n_tiles, int remap) {
+void fuse_kernel(FuseArgs<NB> args) {
   constexpr int AB = acc_blocks_for(kColour);
   __shared__ TileShared<AB, kColour> sh;
+  // the argument segment seen through the constant address space (the
+  // compiler keeps the address space through the cast, so reads stay scalar)
+  const FuseArgs<NB>& A =
+      *(const FuseArgs<NB>*)(ConstPtr<FuseArgs<NB>>)__builtin_amdgcn_kernarg_segment_ptr();
+  const unsigned n_tiles = A.n_tiles, tiles_x = A.tiles_x;
   const unsigned group = blockIdx.x / n_tiles;
-  const unsigned tile = tile_of_group(blockIdx.x % n_tiles, n_tiles, remap != 0);
+  const unsigned tile = tile_of_group(blockIdx.x % n_tiles, n_tiles, A.remap != 0);
   const unsigned x = (tile % tiles_x) * kTileW + (threadIdx.x % kTileW);
   const unsigned y = (tile / tiles_x) * kTileH + (threadIdx.x / kTileW);
   FrameDev frs[F];
@@ -857,12 +873,13 @@ void fuse_kernel(VolumeDev vol, WalkParams wp, FrameBatch<NB> fb, unsigned n_fra
 #pragma unroll
   for (int fi = 0; fi < F; ++fi) {
     const unsigned idx = group * F + fi;
-    frs[fi] = pick_frame(fb, idx);
-    if (idx >= n_frames) frs[fi].width = frs[fi].height = 0;  // past the batch: empty
+    const bool in_batch = idx < A.n_frames;
+    frs[fi] = A.f[in_batch ? idx : 0u];
+    if (!in_batch) frs[fi].width = frs[fi].height = 0;  // past the batch: empty
     px[fi] = x;
     py[fi] = y;
   }
-  fuse_tile<K, F, AB, kMode, kColour>(vol, wp, frs, px, py, blockIdx.x, sh);
+  fuse_tile<K, F, AB, kMode, kColour>(A.vol, A.wp, frs, px, py, blockIdx.x, sh);
 }
 
 // Many volumes, one frame each, in one persistent launch.  The grid is a
@@ -876,10 +893,7 @@ void fuse_kernel(VolumeDev vol, WalkParams wp, FrameBatch<NB> fb, unsigned n_fra
 // contributions before they reach the pool.
 //
 // The work list is read-only for the whole launch: it is read through the
-// constant address space, where uniform loads become scalar loads that may be
-// repeated at will instead of values held in registers.
-template <typename T>
-using ConstPtr = const __attribute__((address_space(4))) T*;
+// constant address space (ConstPtr).
 
 // Four workgroups of a plain volume fit a CU's LDS, so registers are capped to
 // match: 128 VGPRs (two pixels per thread need ~146, and spill a few dwords).
@@ -953,10 +967,12 @@ constexpr int max_frames_for(int K) { return 2 * K + 1 <= 9 ? 4 : 2; }
 template <int K, int F, int NB, bool kColour>
 hipError_t launch_fuse_kf(VolumeDev vol, const WalkParams& wp, const FrameDev* frames, int n,
                           FuseMode mode, bool remap, hipStream_t s) {
-  FrameBatch<NB> fb;
+  FuseArgs<NB> args;
+  args.vol = vol;
+  args.wp = wp;
   unsigned w = 0, h = 0;
   for (int i = 0; i < NB; ++i) {
-    fb.f[i] = frames[i < n ? i : 0];
+    args.f[i] = frames[i < n ? i : 0];
     if (i < n) {
       w = frames[i].width > w ? frames[i].width : w;
       h = frames[i].height > h ? frames[i].height : h;
@@ -966,28 +982,31 @@ hipError_t launch_fuse_kf(VolumeDev vol, const WalkParams& wp, const FrameDev* f
   const unsigned ty = (h + kTileH - 1) / kTileH;
   const unsigned n_tiles = tx * ty;
   if (n_tiles == 0) return hipSuccess;
+  args.n_frames = (unsigned)n;
+  args.tiles_x = tx;
+  args.n_tiles = n_tiles;
+  args.remap = remap ? 1 : 0;
   const unsigned groups = ((unsigned)n + F - 1) / F;
   const dim3 grid(n_tiles * groups), block(kThreads);
   if constexpr (F == 1 && NB == 1) {
     switch (mode) {
       case FuseMode::kFused:
         hipLaunchKernelGGL((fuse_kernel<K, 1, 1, FuseMode::kFused, kColour>), grid, block, 0, s,
-                           vol, wp, fb, (unsigned)n, tx, n_tiles, (int)remap);
+                           args);
         break;
       case FuseMode::kAllocate:  // allocation touches no accumulator
         hipLaunchKernelGGL((fuse_kernel<K, 1, 1, FuseMode::kAllocate, false>), grid, block, 0, s,
-                           vol, wp, fb, (unsigned)n, tx, n_tiles, (int)remap);
+                           args);
         break;
       case FuseMode::kIntegrate:
         hipLaunchKernelGGL((fuse_kernel<K, 1, 1, FuseMode::kIntegrate, kColour>), grid, block, 0,
-                           s, vol, wp, fb, (unsigned)n, tx, n_tiles, (int)remap);
+                           s, args);
         break;
     }
   } else {
     (void)mode;
     static_assert(!kColour, "colour frames are fused one per launch or through batches");
-    hipLaunchKernelGGL((fuse_kernel<K, F, NB, FuseMode::kFused, false>), grid, block, 0, s, vol,
-                       wp, fb, (unsigned)n, tx, n_tiles, (int)remap);
+    hipLaunchKernelGGL((fuse_kernel<K, F, NB, FuseMode::kFused, false>), grid, block, 0, s, args);
   }
   return hipGetLastError();
 }
