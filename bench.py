@@ -329,6 +329,159 @@ def bench_multi(args) -> int:
     return 0
 
 
+def bench_stress(args) -> int:
+    """Contention stress, sub-case A: a fronto-parallel plane at 0.5 m (640x480,
+    voxel 4 mm, truncation 1.6 cm), so that most lanes of a wave insert the
+    same keys, fused through a table of 2^16 slots pre-filled with 62,259
+    seeded random blocks (load factor 0.95), so that probe chains are long.
+
+    One step = reset, pre-fill (untimed: the timed window opens at the first
+    frame's event) and the frames fused; plain (one launch per frame) and
+    batched (16 frames per launch) are timed alike.  The gate requires zero
+    dropped contributions.  An untimed run on a probe-histogram volume gives
+    the distribution of probe distances of the frames' key resolutions.
+    """
+    import torch
+
+    from paper_2608_08287_amd import scenes as S
+    from paper_2608_08287_amd import tsdf as T
+
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    w = S.plane_stress_workload("A", n_frames=args.frames, device="cuda")
+    depth = [torch.from_numpy(d).cuda() for d in w.depth]
+    cams = [T.camera_struct(c) for c in w.cameras]
+    pre = torch.from_numpy(np.ascontiguousarray(w.prefill_blocks, dtype=np.int32)).cuda()
+    n_pix = w.depth[0].size
+    log(f"[bench] generated {len(depth)} frames in {time.time() - t0:.1f}s")
+    stream = torch.cuda.current_stream()
+    L = T.lib()
+    sp = T.C.c_void_p(stream.cuda_stream)
+
+    def prepared(flags=0, vol=None):
+        v = vol if vol is not None else T.Volume(w.voxel_size, w.trunc, w.table_capacity,
+                                                   w.pool_capacity, flags=flags)
+        v.reset()
+        v.insert_blocks(pre)
+        torch.cuda.synchronize()
+        return v
+
+    # ---- gate, algorithmic bytes and probe histogram (untimed) ---------------
+    hv = prepared(T.VOLUME_PROBE_HISTOGRAM)
+    n_pre = hv.stats().blocks_total
+    acc_bytes, prev = [], n_pre
+    wv = hv.weight_view()
+    for k in range(len(depth)):
+        before = wv[:prev].reshape(prev, 512).clone()
+        hv.fuse(depth[k], w.cameras[k])
+        nb = hv.stats().blocks_total
+        after = wv[:nb].reshape(nb, 512)
+        changed = after != torch.nn.functional.pad(before, (0, 0, 0, nb - prev))
+        acc_bytes.append(algorithmic_bytes(n_pix, int(changed.any(dim=1).sum()), nb - prev,
+                                           int(changed.sum())))
+        prev = nb
+    st = hv.stats()
+    hist, hist_total = hv.probe_histogram()
+    if st.status != T.OK or st.pairs_dropped or st.lookup_misses:
+        print(f"correctness gate failed: {T.status_str(st.status)} dropped={st.pairs_dropped}",
+              file=sys.stderr)
+        return 1
+    points_per_step = st.points_valid
+    log(f"[bench] gate ok: {st.points_valid} points, {st.pairs} pairs, {st.blocks_total} blocks "
+        f"({n_pre} pre-filled), load factor {st.blocks_total / w.table_capacity:.4f}, "
+        f"max probe {st.max_probe}")
+
+    vol = T.Volume(w.voxel_size, w.trunc, w.table_capacity, w.pool_capacity)
+    h = vol.handle
+    ptrs = [T.C.c_void_p(d.data_ptr()) for d in depth]
+    cam_refs = [T.C.byref(c) for c in cams]
+    fpl = max(1, min(args.batch, 16))
+    chunks = [(i, min(fpl, len(ptrs) - i)) for i in range(0, len(ptrs), fpl)]
+    ptr_arr = (T.C.c_void_p * len(ptrs))(*[d.data_ptr() for d in depth])
+    cam_arr = (T.CameraC * len(cams))(*cams)
+    bflags = T.FUSE_BATCH(args.per_group)
+
+    def plain(events):
+        for k in range(len(ptrs)):
+            events[k].record(stream)
+            if L.tsdf_fuse_frame(h, ptrs[k], cam_refs[k], sp) != T.OK:
+                raise RuntimeError("fuse failed")
+        events[len(ptrs)].record(stream)
+
+    def batched(events):
+        for j, (i0, n) in enumerate(chunks):
+            events[j].record(stream)
+            p_ = T.C.cast(T.C.byref(ptr_arr, i0 * T.C.sizeof(T.C.c_void_p)), T.C.c_void_p)
+            c_ = T.C.cast(T.C.byref(cam_arr, i0 * T.C.sizeof(T.CameraC)), T.C.c_void_p)
+            if L.tsdf_fuse_frames(h, n, p_, c_, bflags, sp) != T.OK:
+                raise RuntimeError("batched fusion failed")
+        events[len(chunks)].record(stream)
+
+    def timed(run, n_events):
+        ms = []
+        for step in range(args.warmup + args.steps):
+            prepared(vol=vol)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(n_events + 1)]
+            run(ev)
+            torch.cuda.synchronize()
+            if step >= args.warmup:
+                ms.append([ev[k].elapsed_time(ev[k + 1]) for k in range(n_events)])
+            s_ = vol.stats()
+            if s_.status != T.OK or s_.pairs_dropped or s_.points_valid != points_per_step:
+                raise RuntimeError("timed run changed the result")
+        return np.array(ms)
+
+    frame_ms = timed(plain, len(ptrs))
+    launch_ms = timed(batched, len(chunks))
+    step_p = float(frame_ms.sum(axis=1).mean())
+    step_b = float(launch_ms.sum(axis=1).mean())
+    value = points_per_step / (step_b * 1e-3)
+    full = [j for j, (_, n) in enumerate(chunks) if n == fpl]
+    mean_launch_ms = float(launch_ms[:, full].mean())
+    bytes_per_launch = float(np.mean([sum(acc_bytes[i0:i0 + n]) for (i0, n) in chunks if n == fpl]))
+    achieved = bytes_per_launch / (mean_launch_ms * 1e-3) / 1e9
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": step_b, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {
+            "workload": f"contention stress A: {len(ptrs)} frames of 640x480, fronto-parallel "
+                        "plane at 0.5 m, voxel 4 mm, truncation 1.6 cm, table 2^16 slots "
+                        f"pre-filled with {n_pre} random blocks (load factor 0.95), pool 2^16",
+            "path": f"batched: tsdf_fuse_frames, {fpl} frames per launch, "
+                    f"{args.per_group} frame(s) per workgroup",
+            "points_per_step": points_per_step, "parallelism": "single GPU",
+        },
+        "p50_frame_ms": float(np.percentile(frame_ms, 50)),
+        "p99_frame_ms": float(np.percentile(frame_ms, 99)),
+        "frame_latency_path": "plain (one launch per frame)",
+        "plain": {"value": points_per_step / (step_p * 1e-3), "unit": "points/s",
+                  "ms_per_step": step_p, "mean_frame_ms": float(frame_ms.mean())},
+        "batched": {"value": value, "unit": "points/s", "mean_launch_ms": mean_launch_ms,
+                    "p99_launch_ms": float(np.percentile(launch_ms[:, full], 99))},
+        "table": {
+            "load_factor": st.blocks_total / w.table_capacity, "blocks_prefilled": n_pre,
+            "blocks_total": st.blocks_total, "pairs_dropped": st.pairs_dropped,
+            "max_probe": st.max_probe,
+            "probe_histogram": {("0" if b == 0 else f"{1 << (b - 1)}-{(1 << b) - 1}"
+                                 if b < T.PROBE_HIST_BINS - 1 else f">={1 << (b - 1)}"): int(c)
+                                for b, c in enumerate(hist) if c},
+            "resolutions": int(hist.sum()),
+            "mean_probe_distance": hist_total / max(1, int(hist.sum())),
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "kernel": f"fuse_kernel<4, {args.per_group}, 16, fused>",
+            "algorithmic_bytes_per_launch": bytes_per_launch, "mean_launch_ms": mean_launch_ms,
+        },
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def bench_serve(args) -> int:
     """Serving: sessions fed by Poisson frame arrivals, through tsdf_server_*.
 
@@ -492,10 +645,12 @@ def main() -> int:
     ap.add_argument("--variant", choices=["main", "slot", "colour"], default="main",
                     help="trajectory: the volume design (main; slot: block index = table slot, "
                          "pool = table; colour: three colour sums per voxel)")
-    ap.add_argument("--workload", choices=["trajectory", "multi", "serve"], default="trajectory",
+    ap.add_argument("--workload", choices=["trajectory", "multi", "serve", "stress"],
+                    default="trajectory",
                     help="trajectory: one volume, the 300-frame orbit (default); multi: many "
                          "volumes, one frame each per tick, through the batch API; serve: "
-                         "sessions with Poisson arrivals through the server")
+                         "sessions with Poisson arrivals through the server; stress: the "
+                         "fronto-parallel plane through a table at load factor 0.95")
     ap.add_argument("--sessions", type=int, default=256, help="serve: sessions")
     ap.add_argument("--rate", type=float, default=3000.0, help="serve: frames/s, all sessions")
     ap.add_argument("--duration", type=float, default=1.0, help="serve: seconds of arrivals")
@@ -512,11 +667,14 @@ def main() -> int:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "the volume is not sharded across GPUs", file=sys.stderr)
         return 2
-    if args.workload in ("multi", "serve"):
+    if args.workload in ("multi", "serve", "stress"):
         import torch
         if not torch.cuda.is_available():
             print("bench.py needs a GPU", file=sys.stderr)
             return 1
+        if args.workload == "stress":
+            args.frames = min(args.frames, 100)
+            return bench_stress(args)
         return bench_multi(args) if args.workload == "multi" else bench_serve(args)
 
     import torch

@@ -78,6 +78,11 @@ typedef enum tsdf_status {
  *       (tsdf_fuse_frame_rgb, tsdf_fuse_item.rgba_dev). */
 #define TSDF_VOLUME_SLOT_INDEX 0x1u
 #define TSDF_VOLUME_COLOUR 0x2u
+/* Instrumentation, not a design variant: the volume also counts, for every
+ * resolution of a tile's block key against the table (Section 2.3's probe),
+ * its probe distance in a histogram read by tsdf_probe_histogram.  Costs one
+ * device atomic per resolution; results are otherwise unchanged. */
+#define TSDF_VOLUME_PROBE_HISTOGRAM 0x4u
 
 typedef struct tsdf_volume_params {
   float voxel_size;        /* voxel edge in metres, finite and > 0 */
@@ -224,6 +229,21 @@ tsdf_status tsdf_fuse_frames(tsdf_volume* vol, uint32_t n_frames, const float* c
  * condition (INTERNAL > TABLE_FULL > POOL_EXHAUSTED > COORD_RANGE), or TSDF_OK.
  * `out` may be NULL. */
 tsdf_status tsdf_query_status(tsdf_volume* vol, void* hip_stream, tsdf_stats* out);
+
+/* Probe-distance histogram of a TSDF_VOLUME_PROBE_HISTOGRAM volume since its
+ * creation or last reset.  A resolution is one (workgroup tile, distinct block
+ * key) of a fused frame; its distance is the number of slots past the key's
+ * home where the probe found the key or claimed a slot for it.
+ *   bins            host array of TSDF_PROBE_HIST_BINS: bins[0] counts
+ *                   resolutions at distance 0, bins[b] for b >= 1 those at
+ *                   a distance in [2^(b-1), 2^b), the last bin open-ended
+ *   total_distance  optional (NULL): the distances summed
+ * Waits for `hip_stream` like tsdf_query_status.  INVALID_ARGUMENT if the
+ * volume was made without the flag or `bins` is NULL; nothing is written
+ * then. */
+#define TSDF_PROBE_HIST_BINS 16u
+tsdf_status tsdf_probe_histogram(tsdf_volume* vol, void* hip_stream, uint64_t* bins,
+                                 uint64_t* total_distance);
 
 /* Wait for `hip_stream` to learn the block count n, then, if n <= max_blocks,
  * enqueue the extraction of every allocated block in pool order:

@@ -6,6 +6,7 @@
 // if an argument is wrong.  No entry point allocates device memory; the only
 // host allocation is the volume handle.
 
+#include <cstddef>
 #include <cstdlib>
 
 #include "tsdf_host.h"
@@ -28,7 +29,8 @@ bool make_layout(const tsdf_volume_params* p, tsdf_layout* out) {
   const int K = band_half(*p);
   if (K < 1 || K > TSDF_MAX_BAND_HALF) return false;
   if (p->pool_capacity < 1 || p->pool_capacity > TSDF_MAX_POOL_BLOCKS) return false;
-  if ((p->flags & ~(TSDF_VOLUME_SLOT_INDEX | TSDF_VOLUME_COLOUR)) != 0) return false;
+  if ((p->flags & ~(TSDF_VOLUME_SLOT_INDEX | TSDF_VOLUME_COLOUR | TSDF_VOLUME_PROBE_HISTOGRAM)) != 0)
+    return false;
   const bool slot_index = (p->flags & TSDF_VOLUME_SLOT_INDEX) != 0;
   const bool colour = (p->flags & TSDF_VOLUME_COLOUR) != 0;
   uint32_t C = p->table_capacity;
@@ -106,7 +108,7 @@ tsdf_status tsdf_create_volume(const tsdf_volume_params* params, void* dev_arena
   v->dev.table_capacity = L.table_capacity;
   v->dev.pool_capacity = L.pool_capacity;
   v->dev.slot_index = slot_index ? 1u : 0u;
-  v->dev.pad = 0;
+  v->dev.probe_hist = (L.flags & TSDF_VOLUME_PROBE_HISTOGRAM) ? 1u : 0u;
   hipStream_t s = as_stream(hip_stream);
   tsdf_status st = init_table_and_counters(v, s);
   const size_t pool_words = (size_t)L.pool_capacity * tsdf::kBlockFloats;
@@ -267,6 +269,23 @@ tsdf_status tsdf_query_status(tsdf_volume* vol, void* hip_stream, tsdf_stats* ou
   if (bits & TSDF_FLAG_TABLE_FULL) return TSDF_ERR_TABLE_FULL;
   if (bits & TSDF_FLAG_POOL_EXHAUSTED) return TSDF_ERR_POOL_EXHAUSTED;
   if (bits & TSDF_FLAG_COORD_RANGE) return TSDF_ERR_COORD_RANGE;
+  return TSDF_OK;
+}
+
+tsdf_status tsdf_probe_histogram(tsdf_volume* vol, void* hip_stream, uint64_t* bins,
+                                 uint64_t* total_distance) {
+  if (!vol || !bins || !vol->dev.probe_hist) return TSDF_ERR_INVALID_ARGUMENT;
+  hipStream_t s = as_stream(hip_stream);
+  unsigned long long h[TSDF_PROBE_HIST_BINS + 1];  // the bins, then the sum
+  static_assert(offsetof(tsdf::DevCounters, probe_sum) ==
+                    offsetof(tsdf::DevCounters, probe_hist) + 8 * TSDF_PROBE_HIST_BINS,
+                "the sum follows the bins");
+  if (hipMemcpyAsync(h, vol->dev.ctr->probe_hist, sizeof(h), hipMemcpyDeviceToHost, s) !=
+      hipSuccess)
+    return TSDF_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return TSDF_ERR_HIP;
+  for (unsigned i = 0; i < TSDF_PROBE_HIST_BINS; ++i) bins[i] = h[i];
+  if (total_distance) *total_distance = h[TSDF_PROBE_HIST_BINS];
   return TSDF_OK;
 }
 

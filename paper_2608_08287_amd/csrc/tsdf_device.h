@@ -318,6 +318,13 @@ __device__ int resolve_key(const VolumeDev& vol, unsigned long long want, bool a
   return result;
 }
 
+// Probe-histogram volumes: one resolution at `probes` slots past home.
+__device__ __forceinline__ void count_probe(const VolumeDev& vol, unsigned probes) {
+  const unsigned bin = probes == 0u ? 0u : 32u - (unsigned)__builtin_clz(probes);
+  add_u64(&vol.ctr->probe_hist[bin < TSDF_PROBE_HIST_BINS ? bin : TSDF_PROBE_HIST_BINS - 1u], 1ull);
+  if (probes) add_u64(&vol.ctr->probe_sum, probes);
+}
+
 // ---------------------------------------------------------------------------
 // The band walk of one sample (shared by every phase that needs a voxel).
 // ---------------------------------------------------------------------------
@@ -581,6 +588,7 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
       s_dense[h] = (unsigned short)j;
       my_probe_max = probes > my_probe_max ? probes : my_probe_max;
       my_missing += missing ? 1u : 0u;
+      if (vol.probe_hist) count_probe(vol, probes);
     }
   }
   __syncthreads();
@@ -618,6 +626,7 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
         const int blk = resolve_key<kInsert>(
             vol, pack_key(smp.vx >> 3, smp.vy >> 3, smp.vz >> 3), true, probes, missing);
         my_missing += missing ? 1u : 0u;
+        if (vol.probe_hist) count_probe(vol, probes);
         if (blk >= 0) {
           const unsigned loc =
               (unsigned)((((smp.vz & 7) * 8) + (smp.vy & 7)) * 8 + (smp.vx & 7));

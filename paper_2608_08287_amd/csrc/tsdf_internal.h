@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/tsdf.h"
+
 namespace tsdf {
 
 // One hash-table slot (Section 2.1): 64-bit packed key, 32-bit pool index,
@@ -40,7 +42,12 @@ struct DevCounters {
   unsigned long long pairs_dropped;
   unsigned long long coord_out_of_range;
   unsigned long long pad1[14];
-  unsigned long long pad2[32];
+  // probe-histogram volumes: (tile, key) resolutions by probe distance, bin
+  // 0 for distance 0 and bin b >= 1 for distances in [2^(b-1), 2^b), the last
+  // bin open-ended
+  unsigned long long probe_hist[TSDF_PROBE_HIST_BINS];
+  unsigned long long probe_sum;  // and their summed probe distance
+  unsigned long long pad2[31 - TSDF_PROBE_HIST_BINS];
   // sharded traffic counters (summed on the host)
   unsigned long long points_valid[kCounterShards];
   unsigned long long pairs[kCounterShards];
@@ -77,7 +84,7 @@ struct VolumeDev {
   unsigned table_capacity;
   unsigned pool_capacity;
   unsigned slot_index;             // 1: a block's pool index is its table slot
-  unsigned pad;
+  unsigned probe_hist;             // 1: count resolutions by probe distance
 };
 
 // Pool index of the i-th allocated block.

@@ -11,7 +11,7 @@ from __future__ import annotations
 import ctypes as C
 import os
 from dataclasses import dataclass
-from typing import Optional, Sequence
+from typing import Optional, Sequence, Tuple
 
 import numpy as np
 import torch
@@ -25,7 +25,8 @@ OK, ERR_INVALID_ARGUMENT, ERR_BUFFER_TOO_SMALL, ERR_POOL_EXHAUSTED, ERR_TABLE_FU
 FLAG_POOL_EXHAUSTED, FLAG_TABLE_FULL, FLAG_COORD_RANGE, FLAG_INTERNAL = 1, 2, 4, 8
 FUSE_DEFAULT, FUSE_TWO_PASS, FUSE_ALLOCATE_ONLY, FUSE_INTEGRATE_ONLY = 0, 1, 2, 3
 FUSE_XCD_REMAP = 0x100
-VOLUME_SLOT_INDEX, VOLUME_COLOUR = 0x1, 0x2
+VOLUME_SLOT_INDEX, VOLUME_COLOUR, VOLUME_PROBE_HISTOGRAM = 0x1, 0x2, 0x4
+PROBE_HIST_BINS = 16
 
 
 def FUSE_BATCH(m: int) -> int:
@@ -37,7 +38,7 @@ EMPTY_KEY = 0xFFFFFFFFFFFFFFFF
 EXPORTED_SYMBOLS = (
     "tsdf_volume_bytes", "tsdf_volume_layout", "tsdf_create_volume", "tsdf_destroy_volume",
     "tsdf_reset_volume", "tsdf_fuse_frame", "tsdf_fuse_frame_ex", "tsdf_fuse_frames",
-    "tsdf_query_status",
+    "tsdf_query_status", "tsdf_probe_histogram",
     "tsdf_extract_blocks", "tsdf_extract_mesh", "tsdf_insert_blocks", "tsdf_status_str",
     "tsdf_fuse_frame_rgb", "tsdf_extract_colour",
     "tsdf_batch_workspace_bytes", "tsdf_batch_create", "tsdf_batch_destroy",
@@ -138,6 +139,8 @@ def lib() -> C.CDLL:
         L.tsdf_fuse_frames.argtypes = [P, U32, P, P, U32, P]
         L.tsdf_query_status.restype = I
         L.tsdf_query_status.argtypes = [P, P, C.POINTER(StatsC)]
+        L.tsdf_probe_histogram.restype = I
+        L.tsdf_probe_histogram.argtypes = [P, P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
         L.tsdf_extract_blocks.restype = I
         L.tsdf_extract_blocks.argtypes = [P, P, U32, P, P, P, C.POINTER(U32)]
         L.tsdf_fuse_frame_rgb.restype = I
@@ -278,6 +281,17 @@ class _VolumeCalls:
         return Stats(s.points_valid, s.pairs, s.pairs_dropped, s.coord_out_of_range, s.blocks_total,
                      s.keys_pool_overflow, s.table_full_events, s.max_probe, s.lookup_misses,
                      s.status_bits, s.frames, st)
+
+    def probe_histogram(self, stream=None) -> Tuple[np.ndarray, int]:
+        """(resolutions by probe distance, bin 0: distance 0, bin b:
+        [2^(b-1), 2^b); their summed distance); the volume must have been made
+        with VOLUME_PROBE_HISTOGRAM."""
+        out = (C.c_uint64 * PROBE_HIST_BINS)()
+        total = C.c_uint64()
+        st = lib().tsdf_probe_histogram(self._h, _stream_ptr(stream), out, C.byref(total))
+        if st != OK:
+            raise TsdfError(st, "tsdf_probe_histogram")
+        return np.array(out[:], dtype=np.uint64), int(total.value)
 
     def extract(self, stream=None) -> Extracted:
         n = C.c_uint32(0)

@@ -60,8 +60,12 @@ def test_variant_layouts():
     assert col.total_bytes - col.colour == P * 1536 * 4 and col.colour % 256 == 0
     both = T.layout(T.volume_params(0.01, 0.04, 0, P, T.VOLUME_SLOT_INDEX | T.VOLUME_COLOUR))
     assert both.total_bytes == slot.total_bytes + P * 1536 * 4
+    # the probe histogram is instrumentation: it changes no region
+    hist = T.layout(T.volume_params(0.01, 0.04, 0, P, T.VOLUME_PROBE_HISTOGRAM))
+    plain = T.layout(T.volume_params(0.01, 0.04, 0, P))
+    assert hist.total_bytes == plain.total_bytes and hist.flags == T.VOLUME_PROBE_HISTOGRAM
     for bad in (T.volume_params(0.01, 0.04, 2 * P, P, T.VOLUME_SLOT_INDEX),
-                T.volume_params(0.01, 0.04, 0, P, 0x4)):
+                T.volume_params(0.01, 0.04, 0, P, 0x8)):
         assert T.volume_bytes(bad) == 0
 
 

@@ -325,6 +325,73 @@ def test_scattered_tiles_multi_volume(band, cfg):
 
 
 # ---------------------------------------------------------------------------
+# Probe-distance histogram (instrumented volumes)
+# ---------------------------------------------------------------------------
+
+def probe_bins(d: np.ndarray) -> np.ndarray:
+    """Histogram bin of each probe distance: 0 for 0, b for [2^(b-1), 2^b)."""
+    d = np.asarray(d, dtype=np.int64)
+    b = np.zeros(d.shape, dtype=np.int64)
+    nz = d > 0
+    b[nz] = np.floor(np.log2(d[nz])).astype(np.int64) + 1
+    return np.minimum(b, T.PROBE_HIST_BINS - 1)
+
+
+def test_probe_histogram_of_one_tile_is_the_probe_model():
+    """A 16x16 frame is one tile, so each of its distinct keys is resolved
+    once, at the distance where it ends up.  Linear probing makes the total
+    displacement of a key set independent of insertion order, and the
+    pre-filled keys never move: so the frame's summed probe distance is the
+    probe model's total over all keys less its total over the pre-fill alone,
+    through a table pre-filled to a load factor near 0.95."""
+    depths, cams = scattered_frames(1, W=16, H=16, seed=41, focal=20.0, lo=0.4, hi=2.0)
+    v, tau, C, P = 0.004, 0.016, 4096, 8192
+    prefill = S.random_block_coords(3300, seed=42)
+    o = O.fuse_frames(v, tau, P, depths, cams, prefill)
+    vol = T.Volume(v, tau, C, P, flags=T.VOLUME_PROBE_HISTOGRAM)
+    vol.insert_blocks(torch.from_numpy(prefill.astype(np.int32)).cuda())
+    vol.fuse(torch.from_numpy(depths[0]).cuda(), cams[0])
+    hist, total = vol.probe_histogram()
+    g = result_of(vol)
+    assert_parity(g, o)
+    pre = np.array([O.pack_key(*map(int, b)) for b in prefill], dtype=np.uint64)
+    frame = np.setdiff1d(o.keys, pre)
+    assert 100 < frame.size < 1024  # one LDS key set, no overflow
+    want_total = int(O.probe_model(o.keys, C).disp_of.sum()) - int(O.probe_model(pre, C).disp_of.sum())
+    log(f"  {frame.size} keys of the frame; load factor {o.keys.size / C:.3f}; total distance "
+        f"{total} (model {want_total}); histogram {hist.tolist()}")
+    assert int(hist.sum()) == frame.size
+    assert total == want_total
+    # the bins bracket the total: each resolution's distance lies in its bin
+    lo = sum(int(c) * (0 if b == 0 else 1 << (b - 1)) for b, c in enumerate(hist))
+    hi = sum(int(c) * (0 if b == 0 else (1 << b) - 1) for b, c in enumerate(hist))
+    assert lo <= total <= hi
+    top = int(np.nonzero(hist)[0].max())
+    assert top == int(probe_bins(np.array([g.stats.max_probe]))[0])
+
+
+def test_probe_histogram_changes_nothing_else(room):
+    w, o = room
+    plain = run_workload(w)
+    vol = T.Volume(w.voxel_size, w.trunc, w.table_capacity, w.pool_capacity,
+                   flags=T.VOLUME_PROBE_HISTOGRAM)
+    for d, c in zip(w.depth, w.cameras):
+        vol.fuse(torch.from_numpy(d).cuda(), c)
+    g = result_of(vol)
+    assert_parity(g, o)
+    assert np.array_equal(g.keys, plain.keys) and np.array_equal(g.weights, plain.weights)
+    hist, total = vol.probe_histogram()
+    top = int(np.nonzero(hist)[0].max())
+    assert top == int(probe_bins(np.array([g.stats.max_probe]))[0])
+    assert int(hist.sum()) >= g.stats.blocks_total
+    vol.reset()
+    hist, total = vol.probe_histogram()
+    assert int(hist.sum()) == 0 and total == 0
+    with pytest.raises(T.TsdfError):
+        T.Volume(w.voxel_size, w.trunc, 1024, 512).probe_histogram()
+
+
+# ---------------------------------------------------------------------------
 # Several frames per launch (tsdf_fuse_frames)
 # ---------------------------------------------------------------------------
 
