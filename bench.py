@@ -6,7 +6,7 @@ spheres (voxel 5 mm, truncation 2 cm, table of 2^20 slots, pool of 2^18 blocks).
 
 One step = reset the volume, then fuse all frames of the trajectory into it.
 Depth frames are resident in HBM before timing starts.  The headline `value` is
-the trajectory fused through tsdf_fuse_frames (16 frames per launch); the plain
+the trajectory fused through tsdf_fuse_frames (32 frames per launch); the plain
 path (one tsdf_fuse_frame launch per frame) is timed beside it and supplies the
 per-frame latency percentiles.  Also reported: the HBM roofline fraction of the
 headline path's fusion kernel on algorithmic bytes, and the CPU oracle's
@@ -337,7 +337,7 @@ def bench_stress(args) -> int:
 
     One step = reset, pre-fill (untimed: the timed window opens at the first
     frame's event) and the frames fused; plain (one launch per frame) and
-    batched (16 frames per launch) are timed alike.  The gate requires zero
+    batched (32 frames per launch) are timed alike.  The gate requires zero
     dropped contributions.  An untimed run on a probe-histogram volume gives
     the distribution of probe distances of the frames' key resolutions.
     """
@@ -395,7 +395,7 @@ def bench_stress(args) -> int:
     h = vol.handle
     ptrs = [T.C.c_void_p(d.data_ptr()) for d in depth]
     cam_refs = [T.C.byref(c) for c in cams]
-    fpl = max(1, min(args.batch, 16))
+    fpl = max(1, min(args.batch, 32))
     chunks = [(i, min(fpl, len(ptrs) - i)) for i in range(0, len(ptrs), fpl)]
     ptr_arr = (T.C.c_void_p * len(ptrs))(*[d.data_ptr() for d in depth])
     cam_arr = (T.CameraC * len(cams))(*cams)
@@ -473,7 +473,7 @@ def bench_stress(args) -> int:
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "kernel": f"fuse_kernel<4, {args.per_group}, 16, fused>",
+            "kernel": f"fuse_kernel<4, {args.per_group}, 32, fused>",
             "algorithmic_bytes_per_launch": bytes_per_launch, "mean_launch_ms": mean_launch_ms,
         },
         "cpu_baseline": None,
@@ -635,7 +635,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", choices=["fused", "two_pass", "fused_xcd_remap"], default="fused",
                     help="kernel structure of the plain per-frame path")
-    ap.add_argument("--batch", type=int, default=16,
+    ap.add_argument("--batch", type=int, default=32,
                     help="frames per tsdf_fuse_frames call on the headline path")
     ap.add_argument("--per-group", type=int, default=2,
                     help="frames summed per workgroup on the headline path (1, 2 or 4)")
@@ -730,7 +730,7 @@ def main() -> int:
         if events is not None:
             events[len(ptrs)].record(stream)
 
-    fpl = max(1, min(args.batch, 16))  # frames per launch
+    fpl = max(1, min(args.batch, 32))  # frames per launch
     chunks = [(i, min(fpl, len(ptrs) - i)) for i in range(0, len(ptrs), fpl)]
     ptr_arr = (T.C.c_void_p * len(ptrs))(*[d.data_ptr() for d in depth])
     cam_arr = (T.CameraC * len(cams))(*cams)
@@ -924,7 +924,7 @@ def main() -> int:
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": ("fuse_multi_kernel<4, 1, 4, colour>" if colour
-                       else f"fuse_kernel<4, {args.per_group}, 16, fused>"),
+                       else f"fuse_kernel<4, {args.per_group}, 32, fused>"),
             "algorithmic_bytes_per_launch": bytes_per_launch,
             "mean_launch_ms": mean_launch_ms,
             "touched_voxels_per_frame": acc["V"] / len(ptrs),

@@ -205,7 +205,7 @@ tsdf_status tsdf_fuse_frame_ex(tsdf_volume* vol, const float* depth_dev, const t
 tsdf_status tsdf_fuse_frame_rgb(tsdf_volume* vol, const float* depth_dev, const uint32_t* rgba_dev,
                                 const tsdf_camera* cam, uint32_t flags, void* hip_stream);
 
-/* Fuse `n_frames` depth frames into the volume, up to 16 frames per launch:
+/* Fuse `n_frames` depth frames into the volume, up to 32 frames per launch:
  * the tiles of all frames of a launch share one grid, so one frame's start-up
  * overlaps another's pool updates.  Each workgroup takes the same 16x16 pixel
  * tile of F consecutive frames and sums their contributions in LDS before

@@ -107,7 +107,7 @@ struct WalkParams {
 };
 
 // Frames fused by one launch of tsdf_fuse_frames.
-constexpr int kMaxBatchFrames = 16;
+constexpr int kMaxBatchFrames = 32;
 
 enum class FuseMode : int { kFused = 0, kAllocate = 1, kIntegrate = 2 };
 
