@@ -427,13 +427,20 @@ constexpr unsigned slot_floats(bool colour) { return colour ? 5u : 2u; }
 constexpr unsigned kWin = 128;
 constexpr unsigned kMetaFloats = kWin * 8u * (8u + 2u) / 4u;  // masks, then word bases
 
+// Floats of the shared region (below): AB pool blocks' worth and 4 KiB for a
+// plain volume; 48 KiB for a colour volume, whose slots are 2.5 times as wide
+// (52 KiB per workgroup with the block indices, three per CU either way).
+constexpr unsigned region_floats(int AB, bool colour) {
+  return colour ? 12288u : (unsigned)AB * kBlockFloats + kSetCap;
+}
+
 // LDS of one tile: the pool index of each dense block, and a region shared by
 // the key set, the key list and the dense-id map (phases 1-2; the map, which
 // phase 3 reads first, sits at the end) and by phase 3's masks, word bases and
-// voxel slots.  AB sizes the region: AB blocks' worth of floats and 4 KB.
+// voxel slots.
 template <int AB, bool kColour = false>
 struct alignas(16) TileShared {
-  static constexpr unsigned kRegion = AB * acc_block_floats(kColour) + kSetCap;
+  static constexpr unsigned kRegion = region_floats(AB, kColour);
   static constexpr unsigned kCap = (kRegion - kMetaFloats) / slot_floats(kColour);
   union alignas(16) {
     struct {
@@ -797,16 +804,29 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
           }
         }
         if (kColour) {
-          // colour sums: one lane per slot, a zero sum needs no update
-          for (unsigned j = tid; j < n_here; j += kThreads) {
-            const unsigned tg = s_tag[j];
-            const int blk = s_blockd[k0 + (tg >> 21)];
-            if (blk < 0) continue;
-            const unsigned loc = (tg >> 12) & 511u;
+          // colour sums: three lanes per slot (its red, green and blue sums), so
+          // a wave instruction covers 21 slots and a touched 96-byte colour row
+          // costs about two requests; a zero sum needs no update
+          constexpr unsigned kPer = kThreads / 3u;  // slots per iteration
+          const unsigned c = tid % 3u;
+          for (unsigned j0 = tid / 3u; j0 < n_here; j0 += 2u * kPer) {
+            unsigned tg[2];
+            float cv[2];
 #pragma unroll
-            for (unsigned c = 0; c < 3; ++c) {
-              const float cv = s_col[c * kCap + j];
-              if (cv != 0.0f) add_f32(vol.colour + (size_t)blk * kColourFloats + colour_index(loc, c), cv);
+            for (int q = 0; q < 2; ++q) {
+              const unsigned j = j0 + (unsigned)q * kPer;
+              const bool ok = tid < 3u * kPer && j < n_here;
+              tg[q] = ok ? s_tag[j] : 0u;
+              cv[q] = ok ? s_col[c * kCap + j] : 0.0f;
+            }
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+              if (cv[q] == 0.0f) continue;
+              const int blk = s_blockd[k0 + (tg[q] >> 21)];
+              if (blk >= 0)
+                add_f32(vol.colour + (size_t)blk * kColourFloats +
+                            colour_index((tg[q] >> 12) & 511u, c),
+                        cv[q]);
             }
           }
         }
