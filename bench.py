@@ -60,6 +60,27 @@ def algorithmic_bytes(n_pix: int, touched_blocks: int, new_blocks: int, touched_
     return 4 * n_pix + 16 * touched_blocks + 24 * new_blocks + 16 * touched_voxels + extra
 
 
+def atomic_ceiling(T, torch, stream) -> dict:
+    """G requests/s that device-scope fp32 atomic adds sustain on a 1 GiB
+    buffer: in the fused kernels' flush pattern (about 12 pool rows per wave
+    instruction, 5 lanes per row) and in whole 64-byte rows (4 rows of 16
+    lanes)."""
+    buf = torch.zeros(1 << 28, dtype=torch.float32, device="cuda")
+    out = {}
+    for name, rows, lanes in (("flush_pattern", 12, 5), ("full_rows", 4, 16)):
+        waves, iters = 16384, 64
+        T.measure_atomic_rate(buf, waves, iters, rows, lanes, stream)  # warm-up
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(4):
+            T.measure_atomic_rate(buf, waves, iters, rows, lanes, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out[name] = 4 * waves * iters * rows / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del buf
+    return out
+
+
 def tick_accounting(vols, before_blocks, before_w, n_pix) -> tuple[int, dict]:
     """Algorithmic bytes of one tick over many volumes, from weight snapshots."""
     import torch
@@ -847,6 +868,26 @@ def main() -> int:
                 tr.get("per_group") == args.per_group:
             traffic = tr.get("bytes_per_launch")
 
+    # ---- memory-side atomic requests of the headline kernel and their ceiling
+    atomics = None
+    if args.variant == "main":
+        ceiling = atomic_ceiling(T, torch, stream)
+        req = None
+        if os.path.exists(TRAFFIC_FILE):
+            tr = json.load(open(TRAFFIC_FILE))
+            if tr.get("kernel_sha") == kernel_sha() and tr.get("batch") == fpl and \
+                    tr.get("per_group") == args.per_group:
+                req = tr.get("atomic_requests_per_dispatch")
+        atomics = {
+            "unit": "G requests/s", "ceiling": ceiling["flush_pattern"],
+            "ceiling_full_rows": ceiling["full_rows"],
+            "requests_per_launch": req,
+            "achieved": req / (mean_launch_ms * 1e-3) / 1e9 if req else None,
+            "frac": (req / (mean_launch_ms * 1e-3) / 1e9) / ceiling["flush_pattern"] if req else None,
+            "note": "device-scope fp32 atomic requests (TCC_EA0_ATOMIC) of one launch against the "
+                    "rate tsdf_measure_atomic_rate sustains in the flush's pattern",
+        }
+
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import oracle as O
@@ -931,6 +972,7 @@ def main() -> int:
             "touched_blocks_per_frame": acc["Bt"] / len(ptrs),
             "new_blocks_per_frame": acc["Bn"] / len(ptrs),
         },
+        "atomics": atomics,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

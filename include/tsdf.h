@@ -290,6 +290,20 @@ tsdf_status tsdf_extract_colour(tsdf_volume* vol, void* hip_stream, uint32_t max
 tsdf_status tsdf_extract_mesh(tsdf_volume* vol, void* hip_stream, uint32_t max_triangles,
                               float* vertices_dev, uint64_t* ids_dev, uint32_t* n_triangles_out);
 
+/* Measurement only (no volume): the memory-side rate of the device-scope fp32
+ * atomic adds with which fusion flushes its sums into the pool.  Launches
+ * `waves` waves (a multiple of 4, at most 2^24); each issues `iters` (at most
+ * 2^16) instructions, and each instruction adds 1.0 to `lanes_per_row`
+ * consecutive floats at the start of each of `rows_per_instr` 64-byte rows of
+ * `buf_dev`, picked pseudo-randomly.  That is waves * iters * rows_per_instr
+ * requests.  lanes_per_row is 1..16, and rows_per_instr * lanes_per_row is at
+ * most 64.  `bytes` (a multiple of 64, at least 64) bounds the rows; the
+ * buffer's contents are changed.  Asynchronous on `hip_stream`: the caller
+ * times it with events. */
+tsdf_status tsdf_measure_atomic_rate(float* buf_dev, uint64_t bytes, uint32_t waves,
+                                     uint32_t iters, uint32_t rows_per_instr,
+                                     uint32_t lanes_per_row, void* hip_stream);
+
 /* Allocate pool blocks for `n` block coordinates (device array of n rows of
  * int32 bx, by, bz, each in [-2^20, 2^20)) through the same insertion protocol
  * as fusion, as if a frame had touched them.  Used to pre-fill a table to a

@@ -289,6 +289,20 @@ tsdf_status tsdf_probe_histogram(tsdf_volume* vol, void* hip_stream, uint64_t* b
   return TSDF_OK;
 }
 
+tsdf_status tsdf_measure_atomic_rate(float* buf_dev, uint64_t bytes, uint32_t waves,
+                                     uint32_t iters, uint32_t rows_per_instr,
+                                     uint32_t lanes_per_row, void* hip_stream) {
+  if (!buf_dev || bytes < 64 || bytes % 64 != 0 || bytes / 64 > 0xFFFFFFFFull) return TSDF_ERR_INVALID_ARGUMENT;
+  if (waves == 0 || waves % 4 != 0 || waves > (1u << 24) || iters == 0 || iters > (1u << 16))
+    return TSDF_ERR_INVALID_ARGUMENT;
+  if (lanes_per_row < 1 || lanes_per_row > 16 || rows_per_instr < 1 ||
+      rows_per_instr * lanes_per_row > 64)
+    return TSDF_ERR_INVALID_ARGUMENT;
+  return hip_status(tsdf::launch_atomic_rate(buf_dev, (unsigned)(bytes / 64), waves, iters,
+                                             rows_per_instr, lanes_per_row,
+                                             as_stream(hip_stream)));
+}
+
 tsdf_status tsdf_extract_blocks(tsdf_volume* vol, void* hip_stream, uint32_t max_blocks,
                                 uint64_t* keys_dev, float* tsdf_dev, float* weight_dev,
                                 uint32_t* n_blocks_out) {

@@ -122,6 +122,33 @@ hipError_t launch_fill_u32(void* ptr, unsigned value, size_t n_words, hipStream_
   return hipGetLastError();
 }
 
+// Measurement: device-scope fp32 atomic adds in the pattern of the fused
+// kernels' flush.  Each wave instruction adds 1.0 to `lanes` consecutive
+// floats at the start of each of `rows` 64-byte rows, the rows picked by a
+// per-wave linear congruential sequence among the buffer's n_rows rows.
+__global__ __launch_bounds__(256) void atomic_rate_kernel(float* p, unsigned n_rows, unsigned iters,
+                                                          unsigned rows, unsigned lanes) {
+  const unsigned gid = blockIdx.x * 256u + threadIdx.x;
+  const unsigned wave = gid >> 6, lane = gid & 63u;
+  const unsigned r = lane / lanes, e = lane % lanes;
+  const bool act = r < rows;
+  unsigned long long h = (unsigned long long)(wave + 1u) * 0x9E3779B97F4A7C15ull;
+  for (unsigned it = 0; it < iters; ++it) {
+    h = h * 6364136223846793005ull + 1442695040888963407ull;
+    // row r of this instruction: the sequence's value plus r golden-ratio steps
+    const unsigned long long hr = (h >> 16) + (unsigned long long)r * 0x9E3779B9ull;
+    const unsigned row = (unsigned)(hr % n_rows);
+    if (act) add_f32(p + (size_t)row * 16u + e, 1.0f);
+  }
+}
+
+hipError_t launch_atomic_rate(float* p, unsigned n_rows, unsigned waves, unsigned iters,
+                              unsigned rows, unsigned lanes, hipStream_t s) {
+  hipLaunchKernelGGL(atomic_rate_kernel, dim3(waves / 4u), dim3(256), 0, s, p, n_rows, iters, rows,
+                     lanes);
+  return hipGetLastError();
+}
+
 hipError_t launch_reset_used(VolumeDev vol, hipStream_t s) {
   hipLaunchKernelGGL(reset_used_kernel,
                      dim3(grid_for((size_t)vol.pool_capacity * (kBlockFloats / 4), 8192)),

@@ -38,7 +38,7 @@ EMPTY_KEY = 0xFFFFFFFFFFFFFFFF
 EXPORTED_SYMBOLS = (
     "tsdf_volume_bytes", "tsdf_volume_layout", "tsdf_create_volume", "tsdf_destroy_volume",
     "tsdf_reset_volume", "tsdf_fuse_frame", "tsdf_fuse_frame_ex", "tsdf_fuse_frames",
-    "tsdf_query_status", "tsdf_probe_histogram",
+    "tsdf_query_status", "tsdf_probe_histogram", "tsdf_measure_atomic_rate",
     "tsdf_extract_blocks", "tsdf_extract_mesh", "tsdf_insert_blocks", "tsdf_status_str",
     "tsdf_fuse_frame_rgb", "tsdf_extract_colour",
     "tsdf_batch_workspace_bytes", "tsdf_batch_create", "tsdf_batch_destroy",
@@ -140,6 +140,8 @@ def lib() -> C.CDLL:
         L.tsdf_query_status.restype = I
         L.tsdf_query_status.argtypes = [P, P, C.POINTER(StatsC)]
         L.tsdf_probe_histogram.restype = I
+        L.tsdf_measure_atomic_rate.restype = I
+        L.tsdf_measure_atomic_rate.argtypes = [P, C.c_uint64, U32, U32, U32, U32, P]
         L.tsdf_probe_histogram.argtypes = [P, P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
         L.tsdf_extract_blocks.restype = I
         L.tsdf_extract_blocks.argtypes = [P, P, U32, P, P, P, C.POINTER(U32)]
@@ -232,6 +234,16 @@ def layout(p: VolumeParams) -> LayoutC:
     if st != OK:
         raise TsdfError(st, "tsdf_volume_layout")
     return out
+
+
+def measure_atomic_rate(buf: torch.Tensor, waves: int, iters: int, rows_per_instr: int,
+                        lanes_per_row: int, stream=None) -> None:
+    """Enqueue tsdf_measure_atomic_rate on a float32 device buffer (its bytes a
+    multiple of 64); the caller times it."""
+    st = lib().tsdf_measure_atomic_rate(C.c_void_p(buf.data_ptr()), buf.numel() * 4, waves, iters,
+                                        rows_per_instr, lanes_per_row, _stream_ptr(stream))
+    if st != OK:
+        raise TsdfError(st, "tsdf_measure_atomic_rate")
 
 
 def camera_struct(cam) -> CameraC:

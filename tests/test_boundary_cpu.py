@@ -117,6 +117,16 @@ def test_null_handles_are_rejected():
     assert L.tsdf_extract_mesh(None, None, 0, None, None, C.byref(n)) == T.ERR_INVALID_ARGUMENT
 
 
+def test_atomic_rate_measurement_rejects_bad_arguments():
+    L = T.lib()
+    fake = T.C.c_void_p(0x10000)  # never launched on: every call below is refused first
+    for args in ((None, 64, 4, 1, 1, 1), (fake, 0, 4, 1, 1, 1), (fake, 63, 4, 1, 1, 1),
+                 (fake, 64, 0, 1, 1, 1), (fake, 64, 6, 1, 1, 1), (fake, 64, 4, 0, 1, 1),
+                 (fake, 64, 4, 1 << 17, 1, 1), (fake, 64, 4, 1, 0, 1), (fake, 64, 4, 1, 1, 0),
+                 (fake, 64, 4, 1, 1, 17), (fake, 64, 4, 1, 5, 13), (fake, 64, 1 << 25, 1, 1, 1)):
+        assert L.tsdf_measure_atomic_rate(*args, None) == T.ERR_INVALID_ARGUMENT, args
+
+
 def test_status_strings():
     for s in range(9):
         assert T.status_str(s) and T.status_str(s) != "unknown status"

@@ -391,6 +391,20 @@ def test_probe_histogram_changes_nothing_else(room):
         T.Volume(w.voxel_size, w.trunc, 1024, 512).probe_histogram()
 
 
+def test_atomic_rate_measurement_loses_no_update():
+    """The measurement kernel's adds all land: the buffer sums to waves x
+    instructions x rows x lanes (every float stays a small exact integer)."""
+    buf = torch.zeros(1 << 20, dtype=torch.float32, device="cuda")
+    for rows, lanes in ((12, 5), (4, 16), (64, 1)):
+        buf.zero_()
+        T.measure_atomic_rate(buf, 1024, 8, rows, lanes)
+        torch.cuda.synchronize()
+        assert int(buf.double().sum().item()) == 1024 * 8 * rows * lanes
+        # only the first `lanes` floats of a row are ever touched
+        per_row = buf.view(-1, 16)
+        assert float(per_row[:, lanes:].abs().sum()) == 0.0
+
+
 # ---------------------------------------------------------------------------
 # Several frames per launch (tsdf_fuse_frames)
 # ---------------------------------------------------------------------------
