@@ -774,33 +774,42 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
           }
         }
         __syncthreads();
-        // flush: two lanes per voxel slot, its sum and its count; slots are in
-        // block and voxel order, so a wave instruction's 32 voxels fall in a
-        // few 64-byte pool rows, one memory-side atomic request per row.  Four
-        // slots per lane are read before any atomic is issued.
-        const unsigned half = tid & 1u;
-        for (unsigned j0 = tid >> 1; j0 < n_here; j0 += 4u * (kThreads / 2u)) {
-          unsigned tg[4];
-          float sm[4];
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const unsigned j = j0 + (unsigned)q * (kThreads / 2u);
-            const bool ok = j < n_here;
-            tg[q] = ok ? s_tag[j] : 0u;
-            sm[q] = ok ? s_sum[j] : 0.0f;
-          }
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const unsigned cnt = tg[q] & 0xFFFu;
-            if (cnt == 0u) continue;  // past the pass's slots
-            const int blk = s_blockd[k0 + (tg[q] >> 21)];
-            const unsigned loc = (tg[q] >> 12) & 511u;
-            if (blk >= 0)
-              add_f32(vol.voxels + (size_t)blk * kBlockFloats + (loc >> 3) * 16u + half * 8u +
-                          (loc & 7u),
-                      half ? (float)cnt : sm[q]);
-            else if (half)
-              n_drop += cnt;  // the pool had no block for this key
+        // flush: two lanes per voxel slot, its sum and its count, which share
+        // a 64-byte pool row.  Slots are in block and voxel order, so a row's
+        // voxels are consecutive slots.  Each wave walks its quarter of the
+        // pass's slots in windows of at most 32 slots that end where a row
+        // ends, so that every touched row is one memory-side request (a row cut
+        // by a fixed window would cost two).
+        {
+          const unsigned wv = tid / kWave, lane = lane_id();
+          const unsigned half = lane & 1u, li = lane >> 1;
+          unsigned pos = n_here * wv / (kThreads / kWave);
+          const unsigned end = n_here * (wv + 1u) / (kThreads / kWave);
+          while (pos < end) {  // uniform across the wave
+            const unsigned j = pos + li;
+            const bool in = j < end;
+            const unsigned tg = in ? s_tag[j] : 0u;
+            const float sm = in ? s_sum[j] : 0.0f;
+            unsigned take = end - pos < 32u ? end - pos : 32u;
+            if (pos + 32u < end) {
+              // the window's last row may go on past it: it opens the next window
+              const unsigned last = (unsigned)__shfl((int)(tg >> 15), kWave - 1, kWave);
+              const unsigned long long m = __ballot(in && half == 0u && (tg >> 15) == last);
+              const unsigned first = (unsigned)__ffsll((long long)m) - 1u;
+              if (first > 0u) take = first >> 1;
+            }
+            if (li < take) {
+              const unsigned cnt = tg & 0xFFFu;
+              const int blk = s_blockd[k0 + (tg >> 21)];
+              const unsigned loc = (tg >> 12) & 511u;
+              if (blk >= 0)
+                add_f32(vol.voxels + (size_t)blk * kBlockFloats + (loc >> 3) * 16u + half * 8u +
+                            (loc & 7u),
+                        half ? (float)cnt : sm);
+              else if (half)
+                n_drop += cnt;  // the pool had no block for this key
+            }
+            pos += take;
           }
         }
         if (kColour) {
