@@ -534,7 +534,7 @@ def bench_serve(args) -> int:
     need = sum(T.volume_bytes(T.volume_params(sp.voxel_size, sp.trunc, sp.table_capacity,
                                               sp.pool_capacity)) for sp in w.specs)
     cfg = T.BatchConfig(*(int(x) for x in args.batch_config.split(","))) if args.batch_config \
-        else T.BatchConfig(16, 1, 8, 0)
+        else T.BatchConfig(32, 1, 8, 0)
 
     def run(mode, budget):
         server = T.Server(budget, max_sessions=len(w.specs) + 1, max_batch=args.max_batch,
@@ -760,7 +760,7 @@ def main() -> int:
     if colour:
         # colour frames go through the batch path: fpl items of the one volume
         cbatch = T.Batch(fpl)
-        cbatch.set_config(T.BatchConfig(16, 1, 4, 0))
+        cbatch.set_config(T.BatchConfig(32, 1, 4, 0))
         items = (T.FuseItemC * len(ptrs))()
         for k in range(len(ptrs)):
             items[k].volume = h.value

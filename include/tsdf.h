@@ -207,7 +207,7 @@ tsdf_status tsdf_fuse_frame_rgb(tsdf_volume* vol, const float* depth_dev, const 
 
 /* Fuse `n_frames` depth frames into the volume, up to 32 frames per launch:
  * the tiles of all frames of a launch share one grid, so one frame's start-up
- * overlaps another's pool updates.  Each workgroup takes the same 16x16 pixel
+ * overlaps another's pool updates.  Each workgroup takes the same 32x8 pixel
  * tile of F consecutive frames and sums their contributions in LDS before
  * adding them to the pool, so frames of one trajectory that see the same
  * surface share pool updates.  F is set by TSDF_FUSE_BATCH(m): m = 1 -> 1,

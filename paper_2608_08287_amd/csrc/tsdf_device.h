@@ -3,7 +3,7 @@
 // kernel template.  Each tsdf_fuse_k<K>.hip instantiates the fused kernel for
 // one band half-width K so that the variants compile in parallel.
 //
-// The fused kernel: one workgroup of 256 lanes (4 wave64) owns a 16x16 pixel
+// The fused kernel: one workgroup of 256 lanes (4 wave64) owns a 32x8 pixel
 // tile of each of the F frames of its launch (F = 1 for a single frame) and
 // runs three phases separated by workgroup barriers:
 //
@@ -60,8 +60,12 @@
 namespace tsdf {
 namespace {
 
-constexpr int kTileW = 16;
-constexpr int kTileH = 16;
+// The fused kernels' tile: wide tiles cover longer runs of the pool's x-rows
+// (a room orbit's image rows run roughly along them), so a 32x8 tile's
+// contributions fall into fewer 64-byte rows than a 16x16 tile's: about 6 %
+// fewer memory-side requests per contribution on a room trajectory.
+constexpr int kTileW = 32;
+constexpr int kTileH = 8;
 constexpr int kThreads = kTileW * kTileH;  // 256 = 4 x wave64
 constexpr int kWave = 64;
 constexpr unsigned kSetCap = 1024;          // LDS key-set slots per workgroup
@@ -401,7 +405,7 @@ struct FuseArgs {
   int remap;
 };
 
-// One workgroup = one 16x16 tile of F consecutive frames of the launch's NB
+// One workgroup = one 32x8 tile of F consecutive frames of the launch's NB
 // frames: workgroup g covers tile g % n_tiles of frames F * (g / n_tiles) + 0..F-1
 // (frames past the batch are empty).  F > 1 sums the frames' contributions to a
 // tile before they reach the pool; NB > F puts several frames in one grid so
@@ -465,7 +469,7 @@ struct alignas(16) TileShared {
 // Frames with width 0 are empty.  Every thread of the workgroup must call it;
 // it begins with a workgroup barrier, so a persistent workgroup may call it
 // tile after tile.
-template <int K, int F, int AB, FuseMode kMode, bool kColour = false>
+template <int K, int F, int AB, FuseMode kMode, bool kColour = false, bool kRowFlush = true>
 __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams& wp,
                                           const FrameDev (&frs)[F], const unsigned (&px)[F],
                                           const unsigned (&py)[F], unsigned shard,
@@ -775,12 +779,13 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
         }
         __syncthreads();
         // flush: two lanes per voxel slot, its sum and its count, which share
-        // a 64-byte pool row.  Slots are in block and voxel order, so a row's
-        // voxels are consecutive slots.  Each wave walks its quarter of the
-        // pass's slots in windows of at most 32 slots that end where a row
-        // ends, so that every touched row is one memory-side request (a row cut
-        // by a fixed window would cost two).
-        {
+        // a 64-byte pool row; slots are in block and voxel order, so a row's
+        // voxels are consecutive slots.
+        if (kRowFlush) {
+          // Each wave walks its quarter of the pass's slots in windows of at
+          // most 32 slots that end where a row ends, so that every touched row
+          // is one memory-side request (a row cut by a fixed window would cost
+          // two).  For kernels bound by those requests.
           const unsigned wv = tid / kWave, lane = lane_id();
           const unsigned half = lane & 1u, li = lane >> 1;
           unsigned pos = n_here * wv / (kThreads / kWave);
@@ -810,6 +815,35 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
                 n_drop += cnt;  // the pool had no block for this key
             }
             pos += take;
+          }
+        } else {
+          // Fixed windows of 32 slots per wave instruction, four slots per
+          // lane read before any atomic is issued: one LDS wait per four,
+          // for kernels bound by latency rather than by requests.
+          const unsigned half = tid & 1u;
+          for (unsigned j0 = tid >> 1; j0 < n_here; j0 += 4u * (kThreads / 2u)) {
+            unsigned tg[4];
+            float sm[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const unsigned j = j0 + (unsigned)q * (kThreads / 2u);
+              const bool ok = j < n_here;
+              tg[q] = ok ? s_tag[j] : 0u;
+              sm[q] = ok ? s_sum[j] : 0.0f;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const unsigned cnt = tg[q] & 0xFFFu;
+              if (cnt == 0u) continue;  // past the pass's slots
+              const int blk = s_blockd[k0 + (tg[q] >> 21)];
+              const unsigned loc = (tg[q] >> 12) & 511u;
+              if (blk >= 0)
+                add_f32(vol.voxels + (size_t)blk * kBlockFloats + (loc >> 3) * 16u + half * 8u +
+                            (loc & 7u),
+                        half ? (float)cnt : sm[q]);
+              else if (half)
+                n_drop += cnt;  // the pool had no block for this key
+            }
           }
         }
         if (kColour) {
@@ -882,7 +916,7 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
   }
 }
 
-// One workgroup = one 16x16 tile of F consecutive frames of the launch's NB
+// One workgroup = one 32x8 tile of F consecutive frames of the launch's NB
 // frames: workgroup g covers tile g % n_tiles of frames F * (g / n_tiles) + 0..F-1
 // (frames past the batch are empty).  F > 1 sums the frames' contributions to a
 // tile before they reach the pool; NB > F puts several frames in one grid so
@@ -917,7 +951,9 @@ void fuse_kernel(FuseArgs<NB> args) {
     px[fi] = x;
     py[fi] = y;
   }
-  fuse_tile<K, F, AB, kMode, kColour>(A.vol, A.wp, frs, px, py, blockIdx.x, sh);
+  // several frames per workgroup: the trajectory launches that reach the
+  // memory-side atomic ceiling flush in row-aligned windows
+  fuse_tile<K, F, AB, kMode, kColour, (F >= 2)>(A.vol, A.wp, frs, px, py, blockIdx.x, sh);
 }
 
 // Many volumes, one frame each, in one persistent launch.  The grid is a
@@ -972,13 +1008,15 @@ void fuse_multi_kernel(BatchWork w, unsigned tw_log2) {
       px[p] = x;
       py[p] = y0 + p * rows;
     }
-    fuse_tile<K, PPT, AB, FuseMode::kFused, kColour>(it.vol, it.wp, frs, px, py, blockIdx.x, sh);
+    // latency-bound (its workloads sit below the atomic ceiling): fixed windows
+    fuse_tile<K, PPT, AB, FuseMode::kFused, kColour, false>(it.vol, it.wp, frs, px, py, blockIdx.x,
+                                                            sh);
   }
 }
 
 template <int K>
 const void* multi_kernel_k(int pixels_per_thread, int acc_blocks, bool colour) {
-  if (colour)  // one shape: 16x16 tiles' single pixels, 4 blocks per LDS pass
+  if (colour)  // one shape: one pixel per thread, the colour slot region
     return pixels_per_thread == 1 && acc_blocks == kColourAccBlocks
                ? reinterpret_cast<const void*>(&fuse_multi_kernel<K, 1, kColourAccBlocks, true>)
                : nullptr;

@@ -338,13 +338,13 @@ def probe_bins(d: np.ndarray) -> np.ndarray:
 
 
 def test_probe_histogram_of_one_tile_is_the_probe_model():
-    """A 16x16 frame is one tile, so each of its distinct keys is resolved
+    """A 32x8 frame is one tile, so each of its distinct keys is resolved
     once, at the distance where it ends up.  Linear probing makes the total
     displacement of a key set independent of insertion order, and the
     pre-filled keys never move: so the frame's summed probe distance is the
     probe model's total over all keys less its total over the pre-fill alone,
     through a table pre-filled to a load factor near 0.95."""
-    depths, cams = scattered_frames(1, W=16, H=16, seed=41, focal=20.0, lo=0.4, hi=2.0)
+    depths, cams = scattered_frames(1, W=32, H=8, seed=41, focal=20.0, lo=0.4, hi=2.0)
     v, tau, C, P = 0.004, 0.016, 4096, 8192
     prefill = S.random_block_coords(3300, seed=42)
     o = O.fuse_frames(v, tau, P, depths, cams, prefill)
