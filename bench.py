@@ -645,6 +645,143 @@ def bench_serve(args) -> int:
     return 0
 
 
+def device_state(torch) -> dict:
+    """HBM in use on the device (by every process; the part this process's
+    torch allocator holds, cached blocks included) and, where rocm-smi answers
+    within a few seconds, its temperatures and clocks."""
+    import subprocess
+    free, total = torch.cuda.mem_get_info()
+    out = {"hbm_total_gib": total / 2**30, "hbm_in_use_gib": (total - free) / 2**30,
+           "torch_reserved_gib": torch.cuda.memory_reserved() / 2**30}
+    try:
+        r = subprocess.run(["rocm-smi", "--showtemp", "--showclocks", "--json"],
+                           capture_output=True, text=True, timeout=20)
+        cards = json.loads(r.stdout) if r.returncode == 0 else {}
+        card = next((v for k, v in sorted(cards.items()) if k.startswith("card")), None)
+        if card:
+            out["smi"] = {k: v for k, v in card.items()
+                          if "temperature" in k.lower() or "clock" in k.lower()}
+    except Exception as e:  # the report is informational; the bench does not depend on it
+        out["smi_error"] = type(e).__name__
+    return out
+
+
+def check_idle(torch) -> dict:
+    """HBM in use before this process allocates anything.  More than a few GiB
+    means another process holds the GPU, and its work may distort the timing:
+    said on stderr and in the JSON line."""
+    st = device_state(torch)
+    st["shared"] = st["hbm_in_use_gib"] > 4.0
+    if st["shared"]:
+        log(f"[bench] warning: {st['hbm_in_use_gib']:.1f} GiB of HBM in use before the run; "
+            "another process may be using the GPU")
+    return st
+
+
+def bench_lf_sweep(args) -> int:
+    """The room orbit through tables of C = ceil(N / alpha) slots, where N is
+    the number of blocks the trajectory allocates and alpha in {0.25, 0.5,
+    0.75, 0.9} its final load factor (C is not a power of two).  One step =
+    reset + all frames through tsdf_fuse_frames (32 frames per launch, 2 per
+    workgroup), timed as in the trajectory bench.  An untimed run per alpha on
+    a probe-histogram volume gives the mean and longest probe distance of the
+    frames' key resolutions.  `value` is the throughput at alpha = 0.9."""
+    import math
+    import torch
+
+    from paper_2608_08287_amd import scenes as S
+    from paper_2608_08287_amd import tsdf as T
+
+    torch.cuda.set_device(0)
+    idle = check_idle(torch)
+    w = S.room_trajectory_workload(n_frames=300, frames=range(args.frames), device="cuda")
+    depth = [torch.from_numpy(d).cuda() for d in w.depth]
+    cams = [T.camera_struct(c) for c in w.cameras]
+    stream = torch.cuda.current_stream()
+    L = T.lib()
+    sp = T.C.c_void_p(stream.cuda_stream)
+    fpl = max(1, min(args.batch, 32))
+    chunks = [(i, min(fpl, len(depth) - i)) for i in range(0, len(depth), fpl)]
+    ptr_arr = (T.C.c_void_p * len(depth))(*[d.data_ptr() for d in depth])
+    cam_arr = (T.CameraC * len(cams))(*cams)
+    bflags = T.FUSE_BATCH(args.per_group)
+
+    def run(vol, events=None):
+        vol.reset()
+        for j, (i0, n) in enumerate(chunks):
+            if events is not None:
+                events[j].record(stream)
+            p_ = T.C.cast(T.C.byref(ptr_arr, i0 * T.C.sizeof(T.C.c_void_p)), T.C.c_void_p)
+            c_ = T.C.cast(T.C.byref(cam_arr, i0 * T.C.sizeof(T.CameraC)), T.C.c_void_p)
+            if L.tsdf_fuse_frames(vol.handle, n, p_, c_, bflags, sp) != T.OK:
+                raise RuntimeError("batched fusion failed")
+        if events is not None:
+            events[len(chunks)].record(stream)
+
+    ref = T.Volume(w.voxel_size, w.trunc, w.table_capacity, w.pool_capacity)
+    run(ref)
+    st0 = ref.stats()
+    if st0.status != T.OK or st0.pairs_dropped:
+        print("correctness gate failed at the default table", file=sys.stderr)
+        return 1
+    n_final, points = st0.blocks_total, st0.points_valid
+    del ref
+    rows = []
+    for alpha in (0.25, 0.5, 0.75, 0.9):
+        C = int(math.ceil(n_final / alpha))
+        hv = T.Volume(w.voxel_size, w.trunc, C, w.pool_capacity, flags=T.VOLUME_PROBE_HISTOGRAM)
+        run(hv)
+        hst = hv.stats()
+        hist, dist = hv.probe_histogram()
+        del hv
+        if hst.status != T.OK or hst.pairs_dropped or hst.blocks_total != n_final or \
+                hst.points_valid != points:
+            print(f"correctness gate failed at alpha {alpha}", file=sys.stderr)
+            return 1
+        vol = T.Volume(w.voxel_size, w.trunc, C, w.pool_capacity)
+        for _ in range(args.warmup):
+            run(vol)
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(args.steps):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(chunks) + 1)]
+            run(vol, ev)
+            torch.cuda.synchronize()
+            ms.append(ev[0].elapsed_time(ev[-1]))
+            s_ = vol.stats()
+            if s_.status != T.OK or s_.pairs_dropped or s_.blocks_total != n_final:
+                raise RuntimeError("timed run changed the result")
+        del vol
+        n_res = int(hist.sum())
+        rows.append({"alpha": alpha, "table_capacity": C, "load_factor": n_final / C,
+                     "points_per_s": points / (float(np.mean(ms)) * 1e-3),
+                     "ms_per_step": float(np.mean(ms)), "median_ms_per_step": float(np.median(ms)),
+                     "max_probe": hst.max_probe, "resolutions": n_res,
+                     "mean_probe_distance": dist / max(n_res, 1)})
+        log(f"[bench] alpha {alpha}: C={C} {rows[-1]['points_per_s']:.3e} points/s, "
+            f"mean probe {rows[-1]['mean_probe_distance']:.2f}, max {hst.max_probe}")
+    last = rows[-1]
+    out = {
+        "metric": METRIC, "value": last["points_per_s"], "unit": "points/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": last["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"room orbit, {len(depth)} frames of 640x480, voxel 5 mm, truncation "
+                        f"2 cm, pool 2^18 blocks, tables of ceil({n_final} / alpha) slots",
+            "path": f"batched: tsdf_fuse_frames, {fpl} frames per launch, "
+                    f"{args.per_group} frame(s) per workgroup",
+            "blocks": n_final, "points_per_step": points, "parallelism": "single GPU",
+        },
+        "sweep": rows,
+        "device": {"at_start": idle, "after": device_state(torch)},
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -666,12 +803,16 @@ def main() -> int:
     ap.add_argument("--variant", choices=["main", "slot", "colour"], default="main",
                     help="trajectory: the volume design (main; slot: block index = table slot, "
                          "pool = table; colour: three colour sums per voxel)")
-    ap.add_argument("--workload", choices=["trajectory", "multi", "serve", "stress"],
+    ap.add_argument("--workload", choices=["trajectory", "multi", "serve", "stress", "lf-sweep"],
                     default="trajectory",
                     help="trajectory: one volume, the 300-frame orbit (default); multi: many "
                          "volumes, one frame each per tick, through the batch API; serve: "
                          "sessions with Poisson arrivals through the server; stress: the "
-                         "fronto-parallel plane through a table at load factor 0.95")
+                         "fronto-parallel plane through a table at load factor 0.95; "
+                         "lf-sweep: the orbit through tables at final load factors 0.25-0.9")
+    ap.add_argument("--cold-volumes", type=int, default=8,
+                    help="trajectory: fresh volumes for the cold-frame timing (0: skip it and "
+                         "the end-to-end timing)")
     ap.add_argument("--sessions", type=int, default=256, help="serve: sessions")
     ap.add_argument("--rate", type=float, default=3000.0, help="serve: frames/s, all sessions")
     ap.add_argument("--duration", type=float, default=1.0, help="serve: seconds of arrivals")
@@ -688,7 +829,7 @@ def main() -> int:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "the volume is not sharded across GPUs", file=sys.stderr)
         return 2
-    if args.workload in ("multi", "serve", "stress"):
+    if args.workload in ("multi", "serve", "stress", "lf-sweep"):
         import torch
         if not torch.cuda.is_available():
             print("bench.py needs a GPU", file=sys.stderr)
@@ -696,6 +837,8 @@ def main() -> int:
         if args.workload == "stress":
             args.frames = min(args.frames, 100)
             return bench_stress(args)
+        if args.workload == "lf-sweep":
+            return bench_lf_sweep(args)
         return bench_multi(args) if args.workload == "multi" else bench_serve(args)
 
     import torch
@@ -709,6 +852,7 @@ def main() -> int:
     torch.cuda.set_device(0)
     flags = {"fused": T.FUSE_DEFAULT, "two_pass": T.FUSE_TWO_PASS,
              "fused_xcd_remap": T.FUSE_XCD_REMAP}[args.mode]
+    idle = check_idle(torch)
 
     # ---- inputs, resident in HBM ---------------------------------------------
     t0 = time.time()
@@ -888,6 +1032,98 @@ def main() -> int:
                     "rate tsdf_measure_atomic_rate sustains in the flush's pattern",
         }
 
+    # ---- cold frames and the end-to-end rate (main design only) --------------
+    cold = e2e = None
+    if args.variant == "main" and args.cold_volumes > 0:
+        # cold: one frame into a fresh volume; R volumes are reset outside the
+        # timed window and fused back to back, each frame between its own events
+        R = args.cold_volumes
+        cvols = [T.Volume(w.voxel_size, w.trunc, table, pool) for _ in range(R)]
+        cold_ms, cold_pts = [], 0
+        for rep in range(args.warmup + args.steps):
+            for cv in cvols:
+                cv.reset()
+            torch.cuda.synchronize()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * R)]
+            ks = [(rep * R + r) % len(ptrs) for r in range(R)]
+            for r, cv in enumerate(cvols):
+                ev[2 * r].record(stream)
+                if L.tsdf_fuse_frame_ex(cv.handle, ptrs[ks[r]], cam_refs[ks[r]], flags, sp) != T.OK:
+                    raise RuntimeError("fuse failed")
+                ev[2 * r + 1].record(stream)
+            torch.cuda.synchronize()
+            for r, cv in enumerate(cvols):
+                s_ = cv.stats()
+                if s_.status != T.OK or s_.pairs_dropped:
+                    raise RuntimeError("cold frame failed")
+                if rep >= args.warmup:
+                    cold_ms.append(ev[2 * r].elapsed_time(ev[2 * r + 1]))
+                    cold_pts += s_.points_valid
+        del cvols
+        cold_ms = np.array(cold_ms)
+        cold = {"value": cold_pts / (cold_ms.sum() * 1e-3), "unit": "points/s",
+                "volumes": R, "frame_samples": int(cold_ms.size),
+                "mean_frame_ms": float(cold_ms.mean()),
+                "p50_frame_ms": float(np.percentile(cold_ms, 50)),
+                "p99_frame_ms": float(np.percentile(cold_ms, 99)),
+                "path": "plain (one launch per frame), each frame into an empty volume"}
+        log(f"[bench] cold frames: mean {cold['mean_frame_ms']:.4f} ms")
+
+        # end to end: frames start in pinned host memory; each launch's frames
+        # are uploaded on a copy stream into one of two device buffers, so the
+        # upload of one launch overlaps the fusion of the one before
+        H_, W_ = w.depth[0].shape
+        host = torch.empty((len(ptrs), H_, W_), dtype=torch.float32, pin_memory=True)
+        for k in range(len(ptrs)):
+            host[k].copy_(torch.from_numpy(w.depth[k]))
+        bufs = [torch.empty((fpl, H_, W_), dtype=torch.float32, device="cuda") for _ in range(2)]
+        buf_ptrs = [(T.C.c_void_p * fpl)(*[b[i].data_ptr() for i in range(fpl)]) for b in bufs]
+        copy_stream = torch.cuda.Stream()
+        free = [None, None]  # per buffer: the event after the last launch that reads it
+
+        def fuse_e2e(events=None):
+            if L.tsdf_reset_volume(h, sp) != T.OK:
+                raise RuntimeError("reset failed")
+            if events is not None:
+                events[0].record(stream)
+            for j, (i0, n) in enumerate(chunks):
+                b = j % 2
+                if free[b] is not None:
+                    copy_stream.wait_event(free[b])
+                with torch.cuda.stream(copy_stream):
+                    bufs[b][:n].copy_(host[i0:i0 + n], non_blocking=True)
+                ready = torch.cuda.Event()
+                ready.record(copy_stream)
+                stream.wait_event(ready)
+                c_ = T.C.cast(T.C.byref(cam_arr, i0 * T.C.sizeof(T.CameraC)), T.C.c_void_p)
+                if L.tsdf_fuse_frames(h, n, T.C.cast(buf_ptrs[b], T.C.c_void_p), c_, bflags,
+                                      sp) != T.OK:
+                    raise RuntimeError("batched fusion failed")
+                done = torch.cuda.Event()
+                done.record(stream)
+                free[b] = done
+            if events is not None:
+                events[1].record(stream)
+
+        wall_e, e2e_ms = timed(fuse_e2e, 1)
+        # the upload alone: all frames of a step in one pinned-to-device copy
+        dev_all = torch.empty_like(host, device="cuda")
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        dev_all.copy_(host, non_blocking=True)
+        e0.record(stream)
+        dev_all.copy_(host, non_blocking=True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        h2d_gbs = host.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        del dev_all, host, bufs
+        e2e = {"value": points_per_step * args.steps / wall_e, "unit": "points/s",
+               "ms_per_step": wall_e / args.steps * 1e3,
+               "median_ms_per_step": float(np.median(e2e_ms[:, 0])),
+               "h2d_gb_per_s": h2d_gbs,
+               "path": f"frames in pinned host memory, {fpl} uploaded per launch on a second "
+                       "stream into one of two device buffers, then tsdf_fuse_frames"}
+        log(f"[bench] end to end: {e2e['value']:.3e} points/s, H2D {h2d_gbs:.1f} GB/s")
+
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import oracle as O
@@ -952,6 +1188,7 @@ def main() -> int:
             "ms_per_step": wall_p / args.steps * 1e3, "mean_frame_ms": mean_frame_ms,
             "p50_frame_ms": float(np.percentile(frame_ms, 50)),
             "p99_frame_ms": float(np.percentile(frame_ms, 99)), "frame_samples": int(frame_ms.size),
+            "median_ms_per_step": float(np.median(frame_ms.sum(axis=1))),
         },
         "batched": {
             "value": value, "unit": "points/s", "frames_per_launch": fpl,
@@ -960,7 +1197,11 @@ def main() -> int:
             "p50_launch_ms": float(np.percentile(launch_ms[:, full], 50)),
             "p99_launch_ms": float(np.percentile(launch_ms[:, full], 99)),
             "ms_per_frame": mean_launch_ms / fpl,
+            "median_ms_per_step": float(np.median(launch_ms.sum(axis=1))),
         },
+        "cold": cold,
+        "end_to_end": e2e,
+        "device": {"at_start": idle, "after": device_state(torch)},
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
