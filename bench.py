@@ -653,6 +653,12 @@ def device_state(torch) -> dict:
     free, total = torch.cuda.mem_get_info()
     out = {"hbm_total_gib": total / 2**30, "hbm_in_use_gib": (total - free) / 2**30,
            "torch_reserved_gib": torch.cuda.memory_reserved() / 2**30}
+    preload = os.environ.get("LD_PRELOAD", "") + os.environ.get("HSA_TOOLS_LIB", "")
+    if "rocprof" in preload or any(k.startswith(("ROCPROF", "ROCP_")) for k in os.environ):
+        # under a profiler its preloaded library would initialise the GPU in the
+        # rocm-smi launcher too, which then replaces itself with the interpreter
+        out["smi_skipped"] = "profiler loaded"
+        return out
     try:
         r = subprocess.run(["rocm-smi", "--showtemp", "--showclocks", "--json"],
                            capture_output=True, text=True, timeout=20)

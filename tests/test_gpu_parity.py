@@ -284,7 +284,7 @@ def test_stress_C_table_full_is_reported(stress_full):
 
 # ---------------------------------------------------------------------------
 # Tiles that touch many blocks and many voxels.  "sparse": random depths seen
-# through a short focal length put nearly every sample of a 16x16 tile in its
+# through a short focal length put nearly every sample of a tile in its
 # own voxel and its own block, so the LDS sums of a tile take several windows
 # of blocks (and, with 8 mm blocks and a 17-sample band, the tile's 1024-key
 # set overflows).  "dense": a long focal length and a 0.12 m depth spread put
