@@ -281,21 +281,43 @@ def bench_multi(args) -> int:
 
     cpu = None
     if not args.no_cpu_baseline:
+        from concurrent.futures import ThreadPoolExecutor
+
         from oracle import oracle as O
-        t_c0 = time.perf_counter()
-        pts, nf = 0, 0
-        for i in range(nv):
-            s = w.specs[i]
+        # the oracle's calls release the interpreter lock, so independent
+        # volumes fuse in parallel on threads (the box's share: 16 cores)
+        n_thr = max(1, min(16, os.cpu_count() or 1))
+        # every volume's tick-0 frame, rendered before any timing, largest first
+        # so that the threads finish together
+        items = [(w.specs[i], w.depth(i, 0, device="cuda"), w.camera(i, 0)) for i in range(nv)]
+        sample = sorted(items, key=lambda it: -it[1].size)
+
+        def fuse_one(item):
+            s, d, c = item
             ov = O.OracleVolume(s.voxel_size, s.trunc, s.pool_capacity)
-            ov.fuse(w.depth(i, 0), w.camera(i, 0))
-            pts += ov.stats()["points_valid"]
-            nf += 1
-            if time.perf_counter() - t_c0 > args.cpu_seconds:
+            ov.fuse(d, c)
+            return ov.stats()["points_valid"]
+
+        t_c0 = time.perf_counter()
+        with ThreadPoolExecutor(n_thr) as ex:
+            pts_n = sum(ex.map(fuse_one, sample))
+        t_n = time.perf_counter() - t_c0
+        # one thread: the volumes in order, for about half of --cpu-seconds
+        pts, n1 = 0, 0
+        t_c0 = time.perf_counter()
+        for it in items:
+            pts += fuse_one(it)
+            n1 += 1
+            if time.perf_counter() - t_c0 > args.cpu_seconds / 2:
                 break
-        t_c = time.perf_counter() - t_c0
-        cpu = {"value": pts / t_c, "unit": "points/s", "cores": 1, "kind": "oracle",
-               "sample": f"tick 0 of the first {nf} volumes, each fused into its own volume "
-                         f"({pts} points, {t_c:.1f} s including depth rendering, one thread)"}
+        t_1 = time.perf_counter() - t_c0
+        cpu = {"value": pts_n / t_n, "unit": "points/s", "cores": n_thr, "kind": "oracle",
+               "sample": f"tick 0 of all {len(sample)} volumes, each fused into its own volume "
+                         f"({pts_n} points, {t_n:.2f} s), {n_thr} threads on disjoint volumes",
+               "single_thread": {"value": pts / t_1, "cores": 1,
+                                   "sample": f"the first {n1} of those volumes, {t_1:.1f} s"}}
+        log(f"[bench] cpu oracle: {pts / t_1:.3e} points/s on one thread, "
+            f"{pts_n / t_n:.3e} on {n_thr}")
 
     if args.profile_copy_bytes:
         src = torch.empty(args.profile_copy_bytes, dtype=torch.uint8, device="cuda")
