@@ -30,7 +30,8 @@ PROBE_HIST_BINS = 16
 
 
 def FUSE_BATCH(m: int) -> int:
-    """Flag: at most ``m`` frames per launch in ``fuse_frames`` (1..15)."""
+    """Flag for ``fuse_frames``: frames summed per workgroup (m = 1 -> 1, 2 or 3
+    -> 2, 4..15 -> 4; 0, the default, -> 2)."""
     return (m & 0xF) << 16
 BLOCK_VOXELS = 512
 EMPTY_KEY = 0xFFFFFFFFFFFFFFFF
