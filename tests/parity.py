@@ -116,6 +116,50 @@ def run_workload(w, flags=T.FUSE_DEFAULT, keep_volume=False, **kw) -> GpuResult:
                    w.prefill_blocks, flags, keep_volume, **kw)
 
 
+def oracle_slices(voxel_size, trunc, pool_capacity, depths: Sequence[np.ndarray], cams,
+                  n_slices: int) -> list:
+    """The frames cut into n_slices contiguous slices, each fused into its own
+    oracle volume; the slices run on threads (the oracle's calls release the
+    interpreter lock)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    n = len(depths)
+    bounds = [n * i // n_slices for i in range(n_slices + 1)]
+
+    def part(i):
+        ov = O.OracleVolume(voxel_size, trunc, pool_capacity)
+        for k in range(bounds[i], bounds[i + 1]):
+            ov.fuse(depths[k], cams[k])
+        return ov
+
+    with ThreadPoolExecutor(n_slices) as ex:
+        return list(ex.map(part, range(n_slices)))
+
+
+def add_slices(parts: list, keys: np.ndarray):
+    """Sum the slices' TSDF sums and weights into (len(keys), 512) arrays over
+    `keys` (ascending), dropping each slice once added.  Returns the sums, the
+    weights, a mask of the keys some slice allocated, and the summed point and
+    pair counts.  Fails if a slice dropped pairs or holds a key outside `keys`."""
+    sums = np.zeros((keys.size, 512), dtype=np.float64)
+    weights = np.zeros((keys.size, 512), dtype=np.uint32)
+    seen = np.zeros(keys.size, dtype=bool)
+    points = pairs = 0
+    for i in range(len(parts)):
+        r = parts[i].result()
+        parts[i] = None
+        assert r.stats["pairs_dropped"] == 0
+        idx = np.searchsorted(keys, r.keys)
+        assert np.all(idx < keys.size) and np.array_equal(keys[idx], r.keys), \
+            f"slice {i} holds blocks outside the key set"
+        sums[idx] += r.sums
+        weights[idx] += r.weights
+        seen[idx] = True
+        points += r.stats["points_valid"]
+        pairs += r.stats["pairs"]
+    return sums, weights, seen, points, pairs
+
+
 def assert_parity(g: GpuResult, o: O.OracleResult, atol=TSDF_ATOL) -> None:
     assert g.keys.size == o.keys.size, (g.keys.size, o.keys.size)
     assert np.array_equal(g.keys, o.keys), "block key sets differ"

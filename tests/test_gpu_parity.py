@@ -14,8 +14,9 @@ from oracle import oracle as O
 from paper_2608_08287_amd import scenes as S
 from paper_2608_08287_amd import tsdf as T
 
-from parity import (EMPTY, SCATTER, assert_parity, assert_table_invariants, log, result_of,
-                    run_gpu, run_workload, scattered_frames, table_arrays)
+from parity import (EMPTY, SCATTER, TSDF_ATOL, add_slices, assert_parity, assert_table_invariants,
+                    log, oracle_slices, result_of, run_gpu, run_workload, scattered_frames,
+                    table_arrays)
 
 pytestmark = pytest.mark.gpu
 
@@ -484,3 +485,28 @@ def test_full_trajectory_batched_equals_plain():
     # a subset: their keys must all be present here
     o = O.fuse_frames(w.voxel_size, w.trunc, w.pool_capacity, [w.depth[0]], [w.cameras[0]])
     assert np.all(np.isin(o.keys, g_b.keys))
+
+
+def test_full_trajectory_batched_matches_oracle_everywhere():
+    """All 300 frames at 640x480 through the launch configuration the bench times
+    (tsdf_fuse_frames, 32 frames per launch, 2 per workgroup), against the oracle
+    at every voxel.  With no pool overflow, a voxel's weight and TSDF sum are
+    sums over frames, so disjoint slices of the trajectory fused into separate
+    oracle volumes (in parallel: the oracle's calls release the interpreter
+    lock) add up to the sequential result: weights exactly, sums up to float64
+    rounding.  A block exists iff some slice allocated it."""
+    import os
+
+    w = S.room_trajectory_workload(device="cuda")
+    g = run_workload(w, batched=True)
+    assert g.stats.status == T.OK and g.stats.pairs_dropped == 0
+    n_thr = max(1, min(16, os.cpu_count() or 1))
+    parts = oracle_slices(w.voxel_size, w.trunc, w.pool_capacity, w.depth, w.cameras, n_thr)
+    sums, weights, seen, points, pairs = add_slices(parts, g.keys)
+    assert seen.all(), "the GPU volume has blocks no slice allocated"
+    assert g.stats.points_valid == points and g.stats.pairs == pairs
+    assert np.array_equal(g.weights, weights.astype(np.float32)), "weights differ"
+    means = np.divide(sums, weights, out=np.zeros_like(sums), where=weights > 0)
+    err = float(np.abs(g.means.astype(np.float64) - means).max())
+    log(f"  {g.keys.size} blocks, {pairs} pairs, {n_thr} oracle slices, max |dTSDF| {err:.2e}")
+    assert err <= TSDF_ATOL, err

@@ -439,6 +439,22 @@ def test_two_frames_commute():
     assert np.max(np.abs(a.means - b.means)) < 1e-12
 
 
+def test_slices_add_up_to_the_sequential_fusion():
+    """Fusion is a sum over frames: room-orbit frames cut into slices, each fused
+    into its own volume (on threads), add up to fusing them one after another.
+    The GPU test of the whole 300-frame trajectory relies on this."""
+    from parity import add_slices, oracle_slices
+
+    w = S.room_trajectory_workload(frames=[0, 1, 2, 60, 61, 150])
+    seq = O.fuse_workload(w)
+    parts = oracle_slices(w.voxel_size, w.trunc, w.pool_capacity, w.depth, w.cameras, 3)
+    sums, weights, seen, points, pairs = add_slices(parts, seq.keys)
+    assert seen.all()
+    assert np.array_equal(weights, seq.weights)
+    assert np.max(np.abs(sums - seq.sums)) < 1e-9
+    assert points == seq.stats["points_valid"] and pairs == seq.stats["pairs"]
+
+
 def test_pool_overflow_first_keys_win_and_drops_are_counted():
     w = S.single_frame_workload()
     P = 100
