@@ -222,8 +222,12 @@ def test_batch_argument_errors():
 def test_full_size_multi_volume_tick():
     """The 64-volume workload at full size (frames 160x120 .. 1280x720, tables
     2^16..2^20): two batched ticks, first with the autotuner running, then with
-    a fixed configuration replayed as a graph, each against every volume fused
-    alone; the smallest volumes also against the oracle."""
+    the bench's configuration (32-pixel-wide tiles, 2 pixels per thread)
+    replayed as a graph, each against every volume fused alone; then every
+    volume of the graph run against the oracle (volumes fused on threads)."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+
     w = S.MultiVolumeWorkload(64)
     dev = [frames(w, k) for k in range(2)]
     ref = make_volumes(w)
@@ -234,7 +238,7 @@ def test_full_size_multi_volume_tick():
         log(f"  {mode}")
         batch = T.Batch(64)
         if mode == "graph":
-            batch.set_config(T.BatchConfig(16, 1, 8, 0))
+            batch.set_config(T.BatchConfig(32, 2, 8, 0))
         vols = make_volumes(w)
         for d, c in dev:
             batch.fuse(vols, d, c)
@@ -244,12 +248,21 @@ def test_full_size_multi_volume_tick():
             if st.pairs_dropped:
                 dropped.append(i)
         assert dropped == [], f"pools ran out in volumes {dropped}"
-        del vols, batch
-        torch.cuda.empty_cache()
-    small = [i for i, s in enumerate(w.specs) if s.width == 160][:2]
-    for i in small:
+        if mode == "tune":
+            del vols, batch
+            torch.cuda.empty_cache()
+    del ref
+    host = [([dev[k][0][i].cpu().numpy() for k in range(2)], [dev[k][1][i] for k in range(2)])
+            for i in range(len(w))]
+
+    def oracle_of(i):
         s = w.specs[i]
-        o = O.fuse_frames(s.voxel_size, s.trunc, s.pool_capacity,
-                          [dev[k][0][i].cpu().numpy() for k in range(2)],
-                          [dev[k][1][i] for k in range(2)])
-        assert_parity(result_of(ref[i]), o)
+        return O.fuse_frames(s.voxel_size, s.trunc, s.pool_capacity, *host[i])
+
+    n_thr = max(1, min(16, os.cpu_count() or 1))
+    with ThreadPoolExecutor(n_thr) as ex:
+        for c0 in range(0, len(w), n_thr):
+            ids = list(range(c0, min(c0 + n_thr, len(w))))
+            for i, o in zip(ids, ex.map(oracle_of, ids)):
+                assert_parity(result_of(vols[i]), o)
+    log(f"  all {len(w)} volumes match the oracle")
