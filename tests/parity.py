@@ -117,10 +117,10 @@ def run_workload(w, flags=T.FUSE_DEFAULT, keep_volume=False, **kw) -> GpuResult:
 
 
 def oracle_slices(voxel_size, trunc, pool_capacity, depths: Sequence[np.ndarray], cams,
-                  n_slices: int) -> list:
+                  n_slices: int, prefill_blocks=None) -> list:
     """The frames cut into n_slices contiguous slices, each fused into its own
-    oracle volume; the slices run on threads (the oracle's calls release the
-    interpreter lock)."""
+    oracle volume (after the same pre-filled blocks, if any); the slices run
+    on threads (the oracle's calls release the interpreter lock)."""
     from concurrent.futures import ThreadPoolExecutor
 
     n = len(depths)
@@ -128,6 +128,8 @@ def oracle_slices(voxel_size, trunc, pool_capacity, depths: Sequence[np.ndarray]
 
     def part(i):
         ov = O.OracleVolume(voxel_size, trunc, pool_capacity)
+        if prefill_blocks is not None:
+            ov.insert_blocks(prefill_blocks)
         for k in range(bounds[i], bounds[i + 1]):
             ov.fuse(depths[k], cams[k])
         return ov

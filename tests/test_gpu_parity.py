@@ -232,6 +232,30 @@ def test_stress_A_prefilled_to_095_drops_nothing(stress_full):
     log(f"  max_probe={g.stats.max_probe}")
 
 
+def test_stress_A_all_100_frames_batched_matches_oracle():
+    """The stress bench's whole run: 100 plane frames through tsdf_fuse_frames
+    (32 per launch, 2 per workgroup) into the table pre-filled to load factor
+    0.95, against the oracle at every voxel (frame slices fused on threads,
+    each after the same pre-fill, added by key)."""
+    import os
+
+    w = S.plane_stress_workload("A", device="cuda")
+    g = run_workload(w, batched=True)
+    assert g.stats.status == T.OK and g.stats.pairs_dropped == 0
+    n_thr = max(1, min(16, os.cpu_count() or 1))
+    parts = oracle_slices(w.voxel_size, w.trunc, w.pool_capacity, w.depth, w.cameras, n_thr,
+                          prefill_blocks=w.prefill_blocks)
+    sums, weights, seen, points, pairs = add_slices(parts, g.keys)
+    assert seen.all(), "the GPU volume has blocks no slice allocated"
+    assert g.stats.points_valid == points and g.stats.pairs == pairs
+    assert np.array_equal(g.weights, weights.astype(np.float32)), "weights differ"
+    means = np.divide(sums, weights, out=np.zeros_like(sums), where=weights > 0)
+    err = float(np.abs(g.means.astype(np.float64) - means).max())
+    log(f"  {g.keys.size} blocks, {pairs} pairs, max probe {g.stats.max_probe}, "
+        f"max |dTSDF| {err:.2e}")
+    assert err <= TSDF_ATOL, err
+
+
 def _pre_keys(coords):
     return np.array([O.pack_key(*map(int, c)) for c in coords], dtype=np.uint64)
 
