@@ -117,10 +117,11 @@ def run_workload(w, flags=T.FUSE_DEFAULT, keep_volume=False, **kw) -> GpuResult:
 
 
 def oracle_slices(voxel_size, trunc, pool_capacity, depths: Sequence[np.ndarray], cams,
-                  n_slices: int, prefill_blocks=None) -> list:
+                  n_slices: int, prefill_blocks=None, rgbas=None) -> list:
     """The frames cut into n_slices contiguous slices, each fused into its own
-    oracle volume (after the same pre-filled blocks, if any); the slices run
-    on threads (the oracle's calls release the interpreter lock)."""
+    oracle volume (after the same pre-filled blocks, if any; with the colour
+    images, if given); the slices run on threads (the oracle's calls release
+    the interpreter lock)."""
     from concurrent.futures import ThreadPoolExecutor
 
     n = len(depths)
@@ -131,24 +132,30 @@ def oracle_slices(voxel_size, trunc, pool_capacity, depths: Sequence[np.ndarray]
         if prefill_blocks is not None:
             ov.insert_blocks(prefill_blocks)
         for k in range(bounds[i], bounds[i + 1]):
-            ov.fuse(depths[k], cams[k])
+            if rgbas is None:
+                ov.fuse(depths[k], cams[k])
+            else:
+                ov.fuse_rgb(depths[k], rgbas[k], cams[k])
         return ov
 
     with ThreadPoolExecutor(n_slices) as ex:
         return list(ex.map(part, range(n_slices)))
 
 
-def add_slices(parts: list, keys: np.ndarray):
+def add_slices(parts: list, keys: np.ndarray, colour: bool = False):
     """Sum the slices' TSDF sums and weights into (len(keys), 512) arrays over
     `keys` (ascending), dropping each slice once added.  Returns the sums, the
     weights, a mask of the keys some slice allocated, and the summed point and
-    pair counts.  Fails if a slice dropped pairs or holds a key outside `keys`."""
+    pair counts, and with `colour` also the (len(keys), 3, 512) colour sums.
+    Fails if a slice dropped pairs or holds a key outside `keys`."""
+    col = np.zeros((keys.size, 3, 512), dtype=np.float64) if colour else None
     sums = np.zeros((keys.size, 512), dtype=np.float64)
     weights = np.zeros((keys.size, 512), dtype=np.uint32)
     seen = np.zeros(keys.size, dtype=bool)
     points = pairs = 0
     for i in range(len(parts)):
         r = parts[i].result()
+        c = parts[i].colour_sums() if colour else None
         parts[i] = None
         assert r.stats["pairs_dropped"] == 0
         idx = np.searchsorted(keys, r.keys)
@@ -156,9 +163,13 @@ def add_slices(parts: list, keys: np.ndarray):
             f"slice {i} holds blocks outside the key set"
         sums[idx] += r.sums
         weights[idx] += r.weights
+        if colour:
+            col[idx] += c
         seen[idx] = True
         points += r.stats["points_valid"]
         pairs += r.stats["pairs"]
+    if colour:
+        return sums, weights, seen, points, pairs, col
     return sums, weights, seen, points, pairs
 
 

@@ -12,8 +12,8 @@ from oracle import oracle as O
 from paper_2608_08287_amd import scenes as S
 from paper_2608_08287_amd import tsdf as T
 
-from parity import (EMPTY, SCATTER, assert_parity, assert_same_volume, log, result_of,
-                    scattered_frames, table_arrays)
+from parity import (EMPTY, SCATTER, TSDF_ATOL, add_slices, assert_parity, assert_same_volume, log,
+                    oracle_slices, result_of, scattered_frames, table_arrays)
 
 pytestmark = pytest.mark.gpu
 
@@ -179,6 +179,43 @@ def test_colour_matches_the_oracle(room, variant):
                     0.0).transpose(0, 2, 1)
     assert np.max(np.abs(mean[order] - want)) < 1e-3
     log(f"  {variant}: {o.keys.size} blocks, colour sums exact")
+
+
+def test_colour_full_trajectory_batched_matches_oracle():
+    """The colour bench's whole run: all 300 frames into one colour volume
+    through tsdf_batch_fuse, 32 frames per call, in the bench's configuration
+    (32-pixel-wide tiles, one pixel per thread, the colour LDS region), against
+    the oracle at every voxel: weights and colour sums exact, TSDF means within
+    the tolerance (oracle frame slices fused on threads, added by key)."""
+    import os
+
+    w, rgba = S.room_trajectory_rgbd(device="cuda")
+    vol = T.Volume(w.voxel_size, w.trunc, w.table_capacity, w.pool_capacity,
+                   flags=T.VOLUME_COLOUR)
+    batch = T.Batch(32)
+    batch.set_config(T.BatchConfig(32, 1, 4, 0))
+    dev = [torch.from_numpy(d).cuda() for d in w.depth]
+    cols = [torch.from_numpy(c.view(np.int32)).cuda() for c in rgba]
+    for i0 in range(0, len(dev), 32):
+        n = min(32, len(dev) - i0)
+        batch.fuse([vol] * n, dev[i0:i0 + n], w.cameras[i0:i0 + n], rgbas=cols[i0:i0 + n])
+    g = result_of(vol)
+    assert g.stats.status == T.OK and g.stats.pairs_dropped == 0
+    keys, gcol = gpu_colour_sums(vol, g.keys.size, False)
+    assert np.array_equal(keys, g.keys)
+    del dev, cols
+    n_thr = max(1, min(16, os.cpu_count() or 1))
+    parts = oracle_slices(w.voxel_size, w.trunc, w.pool_capacity, w.depth, w.cameras, n_thr,
+                          rgbas=rgba)
+    sums, weights, seen, points, pairs, col = add_slices(parts, g.keys, colour=True)
+    assert seen.all(), "the GPU volume has blocks no slice allocated"
+    assert g.stats.points_valid == points and g.stats.pairs == pairs
+    assert np.array_equal(g.weights, weights.astype(np.float32)), "weights differ"
+    assert np.array_equal(gcol, col), "colour sums differ"
+    means = np.divide(sums, weights, out=np.zeros_like(sums), where=weights > 0)
+    err = float(np.abs(g.means.astype(np.float64) - means).max())
+    log(f"  {g.keys.size} blocks, {pairs} pairs, colour sums exact, max |dTSDF| {err:.2e}")
+    assert err <= TSDF_ATOL, err
 
 
 @pytest.mark.parametrize("band", list(SCATTER))
