@@ -511,10 +511,12 @@ def test_full_trajectory_batched_equals_plain():
     assert np.all(np.isin(o.keys, g_b.keys))
 
 
-def test_full_trajectory_batched_matches_oracle_everywhere():
+@pytest.mark.parametrize("design", ["main", "slot index"])
+def test_full_trajectory_batched_matches_oracle_everywhere(design):
     """All 300 frames at 640x480 through the launch configuration the bench times
     (tsdf_fuse_frames, 32 frames per launch, 2 per workgroup), against the oracle
-    at every voxel.  With no pool overflow, a voxel's weight and TSDF sum are
+    at every voxel; for the main design (table 2^20, pool 2^18) and for the
+    slot-derived block index (pool = table = 2^20), as the bench's variants.  With no pool overflow, a voxel's weight and TSDF sum are
     sums over frames, so disjoint slices of the trajectory fused into separate
     oracle volumes (in parallel: the oracle's calls release the interpreter
     lock) add up to the sequential result: weights exactly, sums up to float64
@@ -522,7 +524,11 @@ def test_full_trajectory_batched_matches_oracle_everywhere():
     import os
 
     w = S.room_trajectory_workload(device="cuda")
-    g = run_workload(w, batched=True)
+    vol = None
+    if design == "slot index":
+        vol = T.Volume(w.voxel_size, w.trunc, w.table_capacity, w.table_capacity,
+                       flags=T.VOLUME_SLOT_INDEX)
+    g = run_workload(w, batched=True, vol=vol)
     assert g.stats.status == T.OK and g.stats.pairs_dropped == 0
     n_thr = max(1, min(16, os.cpu_count() or 1))
     parts = oracle_slices(w.voxel_size, w.trunc, w.pool_capacity, w.depth, w.cameras, n_thr)
