@@ -113,6 +113,53 @@ def test_served_sessions_match_the_oracle():
         assert_parity(g, o)
 
 
+def test_full_serving_trace_sampled_sessions_match_the_oracle():
+    """The serving bench's trace at full size: 256 sessions, Poisson arrivals at
+    3000 frames/s for one second, replayed in real time through the served path
+    in the bench's configuration (up to 256 frames per launch, 2 launches in
+    flight, 32-pixel-wide tiles, one pixel per thread).  Every session counts
+    its own frames, and 32 sessions drawn with a fixed seed match the oracle
+    (fused on threads; the oracle's calls release the interpreter lock)."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+
+    w = S.ServingWorkload(256, rate=3000.0, duration_s=1.0)
+    depths = [torch.from_numpy(w.depth(int(s), int(k), device="cuda")).cuda()
+              for s, k in zip(w.session_of, w.frame_of)]
+    cams = [w.camera(int(s), int(k)) for s, k in zip(w.session_of, w.frame_of)]
+    log(f"  rendered {len(w)} frames")
+    server = T.Server(budget_for(w), max_sessions=len(w.specs), max_batch=256, max_inflight=2,
+                      max_queue=max(4096, len(w)))
+    server.batch_config(T.BatchConfig(32, 1, 8, 0))
+    ids = open_all(server, w)
+    torch.cuda.synchronize()
+    lat, _ = server.replay(w.arrival_ns, [ids[int(s)] for s in w.session_of], depths, cams,
+                           T.REPLAY_SERVED)
+    assert lat.shape == (len(w),) and np.all(lat > 0)
+    for i in range(len(w.specs)):
+        v, fail = server.session(ids[i])
+        assert fail == T.OK
+        st = v.stats()
+        assert st.status == T.OK and st.pairs_dropped == 0
+        assert st.frames == int(np.sum(w.session_of == i))
+    pick = sorted(np.random.default_rng(5).choice(len(w.specs), 32, replace=False).tolist())
+    mine = {i: [j for j in range(len(w)) if w.session_of[j] == i] for i in pick}
+    host = {i: ([depths[j].cpu().numpy() for j in mine[i]], [cams[j] for j in mine[i]])
+            for i in pick}
+
+    def oracle_of(i):
+        spec = w.specs[i]
+        return O.fuse_frames(spec.voxel_size, spec.trunc, spec.pool_capacity, *host[i])
+
+    n_thr = max(1, min(16, os.cpu_count() or 1))
+    with ThreadPoolExecutor(n_thr) as ex:
+        for i, o in zip(pick, ex.map(oracle_of, pick)):
+            assert_parity(result_of(server.session(ids[i])[0]), o)
+    log(f"  {len(w)} frames served; sessions {pick} match the oracle")
+    del server, depths
+    torch.cuda.empty_cache()
+
+
 def test_replay_served_and_plain():
     w = S.ServingWorkload(12, rate=3000.0, duration_s=0.05, seed=23, sizes=S.FRAME_SIZES,
                           log2_pools=(16, 17))
