@@ -1109,31 +1109,40 @@ def main() -> int:
         copy_stream = torch.cuda.Stream()
         free = [None, None]  # per buffer: the event after the last launch that reads it
 
+        spans = []  # per timed step: (upload start, upload end, launch start, launch end) events
+
         def fuse_e2e(events=None):
             if L.tsdf_reset_volume(h, sp) != T.OK:
                 raise RuntimeError("reset failed")
             if events is not None:
                 events[0].record(stream)
+                spans.append([])
             for j, (i0, n) in enumerate(chunks):
                 b = j % 2
+                ev = [torch.cuda.Event(enable_timing=events is not None) for _ in range(4)]
                 if free[b] is not None:
                     copy_stream.wait_event(free[b])
                 with torch.cuda.stream(copy_stream):
+                    ev[0].record(copy_stream)
                     bufs[b][:n].copy_(host[i0:i0 + n], non_blocking=True)
-                ready = torch.cuda.Event()
-                ready.record(copy_stream)
-                stream.wait_event(ready)
+                    ev[1].record(copy_stream)
+                stream.wait_event(ev[1])
+                ev[2].record(stream)
                 c_ = T.C.cast(T.C.byref(cam_arr, i0 * T.C.sizeof(T.CameraC)), T.C.c_void_p)
                 if L.tsdf_fuse_frames(h, n, T.C.cast(buf_ptrs[b], T.C.c_void_p), c_, bflags,
                                       sp) != T.OK:
                     raise RuntimeError("batched fusion failed")
-                done = torch.cuda.Event()
-                done.record(stream)
-                free[b] = done
+                ev[3].record(stream)
+                free[b] = ev[3]
+                if events is not None:
+                    spans[-1].append((ev, n))
             if events is not None:
                 events[1].record(stream)
 
         wall_e, e2e_ms = timed(fuse_e2e, 1)
+        full_spans = [(ev, n) for step in spans for (ev, n) in step if n == fpl]
+        up_ms = float(np.mean([ev[0].elapsed_time(ev[1]) for ev, _ in full_spans]))
+        fuse_ms = float(np.mean([ev[2].elapsed_time(ev[3]) for ev, _ in full_spans]))
         # the upload alone: all frames of a step in one pinned-to-device copy
         dev_all = torch.empty_like(host, device="cuda")
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -1148,6 +1157,7 @@ def main() -> int:
                "ms_per_step": wall_e / args.steps * 1e3,
                "median_ms_per_step": float(np.median(e2e_ms[:, 0])),
                "h2d_gb_per_s": h2d_gbs,
+               "mean_upload_ms_overlapped": up_ms, "mean_launch_ms_overlapped": fuse_ms,
                "path": f"frames in pinned host memory, {fpl} uploaded per launch on a second "
                        "stream into one of two device buffers, then tsdf_fuse_frames"}
         log(f"[bench] end to end: {e2e['value']:.3e} points/s, H2D {h2d_gbs:.1f} GB/s")
