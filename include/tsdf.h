@@ -343,11 +343,15 @@ typedef struct tsdf_fuse_item {
  * tile tile_width pixels wide and pixels_per_thread * 256 / tile_width tall;
  * each thread takes pixels_per_thread pixels of one column, so a wave covers
  * 64 * pixels_per_thread points.  The workgroup sums the tile's contributions
- * in LDS, acc_blocks voxel blocks per pass, before adding them to the pool. */
+ * in LDS, one slot per touched voxel, before adding them to the pool; the LDS
+ * region is acc_blocks voxel blocks' worth of floats plus 4 KiB, which holds
+ * 1280 voxel slots per pass with 4 and 3328 with 8 (colour volumes take a
+ * fixed 48 KiB region of 1945 slots).  A tile that touches more voxels takes
+ * more passes. */
 typedef struct tsdf_batch_config {
   uint32_t tile_width;         /* 16, 32 or 64 */
   uint32_t pixels_per_thread;  /* 1 or 2 */
-  uint32_t acc_blocks;         /* 4 or 8 (8 with 2 pixels per thread) */
+  uint32_t acc_blocks;         /* LDS region: 4 or 8 (8 with 2 pixels per thread) */
   uint32_t groups_per_cu;      /* workgroups of the persistent grid per compute
                                   unit; 0 = as many as can be resident */
 } tsdf_batch_config;
