@@ -171,7 +171,11 @@ tsdf_status tsdf_reset_volume(tsdf_volume* vol, void* hip_stream);
 
 /* Fuse one depth frame (Section 2.2: allocate then integrate).  `depth_dev` is
  * height x width float32 metres, row-major, camera-frame z; pixels that are not
- * finite or not > 0 are not points.  Asynchronous: returns once enqueued. */
+ * finite or not > 0 are not points.  It may be device memory or pinned host
+ * memory at its device address (hipHostGetDevicePointer); the kernels read
+ * each pixel once, so a pinned frame is read over PCIe with no copy.
+ * Asynchronous: returns once enqueued; the frame must stay valid until the
+ * fusion completes. */
 tsdf_status tsdf_fuse_frame(tsdf_volume* vol, const float* depth_dev, const tsdf_camera* cam,
                             void* hip_stream);
 
@@ -215,7 +219,9 @@ tsdf_status tsdf_fuse_frame_rgb(tsdf_volume* vol, const float* depth_dev, const 
  * when round(trunc/voxel_size) > 4.  The result is that of fusing the frames
  * one by one with tsdf_fuse_frame, in any order (keys and weights identical,
  * TSDF sums up to float summation order).
- *   depth_devs  host array of n_frames device pointers (height x width float32)
+ *   depth_devs  host array of n_frames device-accessible pointers (height x
+ *               width float32; device memory or pinned host memory, as for
+ *               tsdf_fuse_frame)
  *   cams        host array of n_frames cameras (sizes may differ)
  *   flags       TSDF_FUSE_XCD_REMAP and/or TSDF_FUSE_BATCH(m), m in 0..15
  * Asynchronous, like tsdf_fuse_frame. */

@@ -14,9 +14,9 @@ from oracle import oracle as O
 from paper_2608_08287_amd import scenes as S
 from paper_2608_08287_amd import tsdf as T
 
-from parity import (EMPTY, SCATTER, TSDF_ATOL, add_slices, assert_parity, assert_table_invariants,
-                    log, oracle_slices, result_of, run_gpu, run_workload, scattered_frames,
-                    table_arrays)
+from parity import (EMPTY, SCATTER, TSDF_ATOL, add_slices, assert_parity, assert_same_volume,
+                    assert_table_invariants, log, oracle_slices, result_of, run_gpu, run_workload,
+                    scattered_frames, table_arrays)
 
 pytestmark = pytest.mark.gpu
 
@@ -509,6 +509,45 @@ def test_full_trajectory_batched_equals_plain():
     # a subset: their keys must all be present here
     o = O.fuse_frames(w.voxel_size, w.trunc, w.pool_capacity, [w.depth[0]], [w.cameras[0]])
     assert np.all(np.isin(o.keys, g_b.keys))
+
+
+def test_frames_read_from_pinned_host_memory():
+    """Depth frames in pinned host memory, passed at the device addresses the
+    runtime maps them to, are read by the kernels over PCIe: the plain and the
+    batched path give the same volume as frames in device memory."""
+    import ctypes
+
+    w = S.room_trajectory_workload(frames=[0, 1, 2, 3, 150])
+    n = len(w.depth)
+    H, W = w.depth[0].shape
+    host = torch.empty((n, H, W), dtype=torch.float32, pin_memory=True)
+    for k in range(n):
+        host[k].copy_(torch.from_numpy(w.depth[k]))
+    hip = ctypes.CDLL("libamdhip64.so.7")
+    hip.hipHostGetDevicePointer.restype = ctypes.c_int
+    hip.hipHostGetDevicePointer.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p,
+                                            ctypes.c_uint]
+    dptr = (ctypes.c_void_p * n)()
+    for k in range(n):
+        dp = ctypes.c_void_p()
+        assert hip.hipHostGetDevicePointer(ctypes.byref(dp), host[k].data_ptr(), 0) == 0
+        assert dp.value
+        dptr[k] = dp.value
+    cams = (T.CameraC * n)(*[T.camera_struct(c) for c in w.cameras])
+    sp = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    L = T.lib()
+    ref = T.Volume(w.voxel_size, w.trunc, w.table_capacity, w.pool_capacity)
+    ref.fuse_frames([torch.from_numpy(d).cuda() for d in w.depth], w.cameras)
+    batched = T.Volume(w.voxel_size, w.trunc, w.table_capacity, w.pool_capacity)
+    assert L.tsdf_fuse_frames(batched.handle, n, dptr, cams, 0, sp) == T.OK
+    plain = T.Volume(w.voxel_size, w.trunc, w.table_capacity, w.pool_capacity)
+    for k in range(n):
+        assert L.tsdf_fuse_frame(plain.handle, dptr[k], ctypes.byref(cams[k]), sp) == T.OK
+    torch.cuda.synchronize()
+    st = assert_same_volume(batched, ref)
+    assert_same_volume(plain, ref)
+    assert st.status == T.OK and st.points_valid == n * H * W
+    del host
 
 
 @pytest.mark.parametrize("design", ["main", "slot index"])
