@@ -339,7 +339,8 @@ typedef struct tsdf_batch tsdf_batch;
 
 typedef struct tsdf_fuse_item {
   tsdf_volume* volume;      /* target volume */
-  const float* depth_dev;   /* height x width float32, as for tsdf_fuse_frame */
+  const float* depth_dev;   /* height x width float32, as for tsdf_fuse_frame
+                               (device memory or pinned host memory) */
   const uint32_t* rgba_dev; /* colour volumes: height x width packed colours, as
                                for tsdf_fuse_frame_rgb; ignored otherwise */
   tsdf_camera camera;

@@ -513,8 +513,9 @@ def test_full_trajectory_batched_equals_plain():
 
 def test_frames_read_from_pinned_host_memory():
     """Depth frames in pinned host memory, passed at the device addresses the
-    runtime maps them to, are read by the kernels over PCIe: the plain and the
-    batched path give the same volume as frames in device memory."""
+    runtime maps them to, are read by the kernels over PCIe: the plain, the
+    batched and the multi-volume batch path give the same volumes as frames in
+    device memory."""
     import ctypes
 
     w = S.room_trajectory_workload(frames=[0, 1, 2, 3, 150])
@@ -543,10 +544,25 @@ def test_frames_read_from_pinned_host_memory():
     plain = T.Volume(w.voxel_size, w.trunc, w.table_capacity, w.pool_capacity)
     for k in range(n):
         assert L.tsdf_fuse_frame(plain.handle, dptr[k], ctypes.byref(cams[k]), sp) == T.OK
+    # the multi-volume batch path: each frame into its own volume, one launch
+    vols = [T.Volume(w.voxel_size, w.trunc, w.table_capacity, w.pool_capacity) for _ in range(n)]
+    items = (T.FuseItemC * n)()
+    for k in range(n):
+        items[k].volume = vols[k].handle.value
+        items[k].depth_dev = dptr[k]
+        items[k].camera = cams[k]
+    batch = T.Batch(n)
+    batch.set_config(T.BatchConfig(32, 2, 8, 0))
+    assert L.tsdf_batch_fuse(batch._h, items, n, 0, sp) == T.OK
+    alone = [T.Volume(w.voxel_size, w.trunc, w.table_capacity, w.pool_capacity) for _ in range(n)]
+    for k in range(n):
+        alone[k].fuse(torch.from_numpy(w.depth[k]).cuda(), w.cameras[k])
     torch.cuda.synchronize()
     st = assert_same_volume(batched, ref)
     assert_same_volume(plain, ref)
     assert st.status == T.OK and st.points_valid == n * H * W
+    for k in range(n):
+        assert_same_volume(vols[k], alone[k])
     del host
 
 
