@@ -558,7 +558,8 @@ def bench_serve(args) -> int:
     cfg = T.BatchConfig(*(int(x) for x in args.batch_config.split(","))) if args.batch_config \
         else T.BatchConfig(32, 1, 8, 0)
 
-    def run(mode, budget):
+    def run(mode, budget, frames=None):
+        frames = depths if frames is None else frames
         server = T.Server(budget, max_sessions=len(w.specs) + 1, max_batch=args.max_batch,
                           max_inflight=args.max_inflight, max_queue=max(4096, n))
         server.batch_config(cfg)
@@ -581,8 +582,8 @@ def bench_serve(args) -> int:
         server.close_session(warm)
         torch.cuda.synchronize()
         sess = [ids[int(s)] for s in w.session_of]
-        lat, elapsed = server.replay(w.arrival_ns, sess, depths, cams, mode)
-        _, cap_elapsed = server.replay(np.zeros(n, dtype=np.int64), sess, depths, cams, mode)
+        lat, elapsed = server.replay(w.arrival_ns, sess, frames, cams, mode)
+        _, cap_elapsed = server.replay(np.zeros(n, dtype=np.int64), sess, frames, cams, mode)
         stats = [server.session(i)[0].stats() for i in ids]
         fails = [k for k, i in enumerate(ids)
                  if server.session(i)[1] != T.OK or stats[k].status != T.OK]
@@ -598,6 +599,48 @@ def bench_serve(args) -> int:
     lat_p, el_p, cap_p, st_p, fail_p, _ = run(T.REPLAY_PLAIN, int(need * 1.02) + (64 << 20))
     log(f"[bench] plain: p50 {np.percentile(lat_p, 50) / 1e3:.1f} us, "
         f"p99 {np.percentile(lat_p, 99) / 1e3:.1f} us; capacity {points / cap_p * 1e9:.3e} points/s")
+    # served again with every frame in pinned host memory, handed over at its
+    # device address: the kernels read the depth over PCIe, nothing is uploaded
+    zc = None
+    total = sum(d.numel() for d in depths)
+    host = torch.empty(total, dtype=torch.float32, pin_memory=True)
+    hip = T.C.CDLL("libamdhip64.so.7")
+    hip.hipHostGetDevicePointer.restype = T.C.c_int
+    hip.hipHostGetDevicePointer.argtypes = [T.C.POINTER(T.C.c_void_p), T.C.c_void_p, T.C.c_uint]
+
+    class _Mapped:  # a frame known by its device address
+        def __init__(self, addr):
+            self.addr = addr
+
+        def data_ptr(self):
+            return self.addr
+
+    zframes, off = [], 0
+    for d in depths:
+        host[off:off + d.numel()].copy_(d.reshape(-1))
+        dp = T.C.c_void_p()
+        if hip.hipHostGetDevicePointer(T.C.byref(dp), T.C.c_void_p(host[off:].data_ptr()),
+                                       0) != 0 or not dp.value:
+            zframes = None  # no device address: the run is skipped, nothing launched
+            break
+        zframes.append(_Mapped(dp.value))
+        off += d.numel()
+    torch.cuda.synchronize()
+    if zframes is not None:
+        lat_z, el_z, cap_z, st_z, fail_z, _ = run(T.REPLAY_SERVED, int(args.budget_gb * 1e9),
+                                                  frames=zframes)
+        log(f"[bench] served, zero copy: p50 {np.percentile(lat_z, 50) / 1e3:.1f} us, "
+            f"p99 {np.percentile(lat_z, 99) / 1e3:.1f} us; capacity "
+            f"{points / cap_z * 1e9:.3e} points/s")
+        for i, (a, b) in enumerate(zip(st_s, st_z)):
+            for f in ("points_valid", "pairs", "pairs_dropped", "blocks_total", "frames"):
+                if getattr(a, f) != getattr(b, f):
+                    print(f"gate failed: zero-copy session {i} {f} {getattr(a, f)} != "
+                          f"{getattr(b, f)}", file=sys.stderr)
+                    return 1
+        fail_s = sorted(set(fail_s) | set(fail_z))
+        zc = (lat_z, el_z, cap_z)
+    del host
     if fail_s or fail_p:
         bad = sorted(set(fail_s) | set(fail_p))
         print(f"gate failed: sessions whose pool or table ran out (served {fail_s}, plain "
@@ -660,6 +703,13 @@ def bench_serve(args) -> int:
             "capacity_points_per_s": plain_value,
         },
         "capacity_vs_plain": value / plain_value,
+        "served_zero_copy": None if zc is None else {
+            "p50_latency_ms": pct(zc[0], 50), "p99_latency_ms": pct(zc[0], 99),
+            "max_latency_ms": pct(zc[0], 100),
+            "sustained_points_per_s": points / (zc[1] * 1e-9),
+            "capacity_points_per_s": points / (zc[2] * 1e-9),
+            "path": "served, every frame in pinned host memory at its device address (the "
+                    "kernels read the depth over PCIe; no upload)"},
         "roofline": None,
         "cpu_baseline": None,
     }
