@@ -888,6 +888,8 @@ def main() -> int:
                          "sessions with Poisson arrivals through the server; stress: the "
                          "fronto-parallel plane through a table at load factor 0.95; "
                          "lf-sweep: the orbit through tables at final load factors 0.25-0.9")
+    ap.add_argument("--colour-path", choices=["frames", "batch"], default="frames",
+                    help="colour variant: tsdf_fuse_frames_rgb (default) or the batch API")
     ap.add_argument("--cold-volumes", type=int, default=8,
                     help="trajectory: fresh volumes for the cold-frame timing (0: skip it and "
                          "the end-to-end timing)")
@@ -980,7 +982,8 @@ def main() -> int:
     bflags = T.FUSE_BATCH(args.per_group)
 
     if colour:
-        # colour frames go through the batch path: fpl items of the one volume
+        rgba_arr = (T.C.c_void_p * len(ptrs))(*[c.data_ptr() for c in rgba])
+        # the alternative route: the batch API, fpl items of the one volume
         cbatch = T.Batch(fpl)
         cbatch.set_config(T.BatchConfig(32, 1, 4, 0))
         items = (T.FuseItemC * len(ptrs))()
@@ -998,10 +1001,15 @@ def main() -> int:
         for j, (i0, n) in enumerate(chunks):
             if events is not None:
                 events[j].record(stream)
-            if colour:
+            if colour and args.colour_path == "batch":
                 it = T.C.cast(T.C.byref(items, i0 * T.C.sizeof(T.FuseItemC)),
                               T.C.POINTER(T.FuseItemC))
                 st = L.tsdf_batch_fuse(cbatch._h, it, n, 0, sp)
+            elif colour:
+                p = T.C.cast(T.C.byref(ptr_arr, i0 * T.C.sizeof(T.C.c_void_p)), T.C.c_void_p)
+                r = T.C.cast(T.C.byref(rgba_arr, i0 * T.C.sizeof(T.C.c_void_p)), T.C.c_void_p)
+                c = T.C.cast(T.C.byref(cam_arr, i0 * T.C.sizeof(T.CameraC)), T.C.c_void_p)
+                st = L.tsdf_fuse_frames_rgb(h, n, p, r, c, bflags, sp)
             else:
                 p = T.C.cast(T.C.byref(ptr_arr, i0 * T.C.sizeof(T.C.c_void_p)), T.C.c_void_p)
                 c = T.C.cast(T.C.byref(cam_arr, i0 * T.C.sizeof(T.CameraC)), T.C.c_void_p)
@@ -1300,9 +1308,9 @@ def main() -> int:
                         f"table 2^20 slots, pool {'2^20' if slot else '2^18'} blocks"
                         + (", colour images" if colour else ""),
             "path": (f"batched: tsdf_batch_fuse, {fpl} frames of the volume per launch"
-                     if colour else
-                     f"batched: tsdf_fuse_frames, {fpl} frames per launch, "
-                     f"{args.per_group} frame(s) per workgroup"),
+                     if colour and args.colour_path == "batch" else
+                     f"batched: tsdf_fuse_frames{'_rgb' if colour else ''}, {fpl} frames per "
+                     f"launch, {args.per_group} frame(s) per workgroup"),
             "variant": {"main": "main design", "slot": "block index = table slot",
                         "colour": "TSDF, weight and three colour sums"}[args.variant],
             "frames_per_step": len(ptrs), "points_per_step": points_per_step,
@@ -1334,8 +1342,9 @@ def main() -> int:
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": ("fuse_multi_kernel<4, 1, 4, colour>" if colour
-                       else f"fuse_kernel<4, {args.per_group}, 32, fused>"),
+            "kernel": ("fuse_multi_kernel<4, 1, 4, colour>" if colour and args.colour_path == "batch"
+                       else f"fuse_kernel<4, {args.per_group}, 32, fused"
+                            f"{', colour' if colour else ''}>"),
             "algorithmic_bytes_per_launch": bytes_per_launch,
             "mean_launch_ms": mean_launch_ms,
             "touched_voxels_per_frame": acc["V"] / len(ptrs),

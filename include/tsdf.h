@@ -231,6 +231,21 @@ tsdf_status tsdf_fuse_frame_rgb(tsdf_volume* vol, const float* depth_dev, const 
 tsdf_status tsdf_fuse_frames(tsdf_volume* vol, uint32_t n_frames, const float* const* depth_devs,
                              const tsdf_camera* cams, uint32_t flags, void* hip_stream);
 
+/* tsdf_fuse_frames for colour volumes (TSDF_VOLUME_COLOUR): frame i also adds
+ * the colours of rgba_devs[i] (height x width packed red | green << 8 |
+ * blue << 16, as for tsdf_fuse_frame_rgb) to the voxels its pairs touch.  F is
+ * set as for tsdf_fuse_frames but at most 2: the colour slot region holds 1945
+ * voxels per pass.  The result is that of fusing the frames one by one with
+ * tsdf_fuse_frame_rgb (keys, weights and colour sums identical, TSDF sums up
+ * to float summation order).  A plain volume, or a null rgba_devs (or entry
+ * for a frame with pixels), is TSDF_ERR_INVALID_ARGUMENT.
+ *   rgba_devs   host array of n_frames device-accessible pointers
+ * Asynchronous, like tsdf_fuse_frame. */
+tsdf_status tsdf_fuse_frames_rgb(tsdf_volume* vol, uint32_t n_frames,
+                                 const float* const* depth_devs,
+                                 const uint32_t* const* rgba_devs, const tsdf_camera* cams,
+                                 uint32_t flags, void* hip_stream);
+
 /* Wait for `hip_stream`, read the counters and return the most severe sticky
  * condition (INTERNAL > TABLE_FULL > POOL_EXHAUSTED > COORD_RANGE), or TSDF_OK.
  * `out` may be NULL. */

@@ -196,22 +196,30 @@ tsdf_status tsdf_fuse_frame_rgb(tsdf_volume* vol, const float* depth_dev, const 
   return fuse_one(vol, depth_dev, rgba_dev, cam, flags, hip_stream);
 }
 
-tsdf_status tsdf_fuse_frames(tsdf_volume* vol, uint32_t n_frames, const float* const* depth_devs,
-                             const tsdf_camera* cams, uint32_t flags, void* hip_stream) {
-  if (!vol || (n_frames > 0 && (!depth_devs || !cams))) return TSDF_ERR_INVALID_ARGUMENT;
+namespace {
+
+// Several frames of one volume, up to kMaxBatchFrames per launch; rgba_devs is
+// null for plain volumes and required (per frame with pixels) for colour ones.
+tsdf_status fuse_frames_impl(tsdf_volume* vol, uint32_t n_frames, const float* const* depth_devs,
+                             const uint32_t* const* rgba_devs, const tsdf_camera* cams,
+                             uint32_t flags, void* hip_stream) {
+  if (n_frames > 0 && (!depth_devs || !cams)) return TSDF_ERR_INVALID_ARGUMENT;
   if ((flags & ~(TSDF_FUSE_XCD_REMAP | TSDF_FUSE_BATCH_MASK)) != 0) return TSDF_ERR_INVALID_ARGUMENT;
-  if (vol->dev.colour) return TSDF_ERR_INVALID_ARGUMENT;  // colour frames: _rgb or batches
+  const bool colour = vol->dev.colour != nullptr;
+  if (colour && n_frames > 0 && !rgba_devs) return TSDF_ERR_INVALID_ARGUMENT;
   for (uint32_t i = 0; i < n_frames; ++i) {
     if (!valid_camera(&cams[i])) return TSDF_ERR_INVALID_ARGUMENT;
-    if ((uint64_t)cams[i].width * cams[i].height > 0 && !depth_devs[i])
+    if ((uint64_t)cams[i].width * cams[i].height > 0 &&
+        (!depth_devs[i] || (colour && !rgba_devs[i])))
       return TSDF_ERR_INVALID_ARGUMENT;
   }
   const tsdf::WalkParams wp = walk_params(vol);
   // frames summed per workgroup: the TSDF_FUSE_BATCH(m) request rounded down to
-  // 1, 2 or 4 (2 when m = 0, the measured best), capped for wide bands
+  // 1, 2 or 4 (2 when m = 0, the measured best), capped for wide bands and, for
+  // colour volumes, at 2
   const uint32_t asked = (flags & TSDF_FUSE_BATCH_MASK) >> TSDF_FUSE_BATCH_SHIFT;
   int per_group = asked == 0 ? 2 : asked >= 4 ? 4 : asked >= 2 ? 2 : 1;
-  const int cap = tsdf::max_frames_per_group(wp.K);
+  const int cap = colour ? 2 : tsdf::max_frames_per_group(wp.K);
   if (per_group > cap) per_group = cap;
   const bool remap = (flags & TSDF_FUSE_XCD_REMAP) != 0;
   hipStream_t s = as_stream(hip_stream);
@@ -222,7 +230,8 @@ tsdf_status tsdf_fuse_frames(tsdf_volume* vol, uint32_t n_frames, const float* c
     const int n = left < (uint32_t)tsdf::kMaxBatchFrames ? (int)left : tsdf::kMaxBatchFrames;
     uint64_t pix = 0;
     for (int i = 0; i < n; ++i) {
-      batch[i] = frame_dev(depth_devs[done + i], &cams[done + i]);
+      batch[i] = frame_dev(depth_devs[done + i], &cams[done + i],
+                           colour ? rgba_devs[done + i] : nullptr);
       pix += (uint64_t)cams[done + i].width * cams[done + i].height;
     }
     if (pix > 0 && tsdf::launch_fuse(vol->dev, wp, batch, n, n > 1 ? per_group : 1,
@@ -232,6 +241,23 @@ tsdf_status tsdf_fuse_frames(tsdf_volume* vol, uint32_t n_frames, const float* c
     vol->frames += (uint32_t)n;
   }
   return TSDF_OK;
+}
+
+}  // namespace
+
+tsdf_status tsdf_fuse_frames(tsdf_volume* vol, uint32_t n_frames, const float* const* depth_devs,
+                             const tsdf_camera* cams, uint32_t flags, void* hip_stream) {
+  if (!vol) return TSDF_ERR_INVALID_ARGUMENT;
+  if (vol->dev.colour) return TSDF_ERR_INVALID_ARGUMENT;  // colour frames: _rgb or batches
+  return fuse_frames_impl(vol, n_frames, depth_devs, nullptr, cams, flags, hip_stream);
+}
+
+tsdf_status tsdf_fuse_frames_rgb(tsdf_volume* vol, uint32_t n_frames,
+                                 const float* const* depth_devs,
+                                 const uint32_t* const* rgba_devs, const tsdf_camera* cams,
+                                 uint32_t flags, void* hip_stream) {
+  if (!vol || !vol->dev.colour) return TSDF_ERR_INVALID_ARGUMENT;
+  return fuse_frames_impl(vol, n_frames, depth_devs, rgba_devs, cams, flags, hip_stream);
 }
 
 tsdf_status tsdf_fuse_frame(tsdf_volume* vol, const float* depth_dev, const tsdf_camera* cam,

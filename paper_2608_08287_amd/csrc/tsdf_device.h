@@ -411,8 +411,9 @@ struct FuseArgs {
 // tile before they reach the pool; NB > F puts several frames in one grid so
 // one frame's start-up overlaps another's pool updates.
 // Two frames per workgroup would take ~146 VGPRs (3 waves per SIMD); asking
-// for 4 waves per SIMD costs a few spilled dwords and measures faster.
-constexpr int waves_per_eu_for(int F) { return F == 2 ? 4 : 1; }
+// for 4 waves per SIMD costs a few spilled dwords and measures faster.  Colour
+// workgroups take more LDS, three per CU: no cap.
+constexpr int waves_per_eu_for(int F, bool colour) { return (F == 2 && !colour) ? 4 : 1; }
 
 // Accumulator floats per block: sums and counts in the pool's row layout,
 // then (colour volumes) the red, green and blue sums in the colour layout.
@@ -927,7 +928,8 @@ constexpr int kColourAccBlocks = 4;
 constexpr int acc_blocks_for(bool colour) { return colour ? kColourAccBlocks : kAccBlocks; }
 
 template <int K, int F, int NB, FuseMode kMode, bool kColour>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(waves_per_eu_for(F))))
+__global__ __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu(waves_per_eu_for(F, kColour))))
 void fuse_kernel(FuseArgs<NB> args) {
   constexpr int AB = acc_blocks_for(kColour);
   __shared__ TileShared<AB, kColour> sh;
@@ -1081,8 +1083,8 @@ hipError_t launch_fuse_kf(VolumeDev vol, const WalkParams& wp, const FrameDev* f
     }
   } else {
     (void)mode;
-    static_assert(!kColour, "colour frames are fused one per launch or through batches");
-    hipLaunchKernelGGL((fuse_kernel<K, F, NB, FuseMode::kFused, false>), grid, block, 0, s, args);
+    hipLaunchKernelGGL((fuse_kernel<K, F, NB, FuseMode::kFused, kColour>), grid, block, 0, s,
+                       args);
   }
   return hipGetLastError();
 }
@@ -1098,7 +1100,13 @@ hipError_t launch_fuse_k(VolumeDev vol, const WalkParams& wp, const FrameDev* fr
   if (n == 1)
     return colour ? launch_fuse_kf<K, 1, 1, true>(vol, wp, frames, 1, mode, remap, s)
                   : launch_fuse_kf<K, 1, 1, false>(vol, wp, frames, 1, mode, remap, s);
-  if (colour) return hipErrorInvalidValue;
+  if (colour) {
+    // colour volumes: one or two frames per workgroup (the colour slot region
+    // holds 1945 voxels; four frames of a tile would take several passes)
+    if (frames_per_group == 1)
+      return launch_fuse_kf<K, 1, kMaxBatchFrames, true>(vol, wp, frames, n, mode, remap, s);
+    return launch_fuse_kf<K, 2, kMaxBatchFrames, true>(vol, wp, frames, n, mode, remap, s);
+  }
   switch (frames_per_group) {
     case 1: return launch_fuse_kf<K, 1, kMaxBatchFrames, false>(vol, wp, frames, n, mode, remap, s);
     case 2: return launch_fuse_kf<K, 2, kMaxBatchFrames, false>(vol, wp, frames, n, mode, remap, s);

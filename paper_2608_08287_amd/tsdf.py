@@ -39,6 +39,7 @@ EMPTY_KEY = 0xFFFFFFFFFFFFFFFF
 EXPORTED_SYMBOLS = (
     "tsdf_volume_bytes", "tsdf_volume_layout", "tsdf_create_volume", "tsdf_destroy_volume",
     "tsdf_reset_volume", "tsdf_fuse_frame", "tsdf_fuse_frame_ex", "tsdf_fuse_frames",
+    "tsdf_fuse_frames_rgb",
     "tsdf_query_status", "tsdf_probe_histogram", "tsdf_measure_atomic_rate",
     "tsdf_extract_blocks", "tsdf_extract_mesh", "tsdf_insert_blocks", "tsdf_status_str",
     "tsdf_fuse_frame_rgb", "tsdf_extract_colour",
@@ -138,6 +139,8 @@ def lib() -> C.CDLL:
         L.tsdf_fuse_frame_ex.argtypes = [P, P, C.POINTER(CameraC), U32, P]
         L.tsdf_fuse_frames.restype = I
         L.tsdf_fuse_frames.argtypes = [P, U32, P, P, U32, P]
+        L.tsdf_fuse_frames_rgb.restype = I
+        L.tsdf_fuse_frames_rgb.argtypes = [P, U32, P, P, P, U32, P]
         L.tsdf_query_status.restype = I
         L.tsdf_query_status.argtypes = [P, P, C.POINTER(StatsC)]
         L.tsdf_probe_histogram.restype = I
@@ -433,6 +436,27 @@ class Volume(_VolumeCalls):
         st = lib().tsdf_fuse_frames(self._h, n, ptrs, cam_arr, flags, _stream_ptr(stream))
         if st != OK:
             raise TsdfError(st, "tsdf_fuse_frames")
+
+    def fuse_frames_rgb(self, depths: Sequence[torch.Tensor], rgbas: Sequence[torch.Tensor], cams,
+                        flags: int = 0, stream=None) -> None:
+        """fuse_frames for a colour volume: (H, W) int32 device colour images
+        (packed red | green << 8 | blue << 16) beside the depth frames."""
+        n = len(depths)
+        structs = [c if isinstance(c, CameraC) else camera_struct(c) for c in cams]
+        if len(structs) != n or len(rgbas) != n:
+            raise ValueError("one camera and one colour image per frame")
+        for d, r, c in zip(depths, rgbas, structs):
+            for t in (d, r):
+                if not t.is_cuda or not t.is_contiguous() or t.numel() != c.width * c.height:
+                    raise TypeError("frames must be contiguous device tensors of the camera's size")
+            if d.dtype != torch.float32 or r.dtype != torch.int32:
+                raise TypeError("depth is float32, colour int32")
+        ptrs = (C.c_void_p * max(n, 1))(*[d.data_ptr() for d in depths])
+        cols = (C.c_void_p * max(n, 1))(*[r.data_ptr() for r in rgbas])
+        cam_arr = (CameraC * max(n, 1))(*structs)
+        st = lib().tsdf_fuse_frames_rgb(self._h, n, ptrs, cols, cam_arr, flags, _stream_ptr(stream))
+        if st != OK:
+            raise TsdfError(st, "tsdf_fuse_frames_rgb")
 
     def insert_blocks(self, coords: torch.Tensor, stream=None) -> None:
         """Allocate blocks for (n, 3) int32 device block coordinates."""

@@ -113,6 +113,8 @@ def test_null_handles_are_rejected():
     assert L.tsdf_insert_blocks(None, C.c_void_p(256), 1, None) == T.ERR_INVALID_ARGUMENT
     assert L.tsdf_fuse_frame_rgb(None, C.c_void_p(256), C.c_void_p(256), C.byref(cam), 0,
                                  None) == T.ERR_INVALID_ARGUMENT
+    assert L.tsdf_fuse_frames(None, 0, None, None, 0, None) == T.ERR_INVALID_ARGUMENT
+    assert L.tsdf_fuse_frames_rgb(None, 0, None, None, None, 0, None) == T.ERR_INVALID_ARGUMENT
     assert L.tsdf_extract_colour(None, None, 0, None, C.byref(n)) == T.ERR_INVALID_ARGUMENT
     assert L.tsdf_extract_mesh(None, None, 0, None, None, C.byref(n)) == T.ERR_INVALID_ARGUMENT
 

@@ -181,6 +181,41 @@ def test_colour_matches_the_oracle(room, variant):
     log(f"  {variant}: {o.keys.size} blocks, colour sums exact")
 
 
+@pytest.mark.parametrize("per_group", [1, 2])
+def test_colour_frames_batched_match_the_oracle(room, per_group):
+    """tsdf_fuse_frames_rgb: colour frames several per launch, 1 or 2 per
+    workgroup, against the oracle (keys, weights and colour sums exact) and
+    against the same frames fused one by one."""
+    w, rgba = room
+    ov = O.OracleVolume(w.voxel_size, w.trunc, 1 << 18)
+    for d, c, cam in zip(w.depth, rgba, w.cameras):
+        ov.fuse_rgb(d, c, cam)
+    o = ov.result()
+    dev = [torch.from_numpy(d).cuda() for d in w.depth]
+    cols = [torch.from_numpy(c.view(np.int32)).cuda() for c in rgba]
+    vol = T.Volume(w.voxel_size, w.trunc, 1 << 20, 1 << 18, flags=T.VOLUME_COLOUR)
+    vol.fuse_frames_rgb(dev, cols, w.cameras, T.FUSE_BATCH(per_group))
+    one = T.Volume(w.voxel_size, w.trunc, 1 << 20, 1 << 18, flags=T.VOLUME_COLOUR)
+    for d, c, cam in zip(dev, cols, w.cameras):
+        one.fuse_rgb(d, c, cam)
+    g = result_of(vol)
+    assert_parity(g, o)
+    keys, sums = gpu_colour_sums(vol, o.keys.size, False)
+    assert np.array_equal(keys, o.keys)
+    assert np.array_equal(sums, ov.colour_sums()), "colour sums differ"
+    assert_same_volume(vol, one)
+    # a plain volume, or colour frames without colour images, are refused
+    plain = T.Volume(w.voxel_size, w.trunc, 1 << 16, 1 << 14)
+    with pytest.raises(T.TsdfError):
+        plain.fuse_frames_rgb(dev[:1], cols[:1], w.cameras[:1])
+    L = T.lib()
+    ptrs = (T.C.c_void_p * 1)(dev[0].data_ptr())
+    cams = (T.CameraC * 1)(T.camera_struct(w.cameras[0]))
+    assert L.tsdf_fuse_frames_rgb(vol.handle, 1, ptrs, None, cams, 0, None) == T.ERR_INVALID_ARGUMENT
+    assert L.tsdf_fuse_frames(vol.handle, 1, ptrs, cams, 0, None) == T.ERR_INVALID_ARGUMENT
+    log(f"  {o.keys.size} blocks, colour sums exact")
+
+
 def test_colour_full_trajectory_batched_matches_oracle():
     """The colour bench's whole run: all 300 frames into one colour volume
     through tsdf_batch_fuse, 32 frames per call, in the bench's configuration
