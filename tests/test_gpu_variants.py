@@ -216,12 +216,14 @@ def test_colour_frames_batched_match_the_oracle(room, per_group):
     log(f"  {o.keys.size} blocks, colour sums exact")
 
 
-def test_colour_full_trajectory_batched_matches_oracle():
-    """The colour bench's whole run: all 300 frames into one colour volume
-    through tsdf_batch_fuse, 32 frames per call, in the bench's configuration
-    (32-pixel-wide tiles, one pixel per thread, the colour LDS region), against
-    the oracle at every voxel: weights and colour sums exact, TSDF means within
-    the tolerance (oracle frame slices fused on threads, added by key)."""
+@pytest.mark.parametrize("path", ["frames", "batch"])
+def test_colour_full_trajectory_batched_matches_oracle(path):
+    """The colour bench's whole run: all 300 frames into one colour volume, 32
+    per call, through tsdf_fuse_frames_rgb (two frames per workgroup, the
+    bench's default) or through tsdf_batch_fuse (32-pixel-wide tiles, one
+    pixel per thread, the colour LDS region), against the oracle at every
+    voxel: weights and colour sums exact, TSDF means within the tolerance
+    (oracle frame slices fused on threads, added by key)."""
     import os
 
     w, rgba = S.room_trajectory_rgbd(device="cuda")
@@ -231,9 +233,12 @@ def test_colour_full_trajectory_batched_matches_oracle():
     batch.set_config(T.BatchConfig(32, 1, 4, 0))
     dev = [torch.from_numpy(d).cuda() for d in w.depth]
     cols = [torch.from_numpy(c.view(np.int32)).cuda() for c in rgba]
-    for i0 in range(0, len(dev), 32):
-        n = min(32, len(dev) - i0)
-        batch.fuse([vol] * n, dev[i0:i0 + n], w.cameras[i0:i0 + n], rgbas=cols[i0:i0 + n])
+    if path == "frames":
+        vol.fuse_frames_rgb(dev, cols, w.cameras)
+    else:
+        for i0 in range(0, len(dev), 32):
+            n = min(32, len(dev) - i0)
+            batch.fuse([vol] * n, dev[i0:i0 + n], w.cameras[i0:i0 + n], rgbas=cols[i0:i0 + n])
     g = result_of(vol)
     assert g.stats.status == T.OK and g.stats.pairs_dropped == 0
     keys, gcol = gpu_colour_sums(vol, g.keys.size, False)
