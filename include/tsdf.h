@@ -224,7 +224,8 @@ tsdf_status tsdf_fuse_frame_rgb(tsdf_volume* vol, const float* depth_dev, const 
  *               tsdf_fuse_frame)
  *   cams        host array of n_frames cameras (sizes may differ)
  *   flags       TSDF_FUSE_XCD_REMAP and/or TSDF_FUSE_BATCH(m), m in 0..15
- * Asynchronous, like tsdf_fuse_frame. */
+ * A colour volume is TSDF_ERR_INVALID_ARGUMENT (its frames carry colour
+ * images: tsdf_fuse_frames_rgb).  Asynchronous, like tsdf_fuse_frame. */
 #define TSDF_FUSE_BATCH_SHIFT 16
 #define TSDF_FUSE_BATCH_MASK (0xFu << TSDF_FUSE_BATCH_SHIFT)
 #define TSDF_FUSE_BATCH(m) (((uint32_t)(m) & 0xFu) << TSDF_FUSE_BATCH_SHIFT)
