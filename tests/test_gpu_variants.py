@@ -216,6 +216,41 @@ def test_colour_frames_batched_match_the_oracle(room, per_group):
     log(f"  {o.keys.size} blocks, colour sums exact")
 
 
+def test_colour_frames_mixed_sizes_and_invalid_pixels():
+    """tsdf_fuse_frames_rgb over frames of ragged sizes (partial tiles, a 1x1
+    frame, a zero-width frame) with invalid depths, two per workgroup: keys,
+    weights and colour sums exactly the oracle's."""
+    rng = np.random.default_rng(8)
+    sizes = [(13, 9), (40, 23), (1, 1), (17, 33), (0, 4), (64, 48), (37, 5)]
+    cams, depths, cols = [], [], []
+    for i, (W, H) in enumerate(sizes):
+        yaw, pitch, roll = rng.uniform(-2, 2, 3)
+        cy_, sy_ = np.cos(yaw), np.sin(yaw)
+        cp, sp_ = np.cos(pitch), np.sin(pitch)
+        cr, sr = np.cos(roll), np.sin(roll)
+        R = (np.array([[cy_, -sy_, 0], [sy_, cy_, 0], [0, 0, 1]])
+             @ np.array([[cp, 0, sp_], [0, 1, 0], [-sp_, 0, cp]])
+             @ np.array([[1, 0, 0], [0, cr, -sr], [0, sr, cr]]))
+        pose = np.concatenate([R, rng.uniform(-1, 1, (3, 1))], 1).astype(np.float32)
+        cams.append(S.Camera(W, H, 20.0 + i, 18.0, W / 2, H / 2, pose))
+        d = rng.uniform(0.3, 1.2, (H, W)).astype(np.float32)
+        if d.size:
+            d[rng.random((H, W)) < 0.2] = np.nan
+        depths.append(d)
+        cols.append(rng.integers(0, 1 << 24, (H, W), dtype=np.uint32))
+    ov = O.OracleVolume(0.01, 0.04, 1 << 14)
+    for d, c, cam in zip(depths, cols, cams):
+        ov.fuse_rgb(d, c, cam)
+    o = ov.result()
+    vol = T.Volume(0.01, 0.04, 1 << 15, 1 << 14, flags=T.VOLUME_COLOUR)
+    vol.fuse_frames_rgb([torch.from_numpy(d).cuda() for d in depths],
+                        [torch.from_numpy(c.view(np.int32)).cuda() for c in cols], cams)
+    assert_parity(result_of(vol), o)
+    keys, sums = gpu_colour_sums(vol, o.keys.size, False)
+    assert np.array_equal(keys, o.keys)
+    assert np.array_equal(sums, ov.colour_sums()), "colour sums differ"
+
+
 @pytest.mark.parametrize("path", ["frames", "batch"])
 def test_colour_full_trajectory_batched_matches_oracle(path):
     """The colour bench's whole run: all 300 frames into one colour volume, 32
