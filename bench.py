@@ -9,8 +9,12 @@ Depth frames are resident in HBM before timing starts.  The headline `value` is
 the trajectory fused through tsdf_fuse_frames (32 frames per launch); the plain
 path (one tsdf_fuse_frame launch per frame) is timed beside it and supplies the
 per-frame latency percentiles.  Also reported: the HBM roofline fraction of the
-headline path's fusion kernel on algorithmic bytes, and the CPU oracle's
-throughput on a bounded sample.
+headline path's fusion kernel on algorithmic bytes, its memory-side atomic
+requests against the ceiling measured in the same run, frames fused into empty
+volumes (cold), the rate with frames starting in pinned host memory (uploaded
+on a second stream, or read by the kernel directly), the device's state, and
+the CPU oracle's throughput on a bounded sample.  Other workloads: --workload
+multi / serve / stress / lf-sweep, and --variant slot / colour.
 """
 from __future__ import annotations
 
