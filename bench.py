@@ -289,7 +289,7 @@ def bench_multi(args) -> int:
 
         from oracle import oracle as O
         # the oracle's calls release the interpreter lock, so independent
-        # volumes fuse in parallel on threads (the box's share: 16 cores)
+        # volumes fuse in parallel on threads (at most 16)
         n_thr = max(1, min(16, os.cpu_count() or 1))
         # every volume's tick-0 frame, rendered before any timing, largest first
         # so that the threads finish together
