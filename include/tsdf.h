@@ -19,7 +19,9 @@
  *  - Device memory is owned by the caller: the volume arena, batch workspace,
  *    depth frames and extraction outputs are device pointers the caller
  *    allocated (with hipMalloc, or a framework's allocator) and keeps alive
- *    while work that uses them may still run.  The library allocates no device
+ *    while work that uses them may still run; depth frames may instead be
+ *    pinned host memory passed at its device address, which the kernels then
+ *    read over PCIe (tsdf_fuse_frame).  The library allocates no device
  *    memory at any time; it owns host handles, and a batch also owns a small
  *    pinned host staging ring, HIP events and HIP graphs (tsdf_batch_create).
  *  - `hip_stream` is a hipStream_t (NULL = the null stream).  All device work is
