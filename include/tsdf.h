@@ -508,10 +508,12 @@ tsdf_status tsdf_server_open(tsdf_server* server, const tsdf_volume_params* para
  * frames, and its memory returns to the budget. */
 tsdf_status tsdf_server_close(tsdf_server* server, uint32_t session);
 
-/* Queue one frame (depth_dev: height x width float32 on the device) for a
- * session.  Returns TSDF_ERR_BUDGET if the queue is full, and the session's
- * failure status (TSDF_ERR_POOL_EXHAUSTED, TSDF_ERR_TABLE_FULL,
- * TSDF_ERR_INTERNAL) once it has failed. */
+/* Queue one frame (depth_dev: height x width float32 in device memory, or in
+ * pinned host memory at its device address, as for tsdf_fuse_frame; it must
+ * stay valid until the frame completes) for a session.  Returns
+ * TSDF_ERR_BUDGET if the queue is full, and the session's failure status
+ * (TSDF_ERR_POOL_EXHAUSTED, TSDF_ERR_TABLE_FULL, TSDF_ERR_INTERNAL) once it
+ * has failed. */
 tsdf_status tsdf_server_submit(tsdf_server* server, uint32_t session, const float* depth_dev,
                                const tsdf_camera* camera, uint64_t tag);
 

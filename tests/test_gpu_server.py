@@ -92,6 +92,52 @@ def test_sessions_equal_fusing_alone(max_inflight, max_batch):
     log(f"  {len(w)} frames over {len(w.specs)} sessions")
 
 
+def test_sessions_served_from_pinned_host_frames():
+    """Frames in pinned host memory, submitted at their device addresses, are
+    read by the kernels over PCIe: every session ends as when its frames are
+    fused alone from device memory."""
+    import ctypes
+
+    w = S.ServingWorkload(8, rate=2000.0, duration_s=0.03, seed=24, sizes=SMALL,
+                          log2_pools=(15, 16))
+    depths, cams = frames_of(w)
+    hip = ctypes.CDLL("libamdhip64.so.7")
+    hip.hipHostGetDevicePointer.restype = ctypes.c_int
+    hip.hipHostGetDevicePointer.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p,
+                                            ctypes.c_uint]
+
+    class Mapped:  # a pinned frame known by its device address
+        def __init__(self, t):
+            self.host = torch.empty(t.shape, dtype=t.dtype, pin_memory=True)
+            self.host.copy_(t)
+            dp = ctypes.c_void_p()
+            assert hip.hipHostGetDevicePointer(ctypes.byref(dp), self.host.data_ptr(), 0) == 0
+            assert dp.value
+            self.addr = dp.value
+
+        def numel(self):
+            return self.host.numel()
+
+        def data_ptr(self):
+            return self.addr
+
+    pinned = [Mapped(d) for d in depths]
+    server = T.Server(budget_for(w), max_sessions=16, max_batch=8, max_inflight=2, max_queue=256)
+    ids = open_all(server, w)
+    for j, (s, c) in enumerate(zip(w.session_of, cams)):
+        assert server.submit(ids[int(s)], pinned[j], c, j) == T.OK
+        if j % 4 == 3:
+            server.step()
+    done = drain(server, len(w))
+    assert all(st == T.OK for st in done.values())
+    ref = alone(w, depths, cams)
+    for i in range(len(w.specs)):
+        v, fail = server.session(ids[i])
+        assert fail == T.OK
+        assert_same_volume(v, ref[i])
+    log(f"  {len(w)} pinned frames over {len(w.specs)} sessions")
+
+
 def test_served_sessions_match_the_oracle():
     w = S.ServingWorkload(4, rate=1000.0, duration_s=0.012, seed=22, sizes=((160, 120),),
                           log2_pools=(16, 16))
