@@ -72,6 +72,7 @@ constexpr unsigned kSetCap = 1024;          // LDS key-set slots per workgroup
 constexpr unsigned kSetNone = 0x7FFu;       // "no LDS slot" (set full)
 constexpr unsigned kAccBlocks = 8;          // phase-3 LDS region, in blocks' worth of floats
 constexpr int kProbeAhead = 4;              // table slots read per probe step
+constexpr int kProbeAheadLong = 8;          // ... per later step, for tables that can fill
 // A publication is one store after the winner's compare-exchange, so a wait is a
 // handful of steps.  A wait this long means the invariant broke: report it as
 // INTERNAL instead of spinning forever.
@@ -185,7 +186,7 @@ __device__ __forceinline__ void set_flag(DevCounters* c, unsigned f) {
 // at once; the winner still counts the block and lists it for extraction.
 // ---------------------------------------------------------------------------
 
-template <bool kInsert>
+template <bool kInsert, bool kLong = false>
 __device__ int resolve_key(const VolumeDev& vol, unsigned long long want, bool active,
                            unsigned& probes_out, bool& missing_out) {
   const unsigned C = vol.table_capacity;
@@ -207,16 +208,22 @@ __device__ int resolve_key(const VolumeDev& vol, unsigned long long want, bool a
         busy = false;
       }
     } else {
-      // Read kProbeAhead consecutive slots with plain, cacheable loads issued
-      // together (one memory latency per step instead of one per slot), then
-      // examine them in probe order.  A stale key costs one more step; a stale
-      // index only enters the wait.
-      unsigned sl[kProbeAhead];
-      TableEntry en[kProbeAhead];
+      // Read consecutive slots with plain, cacheable loads issued together (one
+      // memory latency per step instead of one per slot), then examine them in
+      // probe order.  A stale key costs one more step; a stale index only
+      // enters the wait.
+      // The first read takes kProbeAhead slots.  In a table that can fill
+      // (kLong), a chain that goes on past them takes kProbeAheadLong per read:
+      // fewer dependent reads on long chains, at the cost of registers.
+      constexpr int kMax = kLong ? kProbeAheadLong : kProbeAhead;
+      const unsigned n_read = (!kLong || probes == 0) ? (unsigned)kProbeAhead : (unsigned)kMax;
+      unsigned sl[kMax];
+      TableEntry en[kMax];
 #pragma unroll
-      for (int i = 0; i < kProbeAhead; ++i) {
+      for (int i = 0; i < kMax; ++i) {
         sl[i] = (i == 0) ? slot : ((sl[i - 1] + 1 == C) ? 0u : sl[i - 1] + 1);
-        en[i] = vol.table[sl[i]];
+        if ((unsigned)i < n_read) en[i] = vol.table[sl[i]];
+        else en[i] = TableEntry{0ull, 0, 0u};  // not read: never a candidate
       }
       // the first candidate in probe order (compile-time indices only, so the
       // read-ahead stays in registers)
@@ -225,8 +232,8 @@ __device__ int resolve_key(const VolumeDev& vol, unsigned long long want, bool a
       unsigned at_slot = 0;
       int at_block = 0;
 #pragma unroll
-      for (int i = kProbeAhead - 1; i >= 0; --i) {
-        const bool cand = (probes + (unsigned)i < C) &&
+      for (int i = kMax - 1; i >= 0; --i) {
+        const bool cand = (unsigned)i < n_read && (probes + (unsigned)i < C) &&
                           (en[i].key == want || en[i].key == kEmptyKey);
         if (cand) {
           at = i;
@@ -237,8 +244,9 @@ __device__ int resolve_key(const VolumeDev& vol, unsigned long long want, bool a
       }
       if (at < 0) {
         // none of them: move on (a full cyclic scan means the table is full)
-        probes += kProbeAhead;
-        slot = (sl[kProbeAhead - 1] + 1 == C) ? 0u : sl[kProbeAhead - 1] + 1;
+        probes += n_read;
+        const unsigned last = n_read == (unsigned)kProbeAhead ? sl[kProbeAhead - 1] : sl[kMax - 1];
+        slot = (last + 1 == C) ? 0u : last + 1;
         if (probes >= C) {
           result = kBlockTableFull;
           busy = false;
@@ -470,7 +478,8 @@ struct alignas(16) TileShared {
 // Frames with width 0 are empty.  Every thread of the workgroup must call it;
 // it begins with a workgroup barrier, so a persistent workgroup may call it
 // tile after tile.
-template <int K, int F, int AB, FuseMode kMode, bool kColour = false, bool kRowFlush = true>
+template <int K, int F, int AB, FuseMode kMode, bool kColour = false, bool kRowFlush = true,
+          bool kLong = false>
 __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams& wp,
                                           const FrameDev (&frs)[F], const unsigned (&px)[F],
                                           const unsigned (&py)[F], unsigned shard,
@@ -594,7 +603,7 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
     const unsigned long long key = act ? s_keys[h] : kEmptyKey;
     unsigned probes = 0;
     bool missing = false;
-    const int blk = resolve_key<kInsert>(vol, key, act, probes, missing);
+    const int blk = resolve_key<kInsert, kLong>(vol, key, act, probes, missing);
     if (act) {
       s_blockd[j] = blk;
       s_dense[h] = (unsigned short)j;
@@ -635,7 +644,7 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
         const Sample smp = walk_sample(fr, wp, d[fi], a, b, s - K);
         unsigned probes = 0;
         bool missing = false;
-        const int blk = resolve_key<kInsert>(
+        const int blk = resolve_key<kInsert, kLong>(
             vol, pack_key(smp.vx >> 3, smp.vy >> 3, smp.vz >> 3), true, probes, missing);
         my_missing += missing ? 1u : 0u;
         if (vol.probe_hist) count_probe(vol, probes);
@@ -927,7 +936,7 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
 constexpr int kColourAccBlocks = 4;
 constexpr int acc_blocks_for(bool colour) { return colour ? kColourAccBlocks : kAccBlocks; }
 
-template <int K, int F, int NB, FuseMode kMode, bool kColour>
+template <int K, int F, int NB, FuseMode kMode, bool kColour, bool kLong = false>
 __global__ __launch_bounds__(kThreads)
 __attribute__((amdgpu_waves_per_eu(waves_per_eu_for(F, kColour))))
 void fuse_kernel(FuseArgs<NB> args) {
@@ -955,7 +964,7 @@ void fuse_kernel(FuseArgs<NB> args) {
   }
   // several frames per workgroup: the trajectory launches that reach the
   // memory-side atomic ceiling flush in row-aligned windows
-  fuse_tile<K, F, AB, kMode, kColour, (F >= 2)>(A.vol, A.wp, frs, px, py, blockIdx.x, sh);
+  fuse_tile<K, F, AB, kMode, kColour, (F >= 2), kLong>(A.vol, A.wp, frs, px, py, blockIdx.x, sh);
 }
 
 // Many volumes, one frame each, in one persistent launch.  The grid is a
@@ -1042,6 +1051,14 @@ const void* multi_kernel_k(int pixels_per_thread, int acc_blocks, bool colour) {
 // (F x (2K+1) registers) in registers: 4 for bands of up to 9 samples, 2 above.
 constexpr int max_frames_for(int K) { return 2 * K + 1 <= 9 ? 4 : 2; }
 
+// The long probe read-ahead is for tables that can fill: a pool of at least
+// 80 % of the table.  Slot-index volumes keep the short read: their pool is the
+// table by construction, so the ratio says nothing of the load they reach.
+inline bool long_probe(const VolumeDev& vol) {
+  return !vol.slot_index &&
+         (unsigned long long)vol.pool_capacity * 5ull >= (unsigned long long)vol.table_capacity * 4ull;
+}
+
 template <int K, int F, int NB, bool kColour>
 hipError_t launch_fuse_kf(VolumeDev vol, const WalkParams& wp, const FrameDev* frames, int n,
                           FuseMode mode, bool remap, hipStream_t s) {
@@ -1066,25 +1083,42 @@ hipError_t launch_fuse_kf(VolumeDev vol, const WalkParams& wp, const FrameDev* f
   args.remap = remap ? 1 : 0;
   const unsigned groups = ((unsigned)n + F - 1) / F;
   const dim3 grid(n_tiles * groups), block(kThreads);
+  const bool lp = long_probe(vol);
   if constexpr (F == 1 && NB == 1) {
     switch (mode) {
       case FuseMode::kFused:
-        hipLaunchKernelGGL((fuse_kernel<K, 1, 1, FuseMode::kFused, kColour>), grid, block, 0, s,
-                           args);
+        if (lp)
+          hipLaunchKernelGGL((fuse_kernel<K, 1, 1, FuseMode::kFused, kColour, true>), grid, block,
+                             0, s, args);
+        else
+          hipLaunchKernelGGL((fuse_kernel<K, 1, 1, FuseMode::kFused, kColour, false>), grid,
+                             block, 0, s, args);
         break;
       case FuseMode::kAllocate:  // allocation touches no accumulator
-        hipLaunchKernelGGL((fuse_kernel<K, 1, 1, FuseMode::kAllocate, false>), grid, block, 0, s,
-                           args);
+        if (lp)
+          hipLaunchKernelGGL((fuse_kernel<K, 1, 1, FuseMode::kAllocate, false, true>), grid,
+                             block, 0, s, args);
+        else
+          hipLaunchKernelGGL((fuse_kernel<K, 1, 1, FuseMode::kAllocate, false, false>), grid,
+                             block, 0, s, args);
         break;
       case FuseMode::kIntegrate:
-        hipLaunchKernelGGL((fuse_kernel<K, 1, 1, FuseMode::kIntegrate, kColour>), grid, block, 0,
-                           s, args);
+        if (lp)
+          hipLaunchKernelGGL((fuse_kernel<K, 1, 1, FuseMode::kIntegrate, kColour, true>), grid,
+                             block, 0, s, args);
+        else
+          hipLaunchKernelGGL((fuse_kernel<K, 1, 1, FuseMode::kIntegrate, kColour, false>), grid,
+                             block, 0, s, args);
         break;
     }
   } else {
     (void)mode;
-    hipLaunchKernelGGL((fuse_kernel<K, F, NB, FuseMode::kFused, kColour>), grid, block, 0, s,
-                       args);
+    if (lp)
+      hipLaunchKernelGGL((fuse_kernel<K, F, NB, FuseMode::kFused, kColour, true>), grid, block, 0,
+                         s, args);
+    else
+      hipLaunchKernelGGL((fuse_kernel<K, F, NB, FuseMode::kFused, kColour, false>), grid, block, 0,
+                         s, args);
   }
   return hipGetLastError();
 }
