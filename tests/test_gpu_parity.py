@@ -221,11 +221,14 @@ def test_stress_plain_contention(stress_full):
     assert_parity(g, o)
 
 
-def test_stress_A_prefilled_to_095_drops_nothing(stress_full):
+@pytest.mark.parametrize("flags", [T.FUSE_DEFAULT, T.FUSE_TWO_PASS])
+def test_stress_A_prefilled_to_095_drops_nothing(stress_full, flags):
+    """The pool can fill the table here, so the launches take the long probe
+    read-ahead; the two-pass form runs its allocate and integrate stages."""
     w = S.plane_stress_workload("A", frames=STRESS_FRAMES)
     o = O.fuse_workload(w)
     assert o.stats["pairs_dropped"] == 0 and o.stats["pool_overflow_keys"] == 0
-    g = run_workload(w, keep_volume=True)
+    g = run_workload(w, flags=flags, keep_volume=True)
     assert_parity(g, o)
     assert g.stats.pairs_dropped == 0 and g.stats.status == T.OK
     assert_table_invariants(g.vol, o.keys, o.keys.size)
