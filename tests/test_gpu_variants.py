@@ -216,10 +216,12 @@ def test_colour_frames_batched_match_the_oracle(room, per_group):
     log(f"  {o.keys.size} blocks, colour sums exact")
 
 
-def test_colour_frames_mixed_sizes_and_invalid_pixels():
+@pytest.mark.parametrize("table", [1 << 15, 1 << 14])
+def test_colour_frames_mixed_sizes_and_invalid_pixels(table):
     """tsdf_fuse_frames_rgb over frames of ragged sizes (partial tiles, a 1x1
-    frame, a zero-width frame) with invalid depths, two per workgroup: keys,
-    weights and colour sums exactly the oracle's."""
+    frame, a zero-width frame) with invalid depths, two per workgroup, and the
+    same frames one by one: keys, weights and colour sums exactly the
+    oracle's.  A table as large as the pool takes the long probe read-ahead."""
     rng = np.random.default_rng(8)
     sizes = [(13, 9), (40, 23), (1, 1), (17, 33), (0, 4), (64, 48), (37, 5)]
     cams, depths, cols = [], [], []
@@ -242,13 +244,18 @@ def test_colour_frames_mixed_sizes_and_invalid_pixels():
     for d, c, cam in zip(depths, cols, cams):
         ov.fuse_rgb(d, c, cam)
     o = ov.result()
-    vol = T.Volume(0.01, 0.04, 1 << 15, 1 << 14, flags=T.VOLUME_COLOUR)
-    vol.fuse_frames_rgb([torch.from_numpy(d).cuda() for d in depths],
-                        [torch.from_numpy(c.view(np.int32)).cuda() for c in cols], cams)
-    assert_parity(result_of(vol), o)
-    keys, sums = gpu_colour_sums(vol, o.keys.size, False)
-    assert np.array_equal(keys, o.keys)
-    assert np.array_equal(sums, ov.colour_sums()), "colour sums differ"
+    dev = [torch.from_numpy(d).cuda() for d in depths]
+    col = [torch.from_numpy(c.view(np.int32)).cuda() for c in cols]
+    vol = T.Volume(0.01, 0.04, table, 1 << 14, flags=T.VOLUME_COLOUR)
+    vol.fuse_frames_rgb(dev, col, cams)
+    one = T.Volume(0.01, 0.04, table, 1 << 14, flags=T.VOLUME_COLOUR)
+    for d, c, cam in zip(dev, col, cams):
+        one.fuse_rgb(d, c, cam)
+    for v in (vol, one):
+        assert_parity(result_of(v), o)
+        keys, sums = gpu_colour_sums(v, o.keys.size, False)
+        assert np.array_equal(keys, o.keys)
+        assert np.array_equal(sums, ov.colour_sums()), "colour sums differ"
 
 
 @pytest.mark.parametrize("path", ["frames", "batch"])
