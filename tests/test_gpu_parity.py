@@ -477,10 +477,13 @@ def test_batched_wide_band():
     assert_parity(g, o)
 
 
-def test_batched_stress_prefilled(stress_full):
+@pytest.mark.parametrize("per_group", [1, 2, 4])
+def test_batched_stress_prefilled(stress_full, per_group):
+    """Batched launches on the long probe read-ahead (the pool can fill the
+    table), with 1, 2 and 4 frames per workgroup."""
     w = S.plane_stress_workload("A", frames=[0, 1, 2, 3])
     o = O.fuse_workload(w)
-    g = run_workload(w, batched=True, keep_volume=True)
+    g = run_workload(w, batched=True, keep_volume=True, flags=T.FUSE_BATCH(per_group))
     assert_parity(g, o)
     assert g.stats.pairs_dropped == 0
     assert_table_invariants(g.vol, o.keys, o.keys.size)
