@@ -60,6 +60,9 @@ typedef enum tsdf_status {
 #define TSDF_FLAG_TABLE_FULL 0x2u
 #define TSDF_FLAG_COORD_RANGE 0x4u
 #define TSDF_FLAG_INTERNAL 0x8u
+/* More distinct keys found the table full than the volume's record of them
+ * holds (TSDF_OVERFLOW_KEY_SLOTS): keys_table_overflow is then a lower bound. */
+#define TSDF_FLAG_OVERFLOW_RECORD_FULL 0x10u
 
 /* Block and table geometry (Section 2.1). */
 #define TSDF_BLOCK_EDGE 8u
@@ -67,10 +70,13 @@ typedef enum tsdf_status {
 #define TSDF_EMPTY_KEY 0xFFFFFFFFFFFFFFFFull /* never a packed key: those use 63 bits */
 #define TSDF_MAX_POOL_BLOCKS ((1u << 22) - 1u) /* keeps voxel indices below 2^31 */
 #define TSDF_MAX_BAND_HALF 8 /* round(trunc / voxel_size) must lie in [1, 8] */
+/* Distinct keys a volume can record as having found its table full (Sections
+ * 3.4 and 7.2: probe exhaustion is accounted, never silent). */
+#define TSDF_OVERFLOW_KEY_SLOTS 8192u
 
-/* Volume variants (tsdf_volume_params.flags), both from Section 6:
+/* Volume variants (tsdf_volume_params.flags), from Sections 6.4 and 2.1:
  *   TSDF_VOLUME_SLOT_INDEX  a block's pool index is its hash-table slot
- *       ("Deriving the location from the slot"): no pool counter to win and
+ *       (the location derived from the slot): no pool counter to win and
  *       no index to wait for, at the cost of a pool as large as the table.
  *       pool_capacity must equal the table capacity; table_capacity 0 means
  *       "equal to pool_capacity" here.  The pool cannot run out.
@@ -88,9 +94,10 @@ typedef enum tsdf_status {
 
 typedef struct tsdf_volume_params {
   float voxel_size;        /* voxel edge in metres, finite and > 0 */
-  float trunc;             /* truncation distance tau in metres, finite; the band
-                              walk takes 2K+1 samples, K = round(trunc/voxel_size),
-                              and K must lie in [1, TSDF_MAX_BAND_HALF] */
+  float trunc;             /* truncation distance tau in metres, finite and
+                              >= voxel_size; the band walk takes 2K+1 samples,
+                              K = round(trunc/voxel_size), and K must lie in
+                              [1, TSDF_MAX_BAND_HALF] */
   uint32_t table_capacity; /* hash-table slots C >= 1 (any value, not only powers
                               of two); 0 selects the paper's sizing, the next power
                               of two >= 2 * pool_capacity (Section 2.1) */
@@ -106,16 +113,25 @@ typedef struct tsdf_camera {
                               (R = pose[0..2], pose[4..6], pose[8..10]) */
 } tsdf_camera;
 
-/* Cumulative counters since tsdf_create_volume / tsdf_reset_volume. */
+/* Counters of a volume (Section 3.4: pool exhaustion reported; Section 7.2:
+ * probe exhaustion accounted).  Cumulative since tsdf_create_volume /
+ * tsdf_reset_volume, except blocks_new. */
 typedef struct tsdf_stats {
   uint64_t points_valid;       /* pixels with finite depth > 0 that were fused */
   uint64_t pairs;              /* (point, voxel) contributions that passed the walk */
   uint64_t pairs_dropped;      /* contributions lost to a full pool or table */
   uint64_t coord_out_of_range; /* band samples whose voxel cannot be keyed */
   uint32_t blocks_total;       /* allocated pool blocks, <= pool_capacity */
+  uint32_t blocks_new;         /* blocks allocated since the previous
+                                  tsdf_query_status of this volume (or since its
+                                  creation or reset) */
   uint32_t keys_pool_overflow; /* distinct keys that found the pool full */
-  uint32_t table_full_events;  /* failed insertions into a full table (one per
-                                  workgroup and key, so a key can count twice) */
+  uint32_t keys_table_overflow;/* distinct keys that found the table full (exact
+                                  up to TSDF_OVERFLOW_KEY_SLOTS; beyond that a
+                                  lower bound, flagged TSDF_FLAG_OVERFLOW_RECORD_FULL) */
+  uint32_t table_full_events;  /* failed resolutions against a full table (one per
+                                  workgroup tile and key, so a key can count more
+                                  than once) */
   uint32_t max_probe;          /* longest probe distance met (slots past home) */
   uint32_t lookup_misses;      /* two-pass mode: integrate found no key */
   uint32_t status_bits;        /* TSDF_FLAG_* */
@@ -128,6 +144,8 @@ typedef struct tsdf_stats {
  *   table      : table_capacity entries of 16 bytes: {uint64 key; int32 block;
  *                uint32 pad}, key TSDF_EMPTY_KEY when free; block >= 0 is a pool
  *                index, -1 = being published, -2 = the pool was full
+ *   overflow_keys : TSDF_OVERFLOW_KEY_SLOTS uint64, an open-addressed set of
+ *                the keys that found the table full (TSDF_EMPTY_KEY when free)
  *   block_keys : pool_capacity uint64, the key of the i-th allocated block
  *   alloc_list : (TSDF_VOLUME_SLOT_INDEX only) pool_capacity uint32, the pool
  *                index (= table slot) of the i-th allocated block; without the
@@ -146,7 +164,7 @@ typedef struct tsdf_stats {
  *                  red sum : colour[b * 1536 + r * 24 + lx], green + 8, blue + 16
  *                Regions a volume does not use have size 0. */
 typedef struct tsdf_layout {
-  uint64_t counters, table, block_keys, alloc_list, voxels, colour, total_bytes;
+  uint64_t counters, table, overflow_keys, block_keys, alloc_list, voxels, colour, total_bytes;
   uint32_t table_capacity, pool_capacity, flags, reserved;
 } tsdf_layout;
 
@@ -290,8 +308,8 @@ tsdf_status tsdf_extract_colour(tsdf_volume* vol, void* hip_stream, uint32_t max
 
 /* Surface extraction: the zero crossing of the mean TSDF as a triangle mesh,
  * by marching tetrahedra over the voxel centres (the extraction the paper
- * runs after fusion, Section 3, "What is excluded, and why"; Section 5,
- * "Correctness" checks its output).
+ * runs after fusion and leaves out of its timing, Section 2.4; Section 3.3
+ * checks its output).
  *   - Samples are voxel centres ((i + 1/2) * voxel_size per axis, metres) with
  *     value sum / weight.  A cube of 8 neighbouring centres is meshed only
  *     when all 8 voxels have a weight, and is skipped when it changes sign

@@ -12,7 +12,7 @@
 //     touches, apply the occlusion test, and make sure a block exists for the 8^3
 //     block holding each selected voxel.  Blocks come from a pool of fixed
 //     capacity; a block that does not fit is recorded as overflowed, never lost
-//     silently (Section 3, "Completeness": pool-exhaustion reporting).
+//     silently (Section 3.4: pool-exhaustion reporting).
 //   PASS 2 (update): walk the same band again and add, for each selected voxel,
 //     the truncated signed distance to its block's running *sum* and 1 to its
 //     weight.  Means are recovered only at extraction (Section 2.2).
@@ -250,9 +250,8 @@ uint32_t home_slot(uint64_t key, uint32_t C) {
 // Surface extraction: marching tetrahedra over the voxel centres.
 //
 // The paper extracts the zero crossing of the fused field with marching
-// tetrahedra (Section 3, "What is excluded, and why") and checks the result on
-// a sphere of known radius and by vertex distances between runs (Section 5,
-// "Correctness").  It does not spell the method out; the readings:
+// tetrahedra (Section 2.4) and checks the result on a sphere of known radius
+// and by vertex distances between runs (Section 3.3).  It does not spell the method out; the readings:
 //   - samples are voxel centres ((i + 1/2) v per axis), values the mean TSDF
 //     sum / weight;
 //   - a cube of 8 neighbouring centres is used only when all 8 voxels have a

@@ -25,7 +25,8 @@ uint32_t next_pow2_at_least(uint64_t x) {
 bool make_layout(const tsdf_volume_params* p, tsdf_layout* out) {
   if (!p) return false;
   if (!finite(p->voxel_size) || !(p->voxel_size > 0.0f)) return false;
-  if (!finite(p->trunc) || !(p->trunc > 0.0f)) return false;
+  // Section 2.2: the band reaches at least one voxel either side of the surface
+  if (!finite(p->trunc) || !(p->trunc >= p->voxel_size)) return false;
   const int K = band_half(*p);
   if (K < 1 || K > TSDF_MAX_BAND_HALF) return false;
   if (p->pool_capacity < 1 || p->pool_capacity > TSDF_MAX_POOL_BLOCKS) return false;
@@ -45,6 +46,8 @@ bool make_layout(const tsdf_volume_params* p, tsdf_layout* out) {
   off = align_up(off + tsdf::kCountersBytes);
   L.table = off;
   off = align_up(off + (uint64_t)C * sizeof(tsdf::TableEntry));
+  L.overflow_keys = off;
+  off = align_up(off + (uint64_t)TSDF_OVERFLOW_KEY_SLOTS * 8ull);
   L.block_keys = off;
   off = align_up(off + P * 8ull);
   L.alloc_list = off;
@@ -65,6 +68,8 @@ tsdf_status init_table_and_counters(tsdf_volume* v, hipStream_t s) {
   const tsdf_layout& L = v->layout;
   hipError_t e = tsdf::launch_fill_u32(v->dev.table, 0xFFFFFFFFu,
                                         (size_t)L.table_capacity * (sizeof(tsdf::TableEntry) / 4), s);
+  if (e == hipSuccess)
+    e = tsdf::launch_fill_u32(v->dev.overflow_keys, 0xFFFFFFFFu, TSDF_OVERFLOW_KEY_SLOTS * 2ull, s);
   if (e == hipSuccess) e = tsdf::launch_fill_u32(v->dev.ctr, 0u, tsdf::kCountersBytes / 4, s);
   return hip_status(e);
 }
@@ -96,9 +101,12 @@ tsdf_status tsdf_create_volume(const tsdf_volume_params* params, void* dev_arena
   v->params = *params;
   v->layout = L;
   v->frames = 0;
+  v->blocks_seen = 0;
   char* base = static_cast<char*>(dev_arena);
   v->dev.ctr = reinterpret_cast<tsdf::DevCounters*>(base + L.counters);
   v->dev.table = reinterpret_cast<tsdf::TableEntry*>(base + L.table);
+  v->dev.overflow_keys = reinterpret_cast<unsigned long long*>(base + L.overflow_keys);
+  v->dev.pad[0] = v->dev.pad[1] = 0u;
   v->dev.block_keys = reinterpret_cast<unsigned long long*>(base + L.block_keys);
   v->dev.voxels = reinterpret_cast<float*>(base + L.voxels);
   const bool slot_index = (L.flags & TSDF_VOLUME_SLOT_INDEX) != 0;
@@ -140,7 +148,10 @@ tsdf_status tsdf_reset_volume(tsdf_volume* vol, void* hip_stream) {
   // are zeroed (same stream, in order)
   tsdf_status st = hip_status(tsdf::launch_reset_used(vol->dev, s));
   if (st == TSDF_OK) st = init_table_and_counters(vol, s);
-  if (st == TSDF_OK) vol->frames = 0;
+  if (st == TSDF_OK) {
+    vol->frames = 0;
+    vol->blocks_seen = 0;
+  }
   return st;
 }
 
@@ -284,7 +295,10 @@ tsdf_status tsdf_query_status(tsdf_volume* vol, void* hip_stream, tsdf_stats* ou
     out->coord_out_of_range = c.coord_out_of_range;
     out->blocks_total = c.block_count < vol->layout.pool_capacity ? c.block_count
                                                                   : vol->layout.pool_capacity;
+    out->blocks_new = out->blocks_total - vol->blocks_seen;
+    vol->blocks_seen = out->blocks_total;
     out->keys_pool_overflow = c.keys_pool_overflow;
+    out->keys_table_overflow = c.keys_table_overflow;
     out->table_full_events = c.table_full_events;
     out->max_probe = c.max_probe;
     out->lookup_misses = c.lookup_misses;

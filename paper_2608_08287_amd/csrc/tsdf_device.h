@@ -177,11 +177,29 @@ __device__ __forceinline__ void set_flag(DevCounters* c, unsigned f) {
   __hip_atomic_fetch_or(&c->status_bits, f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// A key that found the table full (Section 7.2: probe exhaustion is accounted,
+// never silent) enters the volume's overflow set once, so that the count of
+// such keys is exact however many tiles, frames and launches meet the key.
+// A full overflow set is itself flagged: the count is then a lower bound.
+__device__ void record_table_overflow(const VolumeDev& vol, unsigned long long key) {
+  unsigned h = home_slot(key, TSDF_OVERFLOW_KEY_SLOTS);
+  for (unsigned i = 0; i < TSDF_OVERFLOW_KEY_SLOTS; ++i) {
+    const unsigned long long prev = cas_key(&vol.overflow_keys[h], kEmptyKey, key);
+    if (prev == kEmptyKey) {
+      add_u32(&vol.ctr->keys_table_overflow, 1u);
+      return;
+    }
+    if (prev == key) return;
+    h = (h + 1 == TSDF_OVERFLOW_KEY_SLOTS) ? 0u : h + 1;
+  }
+  set_flag(vol.ctr, TSDF_FLAG_OVERFLOW_RECORD_FULL);
+}
+
 // ---------------------------------------------------------------------------
 // Section 2.3: find or insert one key.  Converged step loop over the busy lanes.
 // Returns the pool index, kBlockPoolFull, kBlockTableFull, or (lookup only)
-// kBlockTableFull for a key that is absent.  In a slot-index volume (Section 6,
-// "Deriving the location from the slot") the pool index is the slot where the
+// kBlockTableFull for a key that is absent.  In a slot-index volume (Section 6.4,
+// the block index derived from the slot) the pool index is the slot where the
 // key sits, so a lane that finds its key, or loses the exchange to it, is done
 // at once; the winner still counts the block and lists it for extraction.
 // ---------------------------------------------------------------------------
@@ -324,6 +342,7 @@ __device__ int resolve_key(const VolumeDev& vol, unsigned long long want, bool a
   } else if (active && result == kBlockTableFull && !missing) {
     add_u32(&vol.ctr->table_full_events, 1u);
     set_flag(vol.ctr, TSDF_FLAG_TABLE_FULL);
+    record_table_overflow(vol, want);
   }
   probes_out = probes;
   missing_out = missing;

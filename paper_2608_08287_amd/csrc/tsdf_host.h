@@ -17,6 +17,7 @@ struct tsdf_volume {
   tsdf_layout layout;
   tsdf::VolumeDev dev;
   uint32_t frames;
+  uint32_t blocks_seen;  // blocks_total at the previous tsdf_query_status
 };
 
 namespace tsdf_host {

@@ -37,7 +37,8 @@ struct DevCounters {
   unsigned max_probe;
   unsigned lookup_misses;
   unsigned mesh_triangles;      // surface extraction: triangles found
-  unsigned pad0[25];
+  unsigned keys_table_overflow; // distinct keys recorded in the overflow set
+  unsigned pad0[24];
   // line 1: losses
   unsigned long long pairs_dropped;
   unsigned long long coord_out_of_range;
@@ -77,6 +78,7 @@ __host__ __device__ constexpr unsigned colour_index(unsigned loc, unsigned chann
 struct VolumeDev {
   DevCounters* ctr;
   TableEntry* table;
+  unsigned long long* overflow_keys;  // TSDF_OVERFLOW_KEY_SLOTS keys that found the table full
   unsigned long long* block_keys;  // key of the i-th allocated block
   float* voxels;                   // pool_capacity * kBlockFloats
   unsigned* alloc_list;            // slot-index volumes: pool index of the i-th allocated block
@@ -85,7 +87,9 @@ struct VolumeDev {
   unsigned pool_capacity;
   unsigned slot_index;             // 1: a block's pool index is its table slot
   unsigned probe_hist;             // 1: count resolutions by probe distance
+  unsigned pad[2];                 // keeps the struct a whole number of 16-byte units
 };
+static_assert(sizeof(VolumeDev) % 16 == 0, "volume descriptors stay 16-byte aligned");
 
 // Pool index of the i-th allocated block.
 __host__ __device__ inline unsigned allocated_block(const VolumeDev& vol, unsigned i) {

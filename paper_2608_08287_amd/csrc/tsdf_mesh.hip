@@ -1,6 +1,6 @@
 // Surface extraction: marching tetrahedra over the voxel centres of every
-// allocated block (the extraction the paper runs after fusion, Section 3,
-// "What is excluded, and why"; its checks are in Section 5, "Correctness").
+// allocated block (the extraction the paper runs after fusion and leaves out
+// of its timing, Section 2.4; its checks are those of Section 3.3).
 //
 // One workgroup per pool block.  The block's 8^3 voxels and the one-voxel
 // skirt of its +x, +y, +z neighbours (found by lookups in the hash table) are

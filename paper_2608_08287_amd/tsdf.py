@@ -23,6 +23,8 @@ LIB_PATH = os.path.join(_HERE, "libtsdf.so")
 OK, ERR_INVALID_ARGUMENT, ERR_BUFFER_TOO_SMALL, ERR_POOL_EXHAUSTED, ERR_TABLE_FULL, \
     ERR_COORD_RANGE, ERR_INTERNAL, ERR_HIP, ERR_BUDGET = range(9)
 FLAG_POOL_EXHAUSTED, FLAG_TABLE_FULL, FLAG_COORD_RANGE, FLAG_INTERNAL = 1, 2, 4, 8
+FLAG_OVERFLOW_RECORD_FULL = 0x10
+OVERFLOW_KEY_SLOTS = 8192
 FUSE_DEFAULT, FUSE_TWO_PASS, FUSE_ALLOCATE_ONLY, FUSE_INTEGRATE_ONLY = 0, 1, 2, 3
 FUSE_XCD_REMAP = 0x100
 VOLUME_SLOT_INDEX, VOLUME_COLOUR, VOLUME_PROBE_HISTOGRAM = 0x1, 0x2, 0x4
@@ -72,14 +74,16 @@ class CameraC(C.Structure):
 class StatsC(C.Structure):
     _fields_ = [("points_valid", C.c_uint64), ("pairs", C.c_uint64),
                 ("pairs_dropped", C.c_uint64), ("coord_out_of_range", C.c_uint64),
-                ("blocks_total", C.c_uint32), ("keys_pool_overflow", C.c_uint32),
+                ("blocks_total", C.c_uint32), ("blocks_new", C.c_uint32),
+                ("keys_pool_overflow", C.c_uint32), ("keys_table_overflow", C.c_uint32),
                 ("table_full_events", C.c_uint32), ("max_probe", C.c_uint32),
                 ("lookup_misses", C.c_uint32), ("status_bits", C.c_uint32),
                 ("frames", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class LayoutC(C.Structure):
-    _fields_ = [("counters", C.c_uint64), ("table", C.c_uint64), ("block_keys", C.c_uint64),
+    _fields_ = [("counters", C.c_uint64), ("table", C.c_uint64), ("overflow_keys", C.c_uint64),
+                ("block_keys", C.c_uint64),
                 ("alloc_list", C.c_uint64), ("voxels", C.c_uint64), ("colour", C.c_uint64),
                 ("total_bytes", C.c_uint64), ("table_capacity", C.c_uint32),
                 ("pool_capacity", C.c_uint32), ("flags", C.c_uint32), ("reserved", C.c_uint32)]
@@ -269,7 +273,9 @@ class Stats:
     pairs_dropped: int
     coord_out_of_range: int
     blocks_total: int
+    blocks_new: int           # since the previous stats() of this volume
     keys_pool_overflow: int
+    keys_table_overflow: int  # distinct keys that found the table full
     table_full_events: int
     max_probe: int
     lookup_misses: int
@@ -295,8 +301,9 @@ class _VolumeCalls:
         if st == ERR_HIP or st == ERR_INVALID_ARGUMENT:
             raise TsdfError(st, "tsdf_query_status")
         return Stats(s.points_valid, s.pairs, s.pairs_dropped, s.coord_out_of_range, s.blocks_total,
-                     s.keys_pool_overflow, s.table_full_events, s.max_probe, s.lookup_misses,
-                     s.status_bits, s.frames, st)
+                     s.blocks_new, s.keys_pool_overflow, s.keys_table_overflow,
+                     s.table_full_events, s.max_probe, s.lookup_misses, s.status_bits, s.frames,
+                     st)
 
     def probe_histogram(self, stream=None) -> Tuple[np.ndarray, int]:
         """(resolutions by probe distance, bin 0: distance 0, bin b:

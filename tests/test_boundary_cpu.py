@@ -3,6 +3,7 @@ its host-side argument checks reject bad input before anything is enqueued."""
 import ctypes as C
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -30,9 +31,10 @@ def test_volume_bytes_and_layout():
     L = T.layout(p)
     assert L.table_capacity == 8192 and L.pool_capacity == 4096
     assert L.counters == 0
-    for off in (L.table, L.block_keys, L.voxels, L.total_bytes):
+    for off in (L.table, L.overflow_keys, L.block_keys, L.voxels, L.total_bytes):
         assert off % 256 == 0
-    assert L.block_keys - L.table >= 8192 * 16
+    assert L.overflow_keys - L.table >= 8192 * 16
+    assert L.block_keys - L.overflow_keys >= T.OVERFLOW_KEY_SLOTS * 8
     assert L.voxels - L.block_keys >= 4096 * 8
     assert L.total_bytes - L.voxels == 4096 * 1024 * 4
     assert T.volume_bytes(p) == L.total_bytes
@@ -73,6 +75,8 @@ def test_variant_layouts():
     (0.0, 0.04, 8192, 4096), (-0.01, 0.04, 8192, 4096), (float("nan"), 0.04, 8192, 4096),
     (float("inf"), 0.04, 8192, 4096), (0.01, 0.0, 8192, 4096), (0.01, 0.001, 8192, 4096),
     (0.01, 0.2, 8192, 4096), (0.01, float("nan"), 8192, 4096), (0.01, 0.04, 8192, 0),
+    # trunc below one voxel (K = round(0.6) = 1 would still be a valid band)
+    (0.01, 0.006, 8192, 4096), (0.01, 0.0099, 8192, 4096),
     (0.01, 0.04, 8192, 1 << 22), (0.01, 0.04, 0, 0x7FFFFFFF),
 ])
 def test_invalid_volume_params(vs, tr, C_, P):
@@ -169,3 +173,34 @@ def test_batch_rejects_bad_arguments_before_any_device_work():
     assert L.tsdf_batch_fuse(None, None, 0, 0, None) == T.ERR_INVALID_ARGUMENT
     n = C.c_uint32()
     assert L.tsdf_batch_candidates(None, 0, None, None, C.byref(n)) == T.ERR_INVALID_ARGUMENT
+
+
+def _c_offsets(struct: str, fields) -> dict:
+    """Byte offsets and size of a C struct of include/tsdf.h, as gcc lays it out."""
+    import tempfile
+    body = "".join(f'printf("%zu ", offsetof({struct}, {f}));' for f in fields)
+    src = ("#include <stdio.h>\n#include <stddef.h>\n#include \"tsdf.h\"\n"
+           f"int main(void) {{ {body} printf(\"%zu\\n\", sizeof({struct})); return 0; }}\n")
+    with tempfile.TemporaryDirectory() as d:
+        c_path, exe = os.path.join(d, "t.c"), os.path.join(d, "t")
+        open(c_path, "w").write(src)
+        subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), c_path, "-o", exe],
+                       check=True)
+        vals = [int(x) for x in subprocess.run([exe], check=True, capture_output=True,
+                                               text=True).stdout.split()]
+    return dict(zip(list(fields) + ["sizeof"], vals))
+
+
+@pytest.mark.parametrize("struct,mirror", [("tsdf_stats", "StatsC"), ("tsdf_layout", "LayoutC"),
+                                           ("tsdf_volume_params", "VolumeParams"),
+                                           ("tsdf_camera", "CameraC")])
+def test_binding_structs_match_the_header(struct, mirror):
+    """Every ctypes mirror has the C struct's fields at the C struct's offsets."""
+    cls = getattr(T, mirror)
+    names = [f[0] for f in cls._fields_]
+    c = _c_offsets(struct, names)
+    for n in names:
+        assert getattr(cls, n).offset == c[n], (struct, n)
+    assert C.sizeof(cls) == c["sizeof"]
+    if struct == "tsdf_stats":
+        assert {"blocks_new", "keys_table_overflow", "keys_pool_overflow"} <= set(names)

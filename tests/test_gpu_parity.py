@@ -307,7 +307,35 @@ def test_stress_C_table_full_is_reported(stress_full):
     assert scene_in.size == 50
     assert g.stats.blocks_total == pre.size + 50
     _check_subset(g, full1, np.sort(scene_in))
-    assert g.stats.table_full_events >= full1.keys.size - 50
+    # every key that found the table full is counted once: the linear-probe
+    # model's overflow over the pre-fill and the scene's keys
+    model = O.probe_model(np.concatenate([pre, full1.keys]), w.table_capacity)
+    assert model.n_overflow == full1.keys.size - 50
+    assert g.stats.keys_table_overflow == model.n_overflow
+    assert g.stats.table_full_events >= g.stats.keys_table_overflow
+    assert not (g.stats.status_bits & T.FLAG_OVERFLOW_RECORD_FULL)
+    # the same frame again: its failing keys fail again but are not new
+    events = g.stats.table_full_events
+    g.vol.fuse(torch.from_numpy(w.depth[0]).cuda(), w.cameras[0])
+    again = g.vol.stats()
+    assert again.keys_table_overflow == model.n_overflow
+    assert again.table_full_events > events and again.blocks_new == 0
+
+
+def test_blocks_new_counts_since_the_previous_query(room):
+    w, _ = room
+    o0 = O.fuse_frames(w.voxel_size, w.trunc, w.pool_capacity, w.depth[:1], w.cameras[:1])
+    o01 = O.fuse_frames(w.voxel_size, w.trunc, w.pool_capacity, w.depth[:2], w.cameras[:2])
+    vol = T.Volume(w.voxel_size, w.trunc, w.table_capacity, w.pool_capacity)
+    vol.fuse(torch.from_numpy(w.depth[0]).cuda(), w.cameras[0])
+    st = vol.stats()
+    assert st.blocks_new == st.blocks_total == o0.keys.size
+    assert vol.stats().blocks_new == 0
+    vol.fuse(torch.from_numpy(w.depth[1]).cuda(), w.cameras[1])
+    st = vol.stats()
+    assert st.blocks_total == o01.keys.size and st.blocks_new == o01.keys.size - o0.keys.size
+    vol.reset()
+    assert vol.stats().blocks_new == 0
 
 
 # ---------------------------------------------------------------------------

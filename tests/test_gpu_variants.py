@@ -1,6 +1,6 @@
-"""GPU parity of the paper's two design variants (Section 6): the slot-derived
-block index (a block's pool index is its table slot) and colour accumulation
-(three more sums per voxel).  Both against the oracle: keys and weights exact,
+"""GPU parity of the paper's two design variants: the slot-derived
+block index (Section 6.4) (a block's pool index is its table slot) and colour accumulation
+(three more sums per voxel, Section 2.1).  Both against the oracle: keys and weights exact,
 TSDF means within 1e-5, colour sums exact (sums of 8-bit integers stay exact
 in float32), and the table and allocation invariants of the slot index.
 Every case prints its name first."""
@@ -134,6 +134,8 @@ def test_slot_index_table_full_is_reported():
     st = vol.stats()
     assert st.status == T.ERR_TABLE_FULL and st.blocks_total == 256
     assert st.pairs_dropped > 0 and st.keys_pool_overflow == 0
+    keys = O.fuse_workload(w).keys  # every distinct key of the frame
+    assert st.keys_table_overflow == O.probe_model(keys, 256).n_overflow == keys.size - 256
 
 
 # ---------------------------------------------------------------------------
