@@ -400,7 +400,10 @@ typedef struct tsdf_batch_config {
 } tsdf_batch_config;
 
 /* Device workspace bytes for batches of up to `max_items` items (0 if
- * max_items is 0 or above TSDF_BATCH_MAX_ITEMS). */
+ * max_items is 0 or above TSDF_BATCH_MAX_ITEMS).  The workspace holds eight
+ * work lists, one per slot of the batch's staging ring, so that calls from
+ * several streams may overlap: a slot's list is rewritten only behind the
+ * launches that last read it (a device-side wait on their event). */
 #define TSDF_BATCH_MAX_ITEMS 65536u
 size_t tsdf_batch_workspace_bytes(uint32_t max_items);
 
@@ -436,8 +439,10 @@ tsdf_status tsdf_batch_candidates(tsdf_batch* batch, uint32_t max, tsdf_batch_co
 /* Fuse items[i].depth_dev into items[i].volume for i < n_items (n_items <= the
  * batch's max_items): copies the work list to the workspace (a small
  * host-to-device copy from the staging ring) and launches, both on
- * `hip_stream`.  Asynchronous.  Volumes of a call must not be used on another
- * stream until it has run.
+ * `hip_stream`.  Asynchronous.  Calls may come from several streams (each
+ * call uses its own work-list slot); a volume may appear in calls on several
+ * streams at once, whose launches then fuse into it concurrently (the result
+ * is the same, up to float summation order).
  *   flags  TSDF_BATCH_NO_GRAPH: launch directly even once the configuration is
  *          fixed (by default a fixed configuration replays a HIP graph). */
 #define TSDF_BATCH_NO_GRAPH 0x1u

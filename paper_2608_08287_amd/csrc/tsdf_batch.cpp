@@ -4,12 +4,15 @@
 // Per call: the items are sorted by band half-width K (counting sort, stable),
 // each item's tile count is taken for the configuration's tile width, and the
 // work list (K ranges, tile prefix sums, item descriptors) is written into one
-// slot of a pinned host ring and copied to the device workspace on the
-// caller's stream.  Then one persistent kernel per K present runs over the
-// list.  The ring slot is reused only after the event recorded behind its copy
-// has completed, so the host never overwrites a list the copy engine has not
-// read yet; the device workspace has a single copy because every use of it is
-// ordered on the stream behind the copy that filled it.
+// slot of a pinned host ring and copied, on the caller's stream, to the same
+// slot of the device workspace, which holds one work list per ring slot.  Then
+// one persistent kernel per K present runs over the list.
+//
+// Reuse of a slot is ordered, so calls may come from several streams:
+//   - the host rewrites a ring slot only after the event behind its last copy
+//     has completed (the copy engine has read it);
+//   - the copy into a device slot waits (on the device) for the event behind
+//     the launches that last read that slot, whatever stream they ran on.
 
 #include <algorithm>
 #include <cstdlib>
@@ -23,8 +26,8 @@ using namespace tsdf_host;
 
 namespace {
 
-constexpr int kRingSlots = 4;
-constexpr int kMaxGraphs = 4;
+constexpr int kRingSlots = 8;
+constexpr int kMaxGraphs = 32;
 constexpr uint64_t kHeaderBytes = 256;  // k_begin[kBatchGroups], padded
 static_assert(4 * (tsdf::kBatchGroups + 1) <= kHeaderBytes, "group ranges fit the header");
 constexpr int kAccChoices[2] = {4, 8};
@@ -71,6 +74,7 @@ struct Timing {
 
 struct GraphEntry {
   uint32_t k_mask;
+  int slot;  // the device work list its kernel nodes read
   tsdf_batch_config cfg;
   hipGraph_t graph;
   hipGraphExec_t exec;
@@ -87,10 +91,12 @@ struct tsdf_batch {
   // resident workgroups per CU by [K][pixels per thread - 1][acc index][colour];
   // 0 = not yet asked
   int occupancy[TSDF_MAX_BAND_HALF + 1][kMaxPixelsPerThread][2][2];
-  // staging ring
+  // staging ring and the device work lists, one per slot
   char* ring;
-  hipEvent_t ring_done[kRingSlots];
+  hipEvent_t ring_done[kRingSlots];  // behind the copy out of the ring slot
   bool ring_pending[kRingSlots];
+  hipEvent_t slot_done[kRingSlots];  // behind the launches that read the device slot
+  bool slot_used[kRingSlots];
   int next_slot;
   // configuration and tuner
   tsdf_batch_config cfg;
@@ -212,17 +218,21 @@ tsdf_batch_config next_config(tsdf_batch* b, int* cand) {
   return std::isfinite(b->best[arg]) ? b->cands[arg] : b->cands[0];
 }
 
-tsdf::BatchWork device_work(const tsdf_batch* b) {
+// The work list at `list` (a device slot of the workspace, or other device
+// memory laid out the same way).
+tsdf::BatchWork device_work(const tsdf_batch* b, const char* list) {
   tsdf::BatchWork w;
-  w.k_begin = reinterpret_cast<const unsigned*>(b->ws);
-  w.tile_start = reinterpret_cast<const unsigned*>(b->ws + b->L.tile_start);
-  w.items = reinterpret_cast<const tsdf::BatchItem*>(b->ws + b->L.items);
+  w.k_begin = reinterpret_cast<const unsigned*>(list);
+  w.tile_start = reinterpret_cast<const unsigned*>(list + b->L.tile_start);
+  w.items = reinterpret_cast<const tsdf::BatchItem*>(list + b->L.items);
   return w;
 }
 
-hipError_t launch_direct(tsdf_batch* b, uint32_t g_mask, const tsdf_batch_config& c,
-                         const uint32_t* g_tiles, hipStream_t s) {
-  tsdf::BatchWork w = device_work(b);
+const char* slot_list(const tsdf_batch* b, int slot) { return b->ws + (size_t)slot * b->L.total; }
+
+hipError_t launch_direct(tsdf_batch* b, const char* list, uint32_t g_mask,
+                         const tsdf_batch_config& c, const uint32_t* g_tiles, hipStream_t s) {
+  tsdf::BatchWork w = device_work(b, list);
   unsigned tw_log2 = log2_u32(c.tile_width);
   void* args[] = {&w, &tw_log2};
   for (int g = 0; g < tsdf::kBatchGroups; ++g) {
@@ -243,13 +253,13 @@ void destroy_graph(GraphEntry& g) {
 }
 
 // The instantiated graph of one kernel node per group in k_mask (band width
-// and colour) for configuration c (no memory nodes: the work list arrives by
-// the copy before the launch).
-hipError_t graph_for(tsdf_batch* b, uint32_t k_mask, const tsdf_batch_config& c, hipStream_t s,
+// and colour) for configuration c reading the work list of device slot `slot`
+// (no memory nodes: the work list arrives by the copy before the launch).
+hipError_t graph_for(tsdf_batch* b, uint32_t k_mask, int slot, const tsdf_batch_config& c,
                      hipGraphExec_t* out) {
   for (int i = 0; i < b->n_graphs; ++i) {
     GraphEntry& g = b->graphs[i];
-    if (g.k_mask == k_mask && same_config(g.cfg, c)) {
+    if (g.k_mask == k_mask && g.slot == slot && same_config(g.cfg, c)) {
       g.last_use = b->calls;
       *out = g.exec;
       return hipSuccess;
@@ -258,7 +268,7 @@ hipError_t graph_for(tsdf_batch* b, uint32_t k_mask, const tsdf_batch_config& c,
   hipGraph_t graph = nullptr;
   hipError_t e = hipGraphCreate(&graph, 0);
   if (e != hipSuccess) return e;
-  tsdf::BatchWork w = device_work(b);
+  tsdf::BatchWork w = device_work(b, slot_list(b, slot));
   unsigned tw_log2 = log2_u32(c.tile_width);
   void* args[] = {&w, &tw_log2};
   for (int g = 0; g < tsdf::kBatchGroups && e == hipSuccess; ++g) {
@@ -281,23 +291,25 @@ hipError_t graph_for(tsdf_batch* b, uint32_t k_mask, const tsdf_batch_config& c,
     (void)hipGraphDestroy(graph);
     return e;
   }
-  int slot = b->n_graphs;
-  if (slot == kMaxGraphs) {
-    // evict the least recently used; its last replay may still be queued
-    slot = 0;
+  int at = b->n_graphs;
+  if (at == kMaxGraphs) {
+    // evict the least recently used; its last replay may still be queued, on
+    // any stream, and is done once the event behind its slot's last use is
+    at = 0;
     for (int i = 1; i < kMaxGraphs; ++i)
-      if (b->graphs[i].last_use < b->graphs[slot].last_use) slot = i;
-    e = hipStreamSynchronize(s);
+      if (b->graphs[i].last_use < b->graphs[at].last_use) at = i;
+    const int vs = b->graphs[at].slot;
+    e = b->slot_used[vs] ? hipEventSynchronize(b->slot_done[vs]) : hipSuccess;
     if (e != hipSuccess) {
       (void)hipGraphExecDestroy(exec);
       (void)hipGraphDestroy(graph);
       return e;
     }
-    destroy_graph(b->graphs[slot]);
+    destroy_graph(b->graphs[at]);
   } else {
     ++b->n_graphs;
   }
-  b->graphs[slot] = GraphEntry{k_mask, c, graph, exec, b->calls};
+  b->graphs[at] = GraphEntry{k_mask, slot, c, graph, exec, b->calls};
   *out = exec;
   return hipSuccess;
 }
@@ -307,6 +319,10 @@ void free_batch(tsdf_batch* b) {
     if (b->ring_done[i]) {
       (void)hipEventSynchronize(b->ring_done[i]);
       (void)hipEventDestroy(b->ring_done[i]);
+    }
+    if (b->slot_done[i]) {
+      (void)hipEventSynchronize(b->slot_done[i]);
+      (void)hipEventDestroy(b->slot_done[i]);
     }
   }
   release_timings(b);
@@ -319,13 +335,145 @@ void free_batch(tsdf_batch* b) {
   delete b;
 }
 
+bool valid_items(const tsdf_fuse_item* items, uint32_t n_items) {
+  for (uint32_t i = 0; i < n_items; ++i) {
+    const tsdf_fuse_item& it = items[i];
+    if (!it.volume || !valid_camera(&it.camera)) return false;
+    const bool pixels = (uint64_t)it.camera.width * it.camera.height > 0;
+    if (pixels && !it.depth_dev) return false;
+    if (pixels && it.volume->dev.colour && !it.rgba_dev) return false;
+  }
+  return true;
+}
+
+// One call of the batch path.  The work list goes to device slot `slot` of
+// the workspace, or, if `list_dev` is not null, to that device memory (whose
+// uses the caller orders); then the launches.  With `list_dev` the call is
+// launched directly, never timed for the tuner nor replayed from a graph.
+tsdf_status batch_fuse_impl(tsdf_batch* b, const tsdf_fuse_item* items, uint32_t n_items,
+                            uint32_t flags, char* list_dev, hipStream_t s) {
+  if (!valid_items(items, n_items)) return TSDF_ERR_INVALID_ARGUMENT;
+  if (n_items == 0) return TSDF_OK;
+  poll_tuner(b);
+  int cand = -1;
+  const tsdf_batch_config c = next_config(b, &cand);
+  if (list_dev) cand = -1;  // not a tuning trial
+  const uint32_t tw = c.tile_width;
+
+  // the ring slot: wait until the copy that last read it has run
+  const int slot = b->next_slot;
+  b->next_slot = (slot + 1) % kRingSlots;
+  if (b->ring_pending[slot] && hipEventSynchronize(b->ring_done[slot]) != hipSuccess)
+    return TSDF_ERR_HIP;
+  b->ring_pending[slot] = false;
+  char* host = b->ring + (size_t)slot * b->L.total;
+  unsigned* k_begin = reinterpret_cast<unsigned*>(host);
+  unsigned* tile_start = reinterpret_cast<unsigned*>(host + b->L.tile_start);
+  tsdf::BatchItem* out = reinterpret_cast<tsdf::BatchItem*>(host + b->L.items);
+
+  // counting sort by group (band width, colour)
+  auto group_of = [](const tsdf_fuse_item& it) {
+    return tsdf::batch_group(band_half(it.volume->params), it.volume->dev.colour != nullptr);
+  };
+  uint32_t count[tsdf::kBatchGroups] = {0};
+  for (uint32_t i = 0; i < n_items; ++i) ++count[group_of(items[i])];
+  uint32_t k_mask = 0, acc = 0;
+  for (int g = 0; g < tsdf::kBatchGroups; ++g) {
+    k_begin[g] = acc;
+    acc += count[g];
+    if (count[g]) k_mask |= 1u << g;
+  }
+  k_begin[tsdf::kBatchGroups] = acc;
+  uint32_t cursor[tsdf::kBatchGroups];
+  for (int g = 0; g < tsdf::kBatchGroups; ++g) cursor[g] = k_begin[g];
+  b->order.resize(n_items);
+  for (uint32_t i = 0; i < n_items; ++i) b->order[cursor[group_of(items[i])]++] = i;
+
+  uint64_t tiles = 0;
+  double pixels = 0.0;
+  uint32_t k_tiles[tsdf::kBatchGroups] = {0};
+  for (uint32_t j = 0; j < n_items; ++j) {
+    const tsdf_fuse_item& it = items[b->order[j]];
+    const int g = group_of(it);
+    const uint32_t th = (uint32_t)shape_of(g, c).ppt * (256u / tw);
+    tsdf::BatchItem& bi = out[j];
+    std::memset(&bi, 0, sizeof(bi));
+    bi.vol = it.volume->dev;
+    bi.wp = walk_params(it.volume);
+    bi.fr = frame_dev(it.depth_dev, &it.camera, it.volume->dev.colour ? it.rgba_dev : nullptr);
+    const uint32_t tx = (it.camera.width + tw - 1) / tw;
+    const uint32_t ty = (it.camera.height + th - 1) / th;
+    bi.tiles_x = tx;
+    tile_start[j] = (uint32_t)tiles;
+    tiles += (uint64_t)tx * ty;
+    k_tiles[g] += tx * ty;
+    pixels += (double)it.camera.width * it.camera.height;
+    if (tiles > 0x7FFFFFFFull) return TSDF_ERR_INVALID_ARGUMENT;  // tile indices stay in 31 bits
+  }
+  tile_start[n_items] = (uint32_t)tiles;
+  for (int g = 0; g < tsdf::kBatchGroups; ++g)
+    if (k_tiles[g] == 0) k_mask &= ~(1u << g);
+
+  // the device list: the slot's, once the launches that last read it are done
+  char* list = list_dev;
+  if (!list) {
+    list = const_cast<char*>(slot_list(b, slot));
+    if (b->slot_used[slot] && hipStreamWaitEvent(s, b->slot_done[slot], 0) != hipSuccess)
+      return TSDF_ERR_HIP;
+  }
+  const size_t bytes = (size_t)b->L.items + (size_t)n_items * sizeof(tsdf::BatchItem);
+  if (hipMemcpyAsync(list, host, bytes, hipMemcpyHostToDevice, s) != hipSuccess) return TSDF_ERR_HIP;
+  if (hipEventRecord(b->ring_done[slot], s) != hipSuccess) return TSDF_ERR_HIP;
+  b->ring_pending[slot] = true;
+  ++b->calls;
+
+  if (k_mask != 0) {
+    hipError_t e = hipSuccess;
+    if (cand >= 0) {
+      Timing t;
+      if (!b->spare.empty()) {
+        t = b->spare.back();
+        b->spare.pop_back();
+      } else {
+        e = hipEventCreate(&t.start);
+        if (e == hipSuccess) e = hipEventCreate(&t.stop);
+        if (e != hipSuccess) return TSDF_ERR_HIP;
+      }
+      t.cand = cand;
+      t.pixels = pixels;
+      e = hipEventRecord(t.start, s);
+      if (e == hipSuccess) e = launch_direct(b, list, k_mask, c, k_tiles, s);
+      if (e == hipSuccess) e = hipEventRecord(t.stop, s);
+      if (e != hipSuccess) {
+        b->spare.push_back(t);
+        return TSDF_ERR_HIP;
+      }
+      b->pending.push_back(t);
+      ++b->issued;
+    } else if (!list_dev && b->tuned && !(flags & TSDF_BATCH_NO_GRAPH)) {
+      hipGraphExec_t exec = nullptr;
+      e = graph_for(b, k_mask, slot, c, &exec);
+      if (e == hipSuccess) e = hipGraphLaunch(exec, s);
+    } else {
+      e = launch_direct(b, list, k_mask, c, k_tiles, s);
+    }
+    if (e != hipSuccess) return TSDF_ERR_HIP;
+  }
+  if (!list_dev) {
+    if (hipEventRecord(b->slot_done[slot], s) != hipSuccess) return TSDF_ERR_HIP;
+    b->slot_used[slot] = true;
+  }
+  for (uint32_t i = 0; i < n_items; ++i) items[i].volume->frames++;
+  return TSDF_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
 size_t tsdf_batch_workspace_bytes(uint32_t max_items) {
   if (max_items == 0 || max_items > TSDF_BATCH_MAX_ITEMS) return 0;
-  return (size_t)work_layout(max_items).total;
+  return (size_t)work_layout(max_items).total * kRingSlots;
 }
 
 tsdf_status tsdf_batch_create(uint32_t max_items, void* workspace_dev, size_t workspace_bytes,
@@ -335,7 +483,7 @@ tsdf_status tsdf_batch_create(uint32_t max_items, void* workspace_dev, size_t wo
   if (max_items == 0 || max_items > TSDF_BATCH_MAX_ITEMS) return TSDF_ERR_INVALID_ARGUMENT;
   if (!workspace_dev || ((uintptr_t)workspace_dev % kAlign) != 0) return TSDF_ERR_INVALID_ARGUMENT;
   const WorkLayout L = work_layout(max_items);
-  if (workspace_bytes < L.total) return TSDF_ERR_BUFFER_TOO_SMALL;
+  if (workspace_bytes < L.total * kRingSlots) return TSDF_ERR_BUFFER_TOO_SMALL;
   tsdf_batch* b = new (std::nothrow) tsdf_batch();
   if (!b) return TSDF_ERR_INTERNAL;
   b->max_items = max_items;
@@ -346,6 +494,8 @@ tsdf_status tsdf_batch_create(uint32_t max_items, void* workspace_dev, size_t wo
   for (int i = 0; i < kRingSlots; ++i) {
     b->ring_done[i] = nullptr;
     b->ring_pending[i] = false;
+    b->slot_done[i] = nullptr;
+    b->slot_used[i] = false;
   }
   b->next_slot = 0;
   b->n_graphs = 0;
@@ -358,8 +508,10 @@ tsdf_status tsdf_batch_create(uint32_t max_items, void* workspace_dev, size_t wo
   if (e == hipSuccess) e = hipDeviceGetAttribute(&b->n_cu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->ring), kRingSlots * L.total,
                                          hipHostMallocDefault);
-  for (int i = 0; i < kRingSlots && e == hipSuccess; ++i)
+  for (int i = 0; i < kRingSlots && e == hipSuccess; ++i) {
     e = hipEventCreateWithFlags(&b->ring_done[i], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->slot_done[i], hipEventDisableTiming);
+  }
   if (e != hipSuccess || b->n_cu < 1) {
     free_batch(b);
     return TSDF_ERR_HIP;
@@ -422,114 +574,7 @@ tsdf_status tsdf_batch_fuse(tsdf_batch* b, const tsdf_fuse_item* items, uint32_t
                             uint32_t flags, void* hip_stream) {
   if (!b || (n_items > 0 && !items) || n_items > b->max_items) return TSDF_ERR_INVALID_ARGUMENT;
   if ((flags & ~TSDF_BATCH_NO_GRAPH) != 0) return TSDF_ERR_INVALID_ARGUMENT;
-  for (uint32_t i = 0; i < n_items; ++i) {
-    const tsdf_fuse_item& it = items[i];
-    if (!it.volume || !valid_camera(&it.camera)) return TSDF_ERR_INVALID_ARGUMENT;
-    const bool pixels = (uint64_t)it.camera.width * it.camera.height > 0;
-    if (pixels && !it.depth_dev) return TSDF_ERR_INVALID_ARGUMENT;
-    if (pixels && it.volume->dev.colour && !it.rgba_dev) return TSDF_ERR_INVALID_ARGUMENT;
-  }
-  if (n_items == 0) return TSDF_OK;
-  hipStream_t s = as_stream(hip_stream);
-  poll_tuner(b);
-  int cand = -1;
-  const tsdf_batch_config c = next_config(b, &cand);
-  const uint32_t tw = c.tile_width;
-
-  // the ring slot: wait until the copy that last read it has run
-  const int slot = b->next_slot;
-  b->next_slot = (slot + 1) % kRingSlots;
-  if (b->ring_pending[slot] && hipEventSynchronize(b->ring_done[slot]) != hipSuccess)
-    return TSDF_ERR_HIP;
-  b->ring_pending[slot] = false;
-  char* host = b->ring + (size_t)slot * b->L.total;
-  unsigned* k_begin = reinterpret_cast<unsigned*>(host);
-  unsigned* tile_start = reinterpret_cast<unsigned*>(host + b->L.tile_start);
-  tsdf::BatchItem* out = reinterpret_cast<tsdf::BatchItem*>(host + b->L.items);
-
-  // counting sort by group (band width, colour)
-  auto group_of = [](const tsdf_fuse_item& it) {
-    return tsdf::batch_group(band_half(it.volume->params), it.volume->dev.colour != nullptr);
-  };
-  uint32_t count[tsdf::kBatchGroups] = {0};
-  for (uint32_t i = 0; i < n_items; ++i) ++count[group_of(items[i])];
-  uint32_t k_mask = 0, acc = 0;
-  for (int g = 0; g < tsdf::kBatchGroups; ++g) {
-    k_begin[g] = acc;
-    acc += count[g];
-    if (count[g]) k_mask |= 1u << g;
-  }
-  k_begin[tsdf::kBatchGroups] = acc;
-  uint32_t cursor[tsdf::kBatchGroups];
-  for (int g = 0; g < tsdf::kBatchGroups; ++g) cursor[g] = k_begin[g];
-  b->order.resize(n_items);
-  for (uint32_t i = 0; i < n_items; ++i) b->order[cursor[group_of(items[i])]++] = i;
-
-  uint64_t tiles = 0;
-  double pixels = 0.0;
-  uint32_t k_tiles[tsdf::kBatchGroups] = {0};
-  for (uint32_t j = 0; j < n_items; ++j) {
-    const tsdf_fuse_item& it = items[b->order[j]];
-    const int g = group_of(it);
-    const uint32_t th = (uint32_t)shape_of(g, c).ppt * (256u / tw);
-    tsdf::BatchItem& bi = out[j];
-    std::memset(&bi, 0, sizeof(bi));
-    bi.vol = it.volume->dev;
-    bi.wp = walk_params(it.volume);
-    bi.fr = frame_dev(it.depth_dev, &it.camera, it.volume->dev.colour ? it.rgba_dev : nullptr);
-    const uint32_t tx = (it.camera.width + tw - 1) / tw;
-    const uint32_t ty = (it.camera.height + th - 1) / th;
-    bi.tiles_x = tx;
-    tile_start[j] = (uint32_t)tiles;
-    tiles += (uint64_t)tx * ty;
-    k_tiles[g] += tx * ty;
-    pixels += (double)it.camera.width * it.camera.height;
-    if (tiles > 0x7FFFFFFFull) return TSDF_ERR_INVALID_ARGUMENT;  // tile indices stay in 31 bits
-  }
-  tile_start[n_items] = (uint32_t)tiles;
-  for (int g = 0; g < tsdf::kBatchGroups; ++g)
-    if (k_tiles[g] == 0) k_mask &= ~(1u << g);
-
-  const size_t bytes = (size_t)b->L.items + (size_t)n_items * sizeof(tsdf::BatchItem);
-  if (hipMemcpyAsync(b->ws, host, bytes, hipMemcpyHostToDevice, s) != hipSuccess) return TSDF_ERR_HIP;
-  if (hipEventRecord(b->ring_done[slot], s) != hipSuccess) return TSDF_ERR_HIP;
-  b->ring_pending[slot] = true;
-  ++b->calls;
-
-  if (k_mask != 0) {
-    hipError_t e = hipSuccess;
-    if (cand >= 0) {
-      Timing t;
-      if (!b->spare.empty()) {
-        t = b->spare.back();
-        b->spare.pop_back();
-      } else {
-        e = hipEventCreate(&t.start);
-        if (e == hipSuccess) e = hipEventCreate(&t.stop);
-        if (e != hipSuccess) return TSDF_ERR_HIP;
-      }
-      t.cand = cand;
-      t.pixels = pixels;
-      e = hipEventRecord(t.start, s);
-      if (e == hipSuccess) e = launch_direct(b, k_mask, c, k_tiles, s);
-      if (e == hipSuccess) e = hipEventRecord(t.stop, s);
-      if (e != hipSuccess) {
-        b->spare.push_back(t);
-        return TSDF_ERR_HIP;
-      }
-      b->pending.push_back(t);
-      ++b->issued;
-    } else if (b->tuned && !(flags & TSDF_BATCH_NO_GRAPH)) {
-      hipGraphExec_t exec = nullptr;
-      e = graph_for(b, k_mask, c, s, &exec);
-      if (e == hipSuccess) e = hipGraphLaunch(exec, s);
-    } else {
-      e = launch_direct(b, k_mask, c, k_tiles, s);
-    }
-    if (e != hipSuccess) return TSDF_ERR_HIP;
-  }
-  for (uint32_t i = 0; i < n_items; ++i) items[i].volume->frames++;
-  return TSDF_OK;
+  return batch_fuse_impl(b, items, n_items, flags, nullptr, as_stream(hip_stream));
 }
 
 }  // extern "C"

@@ -147,8 +147,9 @@ def test_batch_workspace_bytes():
     for n in (1, 2, 64, 1000, T.BATCH_MAX_ITEMS):
         b = L.tsdf_batch_workspace_bytes(n)
         assert b % 256 == 0 and b > prev
-        # group ranges + tile prefix sums + one 176-byte descriptor per item
-        assert b >= 256 + 4 * (n + 1) + 176 * n
+        # per ring slot: group ranges + tile prefix sums + one 192-byte
+        # descriptor per item; eight slots
+        assert b % 8 == 0 and b // 8 >= 256 + 4 * (n + 1) + 192 * n
         prev = b
 
 
