@@ -449,6 +449,26 @@ tsdf_status tsdf_batch_candidates(tsdf_batch* batch, uint32_t max, tsdf_batch_co
 tsdf_status tsdf_batch_fuse(tsdf_batch* batch, const tsdf_fuse_item* items, uint32_t n_items,
                             uint32_t flags, void* hip_stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): tsdf_batch_fuse with its
+ * work list in a device array of TSDF_STATIC_LIST_BYTES that the library holds
+ * for the life of the process on each device it runs on, instead of in the
+ * batch's workspace.  The call allocates no memory, device or host; it copies
+ * the work list from the batch's pinned staging ring and launches directly
+ * (never a graph, never a tuning trial) with the batch's current
+ * configuration.  Results are those of tsdf_batch_fuse.
+ *   - The list takes 256 + 4 * (max_items + 1) bytes, rounded up to a multiple
+ *     of 256, plus 192 bytes per item (max_items of the batch); a call whose
+ *     list would not fit returns TSDF_ERR_BUFFER_TOO_SMALL with nothing
+ *     enqueued.
+ *   - The current device must be the batch's (TSDF_ERR_INVALID_ARGUMENT).
+ *   - Every call on a device shares that device's array and leaves its list
+ *     there: calls on one stream are ordered, calls that overlap on one GPU
+ *     (from different streams or threads) race and must not be made. */
+#define TSDF_STATIC_LIST_BYTES (1u << 20)
+tsdf_status tsdf_batch_fuse_static(tsdf_batch* batch, const tsdf_fuse_item* items,
+                                   uint32_t n_items, void* hip_stream);
+
 /* ---------------------------------------------------------------------------
  * Device-region sub-allocator.  Carves 256-byte-aligned ranges out of one
  * caller-owned device region (first fit, neighbouring free ranges merged).

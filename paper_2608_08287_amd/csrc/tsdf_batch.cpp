@@ -85,6 +85,7 @@ struct GraphEntry {
 
 struct tsdf_batch {
   uint32_t max_items;
+  int device;  // current at tsdf_batch_create
   char* ws;
   WorkLayout L;
   int n_cu;
@@ -354,7 +355,7 @@ tsdf_status batch_fuse_impl(tsdf_batch* b, const tsdf_fuse_item* items, uint32_t
                             uint32_t flags, char* list_dev, hipStream_t s) {
   if (!valid_items(items, n_items)) return TSDF_ERR_INVALID_ARGUMENT;
   if (n_items == 0) return TSDF_OK;
-  poll_tuner(b);
+  if (!list_dev) poll_tuner(b);  // (its bookkeeping may allocate host memory)
   int cand = -1;
   const tsdf_batch_config c = next_config(b, &cand);
   if (list_dev) cand = -1;  // not a tuning trial
@@ -505,6 +506,7 @@ tsdf_status tsdf_batch_create(uint32_t max_items, void* workspace_dev, size_t wo
   b->issued = 0;
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
+  b->device = dev;
   if (e == hipSuccess) e = hipDeviceGetAttribute(&b->n_cu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->ring), kRingSlots * L.total,
                                          hipHostMallocDefault);
@@ -575,6 +577,20 @@ tsdf_status tsdf_batch_fuse(tsdf_batch* b, const tsdf_fuse_item* items, uint32_t
   if (!b || (n_items > 0 && !items) || n_items > b->max_items) return TSDF_ERR_INVALID_ARGUMENT;
   if ((flags & ~TSDF_BATCH_NO_GRAPH) != 0) return TSDF_ERR_INVALID_ARGUMENT;
   return batch_fuse_impl(b, items, n_items, flags, nullptr, as_stream(hip_stream));
+}
+
+tsdf_status tsdf_batch_fuse_static(tsdf_batch* b, const tsdf_fuse_item* items, uint32_t n_items,
+                                   void* hip_stream) {
+  if (!b || (n_items > 0 && !items) || n_items > b->max_items) return TSDF_ERR_INVALID_ARGUMENT;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return TSDF_ERR_HIP;
+  if (dev != b->device) return TSDF_ERR_INVALID_ARGUMENT;
+  void* list = nullptr;
+  size_t cap = 0;
+  if (tsdf::static_scratch(&list, &cap) != hipSuccess) return TSDF_ERR_HIP;
+  if ((uint64_t)b->L.items + (uint64_t)n_items * sizeof(tsdf::BatchItem) > cap)
+    return TSDF_ERR_BUFFER_TOO_SMALL;
+  return batch_fuse_impl(b, items, n_items, 0, static_cast<char*>(list), as_stream(hip_stream));
 }
 
 }  // extern "C"

@@ -182,6 +182,9 @@ const void* multi_kernel_band7(int pixels_per_thread, int acc_blocks, bool colou
 const void* multi_kernel_band8(int pixels_per_thread, int acc_blocks, bool colour);
 // out[i] = the sticky status bits of the volume whose counters ctrs[i] points
 // to (0 for a null pointer), i < n.  ctrs and out may be host-mapped memory.
+// The device address and size of the process-lifetime work-list array of
+// tsdf_batch_fuse_static on the current device (looked up on first use).
+hipError_t static_scratch(void** ptr, size_t* bytes);
 hipError_t launch_gather_status(DevCounters* const* ctrs, unsigned n, unsigned* out, hipStream_t s);
 // Marching-tetrahedra surface of the first n_blocks pool blocks; counter
 // (zeroed by the caller) receives the triangle count; at most max_tris

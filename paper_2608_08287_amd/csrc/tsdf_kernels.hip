@@ -2,6 +2,8 @@
 // blocks, fills, reset of used blocks, extraction) and the dispatch of the fused
 // kernel to its per-K translation units.
 
+#include <mutex>
+
 #include "tsdf_device.h"
 
 namespace tsdf {
@@ -188,6 +190,37 @@ hipError_t launch_gather_status(DevCounters* const* ctrs, unsigned n, unsigned* 
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(gather_status_kernel, dim3((n + 255) / 256), dim3(256), 0, s, ctrs, n, out);
   return hipGetLastError();
+}
+
+// The work list of tsdf_batch_fuse_static: a device array the library holds
+// for the whole process on every device it runs on, so that the call needs no
+// caller memory and allocates nothing.  Host code never uses the array's name
+// as an address (on the host it is only a stand-in for the symbol): its device
+// address is looked up once per device, with that device current, and kept.
+namespace {
+constexpr size_t kStaticListBytes = TSDF_STATIC_LIST_BYTES;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kStaticListBytes];
+}  // namespace
+
+hipError_t static_scratch(void** ptr, size_t* bytes) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  static std::mutex mu;
+  static void* by_device[kMaxDevices];
+  std::lock_guard<std::mutex> lock(mu);
+  if (!by_device[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    by_device[dev] = p;
+  }
+  *ptr = by_device[dev];
+  *bytes = kStaticListBytes;
+  return hipSuccess;
 }
 
 const void* multi_kernel(int K, int pixels_per_thread, int acc_blocks, bool colour) {

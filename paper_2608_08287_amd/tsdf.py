@@ -47,7 +47,7 @@ EXPORTED_SYMBOLS = (
     "tsdf_fuse_frame_rgb", "tsdf_extract_colour",
     "tsdf_batch_workspace_bytes", "tsdf_batch_create", "tsdf_batch_destroy",
     "tsdf_batch_set_config", "tsdf_batch_autotune", "tsdf_batch_get_config",
-    "tsdf_batch_candidates", "tsdf_batch_fuse",
+    "tsdf_batch_candidates", "tsdf_batch_fuse", "tsdf_batch_fuse_static",
     "tsdf_region_create", "tsdf_region_destroy", "tsdf_region_alloc", "tsdf_region_free",
     "tsdf_region_usage",
     "tsdf_server_workspace_bytes", "tsdf_server_create", "tsdf_server_destroy", "tsdf_server_open",
@@ -57,6 +57,7 @@ EXPORTED_SYMBOLS = (
 REPLAY_SERVED, REPLAY_PLAIN = 0, 1
 BATCH_NO_GRAPH = 0x1
 BATCH_MAX_ITEMS = 65536
+STATIC_LIST_BYTES = 1 << 20
 
 
 class VolumeParams(C.Structure):
@@ -219,6 +220,8 @@ def lib() -> C.CDLL:
                                          C.POINTER(C.c_double)]
         L.tsdf_batch_fuse.restype = I
         L.tsdf_batch_fuse.argtypes = [P, C.POINTER(FuseItemC), U32, U32, P]
+        L.tsdf_batch_fuse_static.restype = I
+        L.tsdf_batch_fuse_static.argtypes = [P, C.POINTER(FuseItemC), U32, P]
         _lib = L
     return _lib
 
@@ -608,9 +611,12 @@ class Batch:
                  float(t)) for c, t in zip(cfgs[:n.value], ns[:n.value])]
 
     def fuse(self, volumes: Sequence[Volume], depths: Sequence[torch.Tensor], cams,
-             flags: int = 0, stream=None, rgbas: Optional[Sequence[torch.Tensor]] = None) -> None:
+             flags: int = 0, stream=None, rgbas: Optional[Sequence[torch.Tensor]] = None,
+             static: bool = False) -> None:
         """Enqueue one frame into each listed volume (a volume may repeat);
-        colour volumes take their colour image from ``rgbas``."""
+        colour volumes take their colour image from ``rgbas``.  ``static``
+        calls tsdf_batch_fuse_static (work list in the library's device array,
+        no allocation; ``flags`` must be 0)."""
         n = len(volumes)
         if len(depths) != n or len(cams) != n or (rgbas is not None and len(rgbas) != n):
             raise ValueError("one depth frame and one camera per item")
@@ -627,6 +633,13 @@ class Batch:
             it.depth_dev = d.data_ptr()
             it.rgba_dev = rgbas[i].data_ptr() if rgbas is not None and rgbas[i] is not None else None
             it.camera = c
+        if static:
+            if flags:
+                raise ValueError("tsdf_batch_fuse_static takes no flags")
+            st = lib().tsdf_batch_fuse_static(self._h, self._items, n, _stream_ptr(stream))
+            if st != OK:
+                raise TsdfError(st, "tsdf_batch_fuse_static")
+            return
         st = lib().tsdf_batch_fuse(self._h, self._items, n, flags, _stream_ptr(stream))
         if st != OK:
             raise TsdfError(st, "tsdf_batch_fuse")
