@@ -252,6 +252,52 @@ tsdf_status tsdf_fuse_frame_rgb(tsdf_volume* vol, const float* depth_dev, const 
 tsdf_status tsdf_fuse_frames(tsdf_volume* vol, uint32_t n_frames, const float* const* depth_devs,
                              const tsdf_camera* cams, uint32_t flags, void* hip_stream);
 
+/* Staged accumulation of many frames of one volume (Section 2.2: the integrate
+ * stage is a sum of contributions, so it can be gathered before it reaches the
+ * pool).  As tsdf_fuse_frames, 32 frames per launch, but a launch's tiles do
+ * not add their contributions to the pool: each tile writes one 4-byte record
+ * per contribution (the voxel and its truncated distance, carried in 23-bit
+ * fixed point of trunc: to within trunc / 2^23), grouped by block, into the
+ * caller's staging memory, and lists each of its (tile, block) runs in that
+ * block's run table (one device atomic per tile and block).  An apply kernel
+ * then sums each block's records per voxel, one work item per 1024 records of
+ * a block, and adds the sums to its pool rows with one memory-side request per
+ * touched row and item.  Runs that do not fit a block's table of 128, or a
+ * launch's records beyond the staging memory, go to the pool directly with
+ * device atomics, so any size is correct; the size only decides how much is
+ * staged.  The staging memory holds two sets used by alternate launches, and
+ * the apply kernels run on a second stream of the device (default priority,
+ * made on first use and kept for the process), so that a launch's tile kernel
+ * overlaps the previous launch's apply; the caller's stream waits for every
+ * apply before the call's later work.  The result is that of fusing the frames
+ * one by one with tsdf_fuse_frame (keys and weights identical, TSDF sums up to
+ * float summation order and the fixed-point carry).  Plain volumes only
+ * (colour volumes: TSDF_ERR_INVALID_ARGUMENT).  Calls from several host
+ * threads are serialised while they enqueue.
+ *   staging_dev    caller-owned device memory, 256-byte aligned, of at least
+ *                  tsdf_staging_bytes(pool_capacity, 65536) bytes for the
+ *                  volume's pool (else TSDF_ERR_BUFFER_TOO_SMALL, nothing
+ *                  enqueued); what it holds beyond that sets the records per
+ *                  launch (a launch of 32 frames of W x H pixels makes at most
+ *                  32 * W * H * (2K + 1)).  Its contents need no initialisation
+ *                  and are meaningless after the call; it may serve any volume of
+ *                  at most that pool, one call at a time (calls on one stream are
+ *                  ordered).
+ *   flags          TSDF_FUSE_BATCH(1): one frame per workgroup; otherwise two
+ *                  (one when round(trunc/voxel_size) > 4).
+ *                  TSDF_FUSE_ONE_STREAM: every kernel on hip_stream (no second
+ *                  stream, no overlap).
+ * Asynchronous, like tsdf_fuse_frame.
+ * tsdf_staging_bytes: the staging bytes for a pool of pool_capacity blocks
+ * (1 .. TSDF_MAX_POOL_BLOCKS) and `records` records per launch (2^16 .. 2^32 -
+ * 1); 0 for other values. */
+#define TSDF_FUSE_ONE_STREAM 0x200u
+size_t tsdf_staging_bytes(uint32_t pool_capacity, uint64_t records);
+tsdf_status tsdf_fuse_frames_staged(tsdf_volume* vol, uint32_t n_frames,
+                                    const float* const* depth_devs, const tsdf_camera* cams,
+                                    uint32_t flags, void* staging_dev, size_t staging_bytes,
+                                    void* hip_stream);
+
 /* tsdf_fuse_frames for colour volumes (TSDF_VOLUME_COLOUR): frame i also adds
  * the colours of rgba_devs[i] (height x width packed red | green << 8 |
  * blue << 16, as for tsdf_fuse_frame_rgb) to the voxels its pairs touch.  F is

@@ -8,6 +8,7 @@
 
 #include <cstddef>
 #include <cstdlib>
+#include <mutex>
 
 #include "tsdf_host.h"
 
@@ -255,6 +256,154 @@ tsdf_status fuse_frames_impl(tsdf_volume* vol, uint32_t n_frames, const float* c
 }
 
 }  // namespace
+
+namespace {
+
+// Staging memory of tsdf_fuse_frames_staged: two sets, used by alternate
+// launches.  A set: four list heads in a 256-byte header, per pool block its
+// run and record counts (8 bytes) and a run table of kStageRuns 8-byte entries,
+// the work items (8 bytes each), then the records (4 bytes each).
+struct StageLayout {
+  uint64_t block_stat, runs, items, recs, set_bytes;
+  uint64_t item_cap;
+};
+StageLayout stage_layout(uint64_t pool, uint64_t records) {
+  StageLayout L;
+  L.item_cap = records / tsdf::kStageItemRecords + pool + 1;  // enough for any launch
+  L.block_stat = kAlign;
+  L.runs = align_up(L.block_stat + 8 * pool);
+  L.items = align_up(L.runs + 8ull * tsdf::kStageRuns * pool);
+  L.recs = align_up(L.items + 8 * L.item_cap);
+  L.set_bytes = align_up(L.recs + 4 * records);
+  return L;
+}
+constexpr uint64_t kMinStageRecords = 1ull << 16;
+constexpr uint64_t kMaxStageRecords = 0xFFFFFFFFull;
+
+// The apply kernels of a call run on a second stream of the device, ordered
+// against the caller's stream by events; the stream and events are made on
+// first use and kept for the life of the process.  A call enqueues its whole
+// sequence holding the device's lock.
+constexpr int kMaxStageDevices = 64;
+struct StageStreams {
+  hipStream_t aux = nullptr;
+  hipEvent_t tile_done[2] = {nullptr, nullptr};
+  hipEvent_t apply_done[2] = {nullptr, nullptr};
+};
+std::mutex g_stage_mu;
+StageStreams g_stage[kMaxStageDevices];
+
+hipError_t stage_streams(StageStreams** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxStageDevices) return hipErrorInvalidDevice;
+  StageStreams& ss = g_stage[dev];
+  if (!ss.aux) {
+    hipStream_t aux = nullptr;
+    e = hipStreamCreateWithFlags(&aux, hipStreamNonBlocking);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+      e = hipEventCreateWithFlags(&ss.tile_done[i], hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&ss.apply_done[i], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) return e;
+    ss.aux = aux;
+  }
+  *out = &ss;
+  return hipSuccess;
+}
+
+}  // namespace
+
+size_t tsdf_staging_bytes(uint32_t pool_capacity, uint64_t records) {
+  if (pool_capacity < 1 || pool_capacity > TSDF_MAX_POOL_BLOCKS) return 0;
+  if (records < kMinStageRecords || records > kMaxStageRecords) return 0;
+  return (size_t)(2 * stage_layout(pool_capacity, records).set_bytes);
+}
+
+tsdf_status tsdf_fuse_frames_staged(tsdf_volume* vol, uint32_t n_frames,
+                                    const float* const* depth_devs, const tsdf_camera* cams,
+                                    uint32_t flags, void* staging_dev, size_t staging_bytes,
+                                    void* hip_stream) {
+  if (!vol || vol->dev.colour) return TSDF_ERR_INVALID_ARGUMENT;
+  if (n_frames > 0 && (!depth_devs || !cams)) return TSDF_ERR_INVALID_ARGUMENT;
+  if ((flags & ~(TSDF_FUSE_BATCH_MASK | TSDF_FUSE_ONE_STREAM)) != 0)
+    return TSDF_ERR_INVALID_ARGUMENT;
+  for (uint32_t i = 0; i < n_frames; ++i) {
+    if (!valid_camera(&cams[i])) return TSDF_ERR_INVALID_ARGUMENT;
+    if ((uint64_t)cams[i].width * cams[i].height > 0 && !depth_devs[i])
+      return TSDF_ERR_INVALID_ARGUMENT;
+  }
+  if (!staging_dev || ((uintptr_t)staging_dev % kAlign) != 0) return TSDF_ERR_INVALID_ARGUMENT;
+  const uint64_t P = vol->layout.pool_capacity;
+  if (staging_bytes < tsdf_staging_bytes((uint32_t)P, kMinStageRecords))
+    return TSDF_ERR_BUFFER_TOO_SMALL;
+  // the most records whose two sets fit
+  uint64_t lo = kMinStageRecords, hi = kMaxStageRecords;
+  while (lo < hi) {
+    const uint64_t mid = lo + (hi - lo + 1) / 2;
+    if (2 * stage_layout(P, mid).set_bytes <= staging_bytes) lo = mid;
+    else hi = mid - 1;
+  }
+  const StageLayout L = stage_layout(P, lo);
+  // frames per workgroup: TSDF_FUSE_BATCH(1) -> 1, anything else -> 2
+  const uint32_t asked = (flags & TSDF_FUSE_BATCH_MASK) >> TSDF_FUSE_BATCH_SHIFT;
+  const int per_group = asked == 1 ? 1 : 2;
+  const tsdf::WalkParams wp = walk_params(vol);
+  hipStream_t s = as_stream(hip_stream);
+  tsdf::StageDev set[2];
+  for (int k = 0; k < 2; ++k) {
+    char* base = static_cast<char*>(staging_dev) + k * L.set_bytes;
+    std::memset(&set[k], 0, sizeof(set[k]));
+    set[k].head = reinterpret_cast<unsigned*>(base);
+    set[k].block_stat = reinterpret_cast<unsigned long long*>(base + L.block_stat);
+    set[k].runs = reinterpret_cast<unsigned long long*>(base + L.runs);
+    set[k].items = reinterpret_cast<unsigned*>(base + L.items);
+    set[k].recs = reinterpret_cast<unsigned*>(base + L.recs);
+    set[k].rec_cap = (unsigned)lo;
+    set[k].item_cap = (unsigned)L.item_cap;
+    set[k].to_fixed = (float)tsdf::kStageQuantum / wp.trunc;
+    set[k].to_metres = wp.trunc / (float)tsdf::kStageQuantum;
+  }
+  const bool one_stream = (flags & TSDF_FUSE_ONE_STREAM) != 0;
+  std::lock_guard<std::mutex> lock(g_stage_mu);
+  StageStreams* ss = nullptr;
+  if (!one_stream && stage_streams(&ss) != hipSuccess) return TSDF_ERR_HIP;
+  hipStream_t aux = one_stream ? s : ss->aux;
+  tsdf::FrameDev batch[tsdf::kMaxBatchFrames];
+  uint32_t done = 0, launch = 0;
+  hipError_t e = hipSuccess;
+  while (done < n_frames && e == hipSuccess) {
+    const uint32_t left = n_frames - done;
+    const int n = left < (uint32_t)tsdf::kMaxBatchFrames ? (int)left : tsdf::kMaxBatchFrames;
+    uint64_t pix = 0;
+    for (int i = 0; i < n; ++i) {
+      batch[i] = frame_dev(depth_devs[done + i], &cams[done + i]);
+      pix += (uint64_t)cams[done + i].width * cams[done + i].height;
+    }
+    if (pix > 0) {
+      const int k = (int)(launch & 1u);
+      // the set is free once the launch two back has been applied; its heads
+      // and block counts start at zero
+      if (!one_stream && launch >= 2) e = hipStreamWaitEvent(s, ss->apply_done[k], 0);
+      if (e == hipSuccess) e = tsdf::launch_fill_u32(set[k].head, 0u, L.runs / 4, s);
+      if (e == hipSuccess) e = tsdf::launch_stage(vol->dev, wp, batch, n, per_group, set[k], s);
+      if (!one_stream) {
+        if (e == hipSuccess) e = hipEventRecord(ss->tile_done[k], s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(aux, ss->tile_done[k], 0);
+      }
+      if (e == hipSuccess) e = tsdf::launch_stage_apply(vol->dev, set[k], aux);
+      if (!one_stream && e == hipSuccess) e = hipEventRecord(ss->apply_done[k], aux);
+      ++launch;
+    }
+    done += (uint32_t)n;
+    vol->frames += (uint32_t)n;
+  }
+  // the caller's stream resumes after every apply of the call
+  for (uint32_t k = 0; !one_stream && k < 2 && k < launch && e == hipSuccess; ++k)
+    e = hipStreamWaitEvent(s, ss->apply_done[k], 0);
+  return e == hipSuccess ? TSDF_OK : TSDF_ERR_HIP;
+}
 
 tsdf_status tsdf_fuse_frames(tsdf_volume* vol, uint32_t n_frames, const float* const* depth_devs,
                              const tsdf_camera* cams, uint32_t flags, void* hip_stream) {

@@ -383,17 +383,20 @@ __device__ __forceinline__ Sample walk_sample(const FrameDev& f, const WalkParam
   const float q0 = w[0] * wp.iv, q1 = w[1] * wp.iv, q2 = w[2] * wp.iv;
   s.in_range = (z > 0.0f) && (__builtin_fabsf(q0) < 8388608.0f) &&
                (__builtin_fabsf(q1) < 8388608.0f) && (__builtin_fabsf(q2) < 8388608.0f);
-  s.vx = s.in_range ? (int)__builtin_floorf(q0) : 0;
-  s.vy = s.in_range ? (int)__builtin_floorf(q1) : 0;
-  s.vz = s.in_range ? (int)__builtin_floorf(q2) : 0;
-  const float c0 = ((float)s.vx + 0.5f) * wp.v;
-  const float c1 = ((float)s.vy + 0.5f) * wp.v;
-  const float c2 = ((float)s.vz + 0.5f) * wp.v;
+  const float f0 = __builtin_floorf(q0), f1 = __builtin_floorf(q1), f2 = __builtin_floorf(q2);
+  s.vx = s.in_range ? (int)f0 : 0;
+  s.vy = s.in_range ? (int)f1 : 0;
+  s.vz = s.in_range ? (int)f2 : 0;
+  // in range (|q| < 2^23) the floored float is the voxel index exactly, so the
+  // centre (i + 1/2) v is computed from it without converting back
+  const float c0 = (f0 + 0.5f) * wp.v;
+  const float c1 = (f1 + 0.5f) * wp.v;
+  const float c2 = (f2 + 0.5f) * wp.v;
   float zcv = f.R[2] * (c0 - f.t[0]);
   zcv = zcv + f.R[5] * (c1 - f.t[1]);
   zcv = zcv + f.R[8] * (c2 - f.t[2]);
   const float sdf = d - zcv;
-  s.keep = (zcv > 0.0f) && !(sdf < -wp.trunc);
+  s.keep = s.in_range && (zcv > 0.0f) && !(sdf < -wp.trunc);
   s.val = sdf < wp.trunc ? sdf : wp.trunc;
   return s;
 }

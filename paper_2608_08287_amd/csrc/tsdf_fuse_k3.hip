@@ -1,11 +1,17 @@
-// The fused kernels (one volume; many volumes) for a band of 7 samples (K = 3).
-#include "tsdf_device.h"
+// The fused kernels (one volume; many volumes) and the staged tile kernel for
+// a band of 2K + 1 samples, K = 3.
+#include "tsdf_stage.h"
 
 namespace tsdf {
 
 hipError_t launch_fuse_band3(VolumeDev vol, const WalkParams& wp, const FrameDev* frames, int n,
                              int frames_per_group, FuseMode mode, bool remap, hipStream_t s) {
   return launch_fuse_k<3>(vol, wp, frames, n, frames_per_group, mode, remap, s);
+}
+
+hipError_t launch_stage_band3(VolumeDev vol, const WalkParams& wp, const FrameDev* frames, int n,
+                              int frames_per_group, const StageDev& stage, hipStream_t s) {
+  return launch_stage_k<3>(vol, wp, frames, n, frames_per_group, stage, s);
 }
 
 const void* multi_kernel_band3(int pixels_per_thread, int acc_blocks, bool colour) {

@@ -1,11 +1,17 @@
-// The fused kernels (one volume; many volumes) for a band of 15 samples (K = 7).
-#include "tsdf_device.h"
+// The fused kernels (one volume; many volumes) and the staged tile kernel for
+// a band of 2K + 1 samples, K = 7.
+#include "tsdf_stage.h"
 
 namespace tsdf {
 
 hipError_t launch_fuse_band7(VolumeDev vol, const WalkParams& wp, const FrameDev* frames, int n,
                              int frames_per_group, FuseMode mode, bool remap, hipStream_t s) {
   return launch_fuse_k<7>(vol, wp, frames, n, frames_per_group, mode, remap, s);
+}
+
+hipError_t launch_stage_band7(VolumeDev vol, const WalkParams& wp, const FrameDev* frames, int n,
+                              int frames_per_group, const StageDev& stage, hipStream_t s) {
+  return launch_stage_k<7>(vol, wp, frames, n, frames_per_group, stage, s);
 }
 
 const void* multi_kernel_band7(int pixels_per_thread, int acc_blocks, bool colour) {

@@ -139,6 +139,41 @@ struct BatchWork {
   const BatchItem* items;
 };
 
+// Staged accumulation (tsdf_fuse_frames_staged).  The tiles of a launch do not
+// add their contributions to the pool.  Each tile writes one record per
+// contribution, grouped by block, into a launch-wide record array (one device
+// atomic per tile reserves its span), and lists each of its (tile, block) runs
+// in the block's run table (one device atomic per tile and block, which also
+// counts the block's runs and records).  A block is cut into one work item per
+// kStageItemRecords records; the apply kernel takes items from a queue, sums
+// an item's share of the block's runs per voxel in LDS and adds the sums to
+// the block's pool rows with device atomics, one request per touched row.
+//
+// A record is one contribution in 32 bits: its voxel's in-block index (bits
+// 0..8) and its truncated distance in signed 23-bit fixed point of the
+// truncation distance (bits 9..31): q = round(sdf * kStageQuantum / trunc),
+// |q| <= kStageQuantum, so sdf is carried to within trunc / 2^23 (2.4e-9 m at
+// trunc = 2 cm).
+constexpr int kStageQuantum = (1 << 22) - 1;
+constexpr unsigned kStageRuns = 128;          // run table entries per block and launch
+constexpr unsigned kStageItemRecords = 1024;  // records per apply work item
+// One set of staging buffers (a launch uses one set; two sets alternate so
+// that a launch's tile kernel may run while the previous launch is applied).
+struct StageDev {
+  unsigned* head;                  // [0] blocks listed, [1] records reserved, [2] items,
+                                   // [3] items taken by the apply kernel
+  unsigned long long* block_stat;  // per pool block: runs << 32 | records
+  unsigned long long* runs;        // per pool block: kStageRuns (first record | count << 32)
+  unsigned* items;                 // work items: (block, part)
+  unsigned* recs;                  // the launch's records
+  unsigned rec_cap;                // records the array holds
+  unsigned item_cap;               // work items the list holds
+  float to_fixed;                  // kStageQuantum / trunc
+  float to_metres;                 // trunc / kStageQuantum
+  unsigned pad[2];
+};
+static_assert(sizeof(StageDev) % 16 == 0, "stage descriptors stay 16-byte aligned");
+
 hipError_t launch_fill_u32(void* ptr, unsigned value, size_t n_words, hipStream_t s);
 hipError_t launch_reset_used(VolumeDev vol, hipStream_t s);
 hipError_t launch_atomic_rate(float* p, unsigned n_rows, unsigned waves, unsigned iters,
@@ -165,6 +200,29 @@ hipError_t launch_fuse_band7(VolumeDev vol, const WalkParams& wp, const FrameDev
                              int frames_per_group, FuseMode mode, bool remap, hipStream_t s);
 hipError_t launch_fuse_band8(VolumeDev vol, const WalkParams& wp, const FrameDev* frames, int n,
                              int frames_per_group, FuseMode mode, bool remap, hipStream_t s);
+// The tile kernel of staged accumulation: n frames (1..kMaxBatchFrames) of one
+// volume in one launch, frames_per_group (1 or 2) of them per workgroup; then
+// the apply kernel, which consumes the launch's work items.  A set's heads and
+// block counts must be zero before its tile kernel runs.
+hipError_t launch_stage(VolumeDev vol, const WalkParams& wp, const FrameDev* frames, int n,
+                        int frames_per_group, const StageDev& stage, hipStream_t s);
+hipError_t launch_stage_band1(VolumeDev, const WalkParams&, const FrameDev*, int, int,
+                              const StageDev&, hipStream_t);
+hipError_t launch_stage_band2(VolumeDev, const WalkParams&, const FrameDev*, int, int,
+                              const StageDev&, hipStream_t);
+hipError_t launch_stage_band3(VolumeDev, const WalkParams&, const FrameDev*, int, int,
+                              const StageDev&, hipStream_t);
+hipError_t launch_stage_band4(VolumeDev, const WalkParams&, const FrameDev*, int, int,
+                              const StageDev&, hipStream_t);
+hipError_t launch_stage_band5(VolumeDev, const WalkParams&, const FrameDev*, int, int,
+                              const StageDev&, hipStream_t);
+hipError_t launch_stage_band6(VolumeDev, const WalkParams&, const FrameDev*, int, int,
+                              const StageDev&, hipStream_t);
+hipError_t launch_stage_band7(VolumeDev, const WalkParams&, const FrameDev*, int, int,
+                              const StageDev&, hipStream_t);
+hipError_t launch_stage_band8(VolumeDev, const WalkParams&, const FrameDev*, int, int,
+                              const StageDev&, hipStream_t);
+hipError_t launch_stage_apply(VolumeDev vol, const StageDev& stage, hipStream_t s);
 // The persistent multi-volume kernel for band half-width K taking
 // pixels_per_thread (1 or 2) pixels per thread and accumulating acc_blocks
 // (4 or 8; 8 with 2 pixels) blocks in LDS per pass, as a host

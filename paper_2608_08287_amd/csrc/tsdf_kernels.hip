@@ -158,6 +158,131 @@ hipError_t launch_reset_used(VolumeDev vol, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Staged accumulation, the apply kernels.  A block's records are its runs (one
+// per tile that touched it), each a contiguous span of the launch's record
+// array; its run table lists them.
+//
+// Sum a block's runs r = part, part + step, ... into a wave's LDS sums and
+// counts (512 of each, zeroed here).  The run descriptors are read by the
+// lanes together; then the runs are taken four at a time, each run's records
+// by consecutive lanes, with the four runs' loads issued before any is added
+// (four memory latencies overlapped, not four in a row).
+__device__ void stage_sum_runs(const StageDev& stg, unsigned blk, unsigned n_runs, unsigned part,
+                               unsigned step, float* sum, unsigned* cnt) {
+  const unsigned lane = lane_id();
+#pragma unroll
+  for (unsigned i = 0; i < TSDF_BLOCK_VOXELS / (4u * kWave); ++i) {
+    reinterpret_cast<float4*>(sum)[lane + i * kWave] = make_float4(0.f, 0.f, 0.f, 0.f);
+    reinterpret_cast<uint4*>(cnt)[lane + i * kWave] = make_uint4(0u, 0u, 0u, 0u);
+  }
+  const unsigned long long* const runs = stg.runs + (size_t)blk * kStageRuns;
+  constexpr unsigned kAhead = 4;
+  for (unsigned r0 = part; r0 < n_runs; r0 += step * kWave) {
+    const unsigned rr = r0 + lane * step;
+    const unsigned long long mine = rr < n_runs ? runs[rr] : 0ull;
+    const unsigned here = (n_runs - r0 + step - 1) / step;  // runs of this round
+    for (unsigned k = 0; k < kWave && k < here; k += kAhead) {
+      unsigned first[kAhead], count[kAhead], longest = 0;
+#pragma unroll
+      for (unsigned j = 0; j < kAhead; ++j) {
+        const int src = (int)(k + j < here ? k + j : k);
+        first[j] = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)mine, src);
+        count[j] = k + j < here
+                       ? (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(mine >> 32), src)
+                       : 0u;
+        longest = count[j] > longest ? count[j] : longest;
+      }
+      for (unsigned i0 = 0; i0 < longest; i0 += kWave) {
+        unsigned rec[kAhead];
+        bool in[kAhead];
+#pragma unroll
+        for (unsigned j = 0; j < kAhead; ++j) {
+          in[j] = i0 + lane < count[j];
+          rec[j] = in[j] ? stg.recs[first[j] + i0 + lane] : 0u;
+        }
+#pragma unroll
+        for (unsigned j = 0; j < kAhead; ++j) {
+          if (in[j]) {
+            const unsigned loc = rec[j] & 511u;
+            __hip_atomic_fetch_add(sum + loc, (float)((int)rec[j] >> 9) * stg.to_metres,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            __hip_atomic_fetch_add(cnt + loc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+          }
+        }
+      }
+    }
+  }
+}
+
+// The work items of a launch, taken by waves from a queue (one device atomic
+// per eight items).  Item (block, k) of a block with n records (parts = ceil(n /
+// kStageItemRecords) items, appended by the tile kernel) sums the block's runs
+// k, k + parts, ... per voxel in LDS and adds the sums to the block's pool rows
+// with device atomics: a row's 8 sums and 8 weights by 16 lanes of one
+// instruction, one memory-side request per touched row.  Items of one block,
+// the tile kernel's direct additions and the items of an earlier launch may
+// all update a row at once: every update is an atomic add.
+constexpr unsigned kApplyWaves = kThreads / kWave;
+
+__global__ __launch_bounds__(kThreads) void stage_apply_kernel(VolumeDev vol, StageDev stg) {
+  __shared__ float s_sum[kApplyWaves][TSDF_BLOCK_VOXELS];
+  __shared__ unsigned s_cnt[kApplyWaves][TSDF_BLOCK_VOXELS];
+  const unsigned wv = threadIdx.x / kWave, lane = lane_id();
+  const unsigned n_items = stg.head[2] < stg.item_cap ? stg.head[2] : stg.item_cap;
+  float* const sum = s_sum[wv];
+  unsigned* const cnt = s_cnt[wv];
+  constexpr unsigned kGrab = 8;  // items per queue atomic: one counter serves every wave
+  for (;;) {
+    unsigned t0 = 0;
+    if (lane == 0) t0 = add_u32(stg.head + 3, kGrab);
+    t0 = (unsigned)__builtin_amdgcn_readfirstlane((int)t0);
+    if (t0 >= n_items) break;
+    for (unsigned t = t0; t < t0 + kGrab && t < n_items; ++t) {
+    const unsigned blk = stg.items[2u * t], part = stg.items[2u * t + 1u];
+    const unsigned long long stat = stg.block_stat[blk];
+    const unsigned runs_listed = (unsigned)(stat >> 32);
+    const unsigned n_runs = runs_listed < kStageRuns ? runs_listed : kStageRuns;
+    const unsigned parts = ((unsigned)stat + kStageItemRecords - 1) / kStageItemRecords;
+    stage_sum_runs(stg, blk, n_runs, part, parts, sum, cnt);
+    float* const bp = vol.voxels + (size_t)blk * kBlockFloats;
+#pragma unroll
+    for (unsigned q = 0; q < 16; ++q) {
+      const unsigned row = q * 4u + (lane >> 4), e = lane & 15u;  // e < 8: sums, else weights
+      const unsigned loc = row * 8u + (e & 7u);
+      const unsigned c = cnt[loc];
+      if (c) add_f32(bp + row * 16u + e, e < 8u ? sum[loc] : (float)c);
+    }
+    }
+  }
+}
+
+hipError_t launch_stage_apply(VolumeDev vol, const StageDev& stage, hipStream_t s) {
+  // a fixed grid of resident workgroups (16 KiB of LDS each, eight per CU)
+  // taking items until the queue is empty
+  int dev = 0, n_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  const unsigned grid = (unsigned)(n_cu > 0 ? n_cu : 1) * 8u;
+  hipLaunchKernelGGL(stage_apply_kernel, dim3(grid), dim3(kThreads), 0, s, vol, stage);
+  return hipGetLastError();
+}
+
+hipError_t launch_stage(VolumeDev vol, const WalkParams& wp, const FrameDev* frames, int n,
+                        int frames_per_group, const StageDev& stage, hipStream_t s) {
+  switch (wp.K) {
+    case 1: return launch_stage_band1(vol, wp, frames, n, frames_per_group, stage, s);
+    case 2: return launch_stage_band2(vol, wp, frames, n, frames_per_group, stage, s);
+    case 3: return launch_stage_band3(vol, wp, frames, n, frames_per_group, stage, s);
+    case 4: return launch_stage_band4(vol, wp, frames, n, frames_per_group, stage, s);
+    case 5: return launch_stage_band5(vol, wp, frames, n, frames_per_group, stage, s);
+    case 6: return launch_stage_band6(vol, wp, frames, n, frames_per_group, stage, s);
+    case 7: return launch_stage_band7(vol, wp, frames, n, frames_per_group, stage, s);
+    case 8: return launch_stage_band8(vol, wp, frames, n, frames_per_group, stage, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 int max_frames_per_group(int K) {
   return K >= 1 && K <= TSDF_MAX_BAND_HALF ? max_frames_for(K) : 0;
 }

@@ -27,6 +27,7 @@ FLAG_OVERFLOW_RECORD_FULL = 0x10
 OVERFLOW_KEY_SLOTS = 8192
 FUSE_DEFAULT, FUSE_TWO_PASS, FUSE_ALLOCATE_ONLY, FUSE_INTEGRATE_ONLY = 0, 1, 2, 3
 FUSE_XCD_REMAP = 0x100
+FUSE_ONE_STREAM = 0x200
 VOLUME_SLOT_INDEX, VOLUME_COLOUR, VOLUME_PROBE_HISTOGRAM = 0x1, 0x2, 0x4
 PROBE_HIST_BINS = 16
 
@@ -41,7 +42,7 @@ EMPTY_KEY = 0xFFFFFFFFFFFFFFFF
 EXPORTED_SYMBOLS = (
     "tsdf_volume_bytes", "tsdf_volume_layout", "tsdf_create_volume", "tsdf_destroy_volume",
     "tsdf_reset_volume", "tsdf_fuse_frame", "tsdf_fuse_frame_ex", "tsdf_fuse_frames",
-    "tsdf_fuse_frames_rgb",
+    "tsdf_fuse_frames_rgb", "tsdf_staging_bytes", "tsdf_fuse_frames_staged",
     "tsdf_query_status", "tsdf_probe_histogram", "tsdf_measure_atomic_rate",
     "tsdf_extract_blocks", "tsdf_extract_mesh", "tsdf_insert_blocks", "tsdf_status_str",
     "tsdf_fuse_frame_rgb", "tsdf_extract_colour",
@@ -146,6 +147,10 @@ def lib() -> C.CDLL:
         L.tsdf_fuse_frames.argtypes = [P, U32, P, P, U32, P]
         L.tsdf_fuse_frames_rgb.restype = I
         L.tsdf_fuse_frames_rgb.argtypes = [P, U32, P, P, P, U32, P]
+        L.tsdf_staging_bytes.restype = C.c_size_t
+        L.tsdf_staging_bytes.argtypes = [U32, C.c_uint64]
+        L.tsdf_fuse_frames_staged.restype = I
+        L.tsdf_fuse_frames_staged.argtypes = [P, U32, P, P, U32, P, C.c_size_t, P]
         L.tsdf_query_status.restype = I
         L.tsdf_query_status.argtypes = [P, P, C.POINTER(StatsC)]
         L.tsdf_probe_histogram.restype = I
@@ -245,6 +250,22 @@ def layout(p: VolumeParams) -> LayoutC:
     if st != OK:
         raise TsdfError(st, "tsdf_volume_layout")
     return out
+
+
+def staging_bytes(pool_capacity: int, records: int) -> int:
+    """Bytes of staging memory for tsdf_fuse_frames_staged holding `records`
+    records per launch (0 if invalid)."""
+    return int(lib().tsdf_staging_bytes(pool_capacity, records))
+
+
+def staging_buffer(pool_capacity: int, records: int = 32 * 640 * 480 * 9,
+                   device: str | torch.device = "cuda") -> torch.Tensor:
+    """A device byte tensor to hand to ``Volume.fuse_frames_staged``; the
+    default holds every record of 32 frames of 640x480 with a 9-sample band."""
+    n = staging_bytes(pool_capacity, records)
+    if n == 0:
+        raise TsdfError(ERR_INVALID_ARGUMENT, "tsdf_staging_bytes")
+    return torch.empty(n, dtype=torch.uint8, device=device)
 
 
 def measure_atomic_rate(buf: torch.Tensor, waves: int, iters: int, rows_per_instr: int,
@@ -446,6 +467,30 @@ class Volume(_VolumeCalls):
         st = lib().tsdf_fuse_frames(self._h, n, ptrs, cam_arr, flags, _stream_ptr(stream))
         if st != OK:
             raise TsdfError(st, "tsdf_fuse_frames")
+
+    def fuse_frames_staged(self, depths: Sequence[torch.Tensor], cams, staging: torch.Tensor,
+                           flags: int = 0, stream=None) -> None:
+        """tsdf_fuse_frames_staged: as fuse_frames, the per-voxel sums gathered
+        per block in ``staging`` (a device byte tensor, e.g. staging_buffer)
+        and added to the pool once per launch."""
+        n = len(depths)
+        structs = [c if isinstance(c, CameraC) else camera_struct(c) for c in cams]
+        if len(structs) != n:
+            raise ValueError("one camera per frame")
+        for d, c in zip(depths, structs):
+            if d.dtype != torch.float32 or not d.is_cuda or not d.is_contiguous():
+                raise TypeError("depth must be a contiguous float32 device tensor")
+            if d.numel() != c.width * c.height:
+                raise ValueError("depth size does not match the camera")
+        if staging.dtype != torch.uint8 or not staging.is_cuda:
+            raise TypeError("staging must be a device byte tensor")
+        ptrs = (C.c_void_p * max(n, 1))(*[d.data_ptr() for d in depths])
+        cam_arr = (CameraC * max(n, 1))(*structs)
+        st = lib().tsdf_fuse_frames_staged(self._h, n, ptrs, cam_arr, flags,
+                                           C.c_void_p(staging.data_ptr()), staging.numel(),
+                                           _stream_ptr(stream))
+        if st != OK:
+            raise TsdfError(st, "tsdf_fuse_frames_staged")
 
     def fuse_frames_rgb(self, depths: Sequence[torch.Tensor], rgbas: Sequence[torch.Tensor], cams,
                         flags: int = 0, stream=None) -> None:

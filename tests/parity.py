@@ -37,13 +37,18 @@ class GpuResult:
 
 def run_gpu(voxel_size, trunc, table_capacity, pool_capacity, depths: Sequence[np.ndarray], cams,
             prefill_blocks=None, flags=T.FUSE_DEFAULT, keep_volume=False,
-            vol: Optional[T.Volume] = None, batched: bool = False) -> GpuResult:
+            vol: Optional[T.Volume] = None, batched: bool = False,
+            staged: Optional[int] = None) -> GpuResult:
+    """Fuse through one launch per frame, tsdf_fuse_frames (`batched`), or
+    tsdf_fuse_frames_staged with staging for `staged` records per launch."""
     if vol is None:
         vol = T.Volume(voxel_size, trunc, table_capacity, pool_capacity)
     if prefill_blocks is not None:
         vol.insert_blocks(torch.from_numpy(np.ascontiguousarray(prefill_blocks, dtype=np.int32)).cuda())
     dev = [torch.from_numpy(np.ascontiguousarray(d, dtype=np.float32)).cuda() for d in depths]
-    if batched:
+    if staged is not None:
+        vol.fuse_frames_staged(dev, cams, T.staging_buffer(pool_capacity, staged), flags)
+    elif batched:
         vol.fuse_frames(dev, cams, flags)
     else:
         for d, c in zip(dev, cams):

@@ -205,3 +205,21 @@ def test_binding_structs_match_the_header(struct, mirror):
     assert C.sizeof(cls) == c["sizeof"]
     if struct == "tsdf_stats":
         assert {"blocks_new", "keys_table_overflow", "keys_pool_overflow"} <= set(names)
+
+
+def test_staging_bytes_and_refusals_without_a_gpu():
+    L = T.lib()
+    P = 1 << 11
+    r = lambda x: (x + 255) // 256 * 256
+
+    def set_bytes(rec):
+        # header, per block 8 bytes and a 128-entry run table, the work items
+        # (one per 1024 records of a block: at most rec / 1024 + P + 1), the records
+        items = rec // 1024 + P + 1
+        return r(r(r(r(256 + 8 * P) + 8 * 128 * P) + 8 * items) + 4 * rec)
+    for rec in (1 << 16, 10 ** 7):
+        assert T.staging_bytes(P, rec) == 2 * set_bytes(rec)
+    for pool, rec in ((0, 1 << 16), (1 << 22, 1 << 16), (P, (1 << 16) - 1), (P, 0), (P, 1 << 32)):
+        assert T.staging_bytes(pool, rec) == 0, (pool, rec)
+    assert L.tsdf_fuse_frames_staged(None, 0, None, None, 0, C.c_void_p(256), 1 << 30,
+                                     None) == T.ERR_INVALID_ARGUMENT
