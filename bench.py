@@ -902,7 +902,7 @@ def main() -> int:
     ap.add_argument("--duration", type=float, default=1.0, help="serve: seconds of arrivals")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="serve: session budget")
     ap.add_argument("--max-batch", type=int, default=256, help="serve: frames per launch")
-    ap.add_argument("--max-inflight", type=int, default=2, help="serve: launches in flight")
+    ap.add_argument("--max-inflight", type=int, default=4, help="serve: launches in flight, one stream each")
     ap.add_argument("--volumes", type=int, default=64, help="multi: volumes per tick")
     ap.add_argument("--trials", type=int, default=2, help="multi: autotuner trials per candidate")
     ap.add_argument("--batch-config", default="",

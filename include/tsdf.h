@@ -557,16 +557,24 @@ tsdf_status tsdf_region_usage(const tsdf_region* region, uint64_t* capacity, uin
  *
  * The server is driven from one host thread: tsdf_server_submit queues,
  * tsdf_server_step retires finished launches and starts new ones, and
- * tsdf_server_completions hands back the tags of finished frames.  All device
- * work goes to the stream given at creation.  Depth frames must stay valid
- * until their tags come back.
+ * tsdf_server_completions hands back the tags of finished frames.  Each launch
+ * in flight has a stream of its own: the stream given at creation and
+ * max_inflight - 1 streams the server makes (default priority), so launches
+ * overlap on the device and a frame that arrives while others are fused
+ * starts at once; launches into one volume may run together (fusion is a sum
+ * of atomic updates, so the result is that of fusing the frames one by one,
+ * up to the order of the fp32 additions).  Volume initialisation
+ * and the plain launches of tsdf_server_replay use the stream given at
+ * creation; status and extraction calls on a session's volume belong on that
+ * stream too, after tsdf_server_step has retired the session's launches.
+ * Depth frames must stay valid until their tags come back.
  * ------------------------------------------------------------------------- */
 typedef struct tsdf_server tsdf_server;
 
 typedef struct tsdf_server_params {
   uint32_t max_sessions;  /* 1 .. 65536 */
   uint32_t max_batch;     /* frames per launch, 1 .. TSDF_BATCH_MAX_ITEMS */
-  uint32_t max_inflight;  /* launches running at once, 1 .. 16 */
+  uint32_t max_inflight;  /* launches running at once, one stream each, 1 .. 4 */
   uint32_t max_queue;     /* frames waiting, max_batch .. 2^24 */
 } tsdf_server_params;
 

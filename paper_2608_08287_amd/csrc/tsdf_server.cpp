@@ -3,10 +3,17 @@
 // through tsdf_batch_fuse, per-session failure marking, and a real-time
 // replay driver for arrival traces.
 //
-// Ordering: every device operation of a server (volume initialisation, work
-// list copies, fusion launches, status gathers, plain launches of a replay)
-// goes to the one stream given at creation, so launches retire in the order
-// they were made and one event per launch tells when its frames are fused.
+// Ordering: a server has max_inflight streams: the one given at creation and
+// max_inflight - 1 of its own (default priority).  Volume initialisation and
+// the plain launches of a replay go to the first; each fusion launch (its work
+// list copy, kernels and status gather) goes to a stream that has no launch
+// running, so launches overlap on the device and a frame that arrives while
+// others are being fused starts at once.  Launches may finish out of order;
+// one event per launch tells when its frames are fused.  A session's volume is
+// initialised on the first stream, and the other streams wait for an event
+// recorded behind that before any launch can reach the volume.  Launches into
+// one volume may run at once on different streams: fusion is a sum, and every
+// update the kernels make is an atomic one.
 
 #include <chrono>
 #include <deque>
@@ -20,7 +27,7 @@ using namespace tsdf_host;
 namespace {
 
 constexpr uint32_t kMaxSessions = 65536;
-constexpr uint32_t kMaxInflight = 4;  // the batch's staging ring has 4 slots
+constexpr uint32_t kMaxInflight = 4;  // one stream per launch; within the device's hardware queues
 constexpr uint32_t kMaxQueue = 1u << 24;
 
 struct Session {
@@ -44,6 +51,7 @@ struct Pending {
 // passed, so the status copy stays off the frames' latency.
 struct Launch {
   uint64_t seq;
+  uint32_t stream;  // index into the server's streams
   hipEvent_t done;
   hipEvent_t gathered;
   bool frames_retired = false;
@@ -75,7 +83,10 @@ double now_ns() {
 
 struct tsdf_server {
   tsdf_server_params p;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;        // the caller's: streams[0]
+  std::vector<hipStream_t> streams;    // one per launch in flight
+  std::vector<bool> stream_busy;
+  hipEvent_t opened = nullptr;         // behind the latest volume initialisation
   tsdf_batch* batch = nullptr;
   tsdf_region* region = nullptr;
   std::vector<Session> sessions;
@@ -88,7 +99,9 @@ struct tsdf_server {
   uint64_t next_seq = 0;
   uint32_t inflight_frames = 0;
   // pinned, device-mapped mirrors: counters pointer per session (read by the
-  // gather kernel) and the sticky status it copies out
+  // gather kernel) and the sticky status it copies out, one row of
+  // max_sessions words per stream, so that a gather running late on one stream
+  // never overwrites what a later gather on another stream wrote
   tsdf::DevCounters** ctr_host = nullptr;
   tsdf::DevCounters** ctr_dev = nullptr;
   unsigned* status_host = nullptr;
@@ -112,13 +125,13 @@ hipError_t poll(hipEvent_t ev, bool wait) {
 }
 
 // Hand back the frames of launches that have finished, and read the status
-// words of those whose status copy has finished.  Launches retire in order
-// (one stream).  Non-blocking unless `wait_all`.
+// words of those whose status copy has finished.  Launches on different
+// streams finish in any order.  Non-blocking unless `wait_all`.
 tsdf_status retire(tsdf_server* s, bool wait_all) {
   for (Launch& L : s->inflight) {
     if (L.frames_retired) continue;
     const hipError_t e = poll(L.done, wait_all);
-    if (e == hipErrorNotReady) break;
+    if (e == hipErrorNotReady) continue;
     if (e != hipSuccess) return TSDF_ERR_HIP;
     for (size_t i = 0; i < L.tags.size(); ++i) {
       s->done.emplace_back(L.tags[i], (int32_t)TSDF_OK);
@@ -127,22 +140,33 @@ tsdf_status retire(tsdf_server* s, bool wait_all) {
     s->inflight_frames -= (uint32_t)L.tags.size();
     L.frames_retired = true;
     --s->running;
+    // a new launch on this stream queues behind the small status copy only
+    s->stream_busy[L.stream] = false;
   }
-  while (!s->inflight.empty() && s->inflight.front().frames_retired) {
-    Launch& L = s->inflight.front();
+  for (auto it = s->inflight.begin(); it != s->inflight.end();) {
+    Launch& L = *it;
+    if (!L.frames_retired) {
+      ++it;
+      continue;
+    }
     const hipError_t e = poll(L.gathered, wait_all);
-    if (e == hipErrorNotReady) break;
+    if (e == hipErrorNotReady) {
+      ++it;
+      continue;
+    }
     if (e != hipSuccess) return TSDF_ERR_HIP;
-    // statuses copied behind this launch are current for sessions opened
-    // before it was made
+    // statuses copied behind this launch, or behind a later one on its stream,
+    // are current for sessions opened before it was made (status bits are only
+    // ever set while a session is open)
+    const unsigned* row = s->status_host + (size_t)L.stream * s->p.max_sessions;
     for (uint32_t id = 0; id < s->p.max_sessions; ++id) {
       Session& ss = s->sessions[id];
       if (!ss.open || ss.failure != TSDF_OK || L.seq < ss.opened_at) continue;
-      ss.failure = failure_of(__atomic_load_n(&s->status_host[id], __ATOMIC_ACQUIRE));
+      ss.failure = failure_of(__atomic_load_n(&row[id], __ATOMIC_ACQUIRE));
     }
     s->spare_events.push_back(L.done);
     s->spare_events.push_back(L.gathered);
-    s->inflight.pop_front();
+    it = s->inflight.erase(it);
   }
   return TSDF_OK;
 }
@@ -173,6 +197,11 @@ tsdf_status launch_one(tsdf_server* s, uint32_t* launched) {
     L.tags.push_back(q.tag);
   }
   if (s->items.empty()) return TSDF_OK;
+  uint32_t k = 0;
+  while (k < s->streams.size() && s->stream_busy[k]) ++k;
+  if (k == s->streams.size()) return TSDF_ERR_INTERNAL;  // the caller checked for room
+  hipStream_t st_k = s->streams[k];
+  L.stream = k;
   if (!take_event(s, &L.done)) return TSDF_ERR_HIP;
   if (!take_event(s, &L.gathered)) {
     s->spare_events.push_back(L.done);
@@ -182,20 +211,21 @@ tsdf_status launch_one(tsdf_server* s, uint32_t* launched) {
   // search.  Several frames share one persistent launch.
   const tsdf_fuse_item& one = s->items[0];
   tsdf_status st = s->items.size() == 1
-                       ? tsdf_fuse_frame(one.volume, one.depth_dev, &one.camera, s->stream)
+                       ? tsdf_fuse_frame(one.volume, one.depth_dev, &one.camera, st_k)
                        : tsdf_batch_fuse(s->batch, s->items.data(), (uint32_t)s->items.size(), 0,
-                                         s->stream);
-  if (st == TSDF_OK) st = hip_status(hipEventRecord(L.done, s->stream));
+                                         st_k);
+  if (st == TSDF_OK) st = hip_status(hipEventRecord(L.done, st_k));
   if (st == TSDF_OK)
-    st = hip_status(tsdf::launch_gather_status(s->ctr_dev, s->p.max_sessions, s->status_dev,
-                                               s->stream));
-  if (st == TSDF_OK) st = hip_status(hipEventRecord(L.gathered, s->stream));
+    st = hip_status(tsdf::launch_gather_status(
+        s->ctr_dev, s->p.max_sessions, s->status_dev + (size_t)k * s->p.max_sessions, st_k));
+  if (st == TSDF_OK) st = hip_status(hipEventRecord(L.gathered, st_k));
   if (st != TSDF_OK) {
     s->spare_events.push_back(L.done);
     s->spare_events.push_back(L.gathered);
     return st;
   }
   L.seq = s->next_seq++;
+  s->stream_busy[k] = true;
   for (uint32_t id : L.sessions) ++s->sessions[id].inflight;
   s->inflight_frames += (uint32_t)L.tags.size();
   ++s->running;
@@ -205,7 +235,7 @@ tsdf_status launch_one(tsdf_server* s, uint32_t* launched) {
 }
 
 void free_server(tsdf_server* s) {
-  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  for (hipStream_t st : s->streams) (void)hipStreamSynchronize(st);
   for (uint32_t id = 0; id < s->sessions.size(); ++id)
     if (s->sessions[id].open) release_session(s, id);
   for (Launch& L : s->inflight) {
@@ -213,6 +243,8 @@ void free_server(tsdf_server* s) {
     s->spare_events.push_back(L.gathered);
   }
   for (hipEvent_t ev : s->spare_events) (void)hipEventDestroy(ev);
+  if (s->opened) (void)hipEventDestroy(s->opened);
+  for (size_t k = 1; k < s->streams.size(); ++k) (void)hipStreamDestroy(s->streams[k]);
   if (s->batch) (void)tsdf_batch_destroy(s->batch);
   if (s->region) (void)tsdf_region_destroy(s->region);
   if (s->ctr_host) (void)hipHostFree(s->ctr_host);
@@ -241,7 +273,16 @@ tsdf_status tsdf_server_create(const tsdf_server_params* params, void* workspace
   if (!s) return TSDF_ERR_INTERNAL;
   s->p = *params;
   s->stream = as_stream(hip_stream);
-  tsdf_status st = tsdf_region_create(session_region_dev, budget_bytes, &s->region);
+  s->streams.push_back(s->stream);
+  tsdf_status st = TSDF_OK;
+  for (uint32_t k = 1; k < params->max_inflight && st == TSDF_OK; ++k) {
+    hipStream_t extra = nullptr;
+    st = hip_status(hipStreamCreateWithFlags(&extra, hipStreamNonBlocking));
+    if (st == TSDF_OK) s->streams.push_back(extra);
+  }
+  s->stream_busy.assign(s->streams.size(), false);
+  if (st == TSDF_OK) st = hip_status(hipEventCreateWithFlags(&s->opened, hipEventDisableTiming));
+  if (st == TSDF_OK) st = tsdf_region_create(session_region_dev, budget_bytes, &s->region);
   if (st == TSDF_OK)
     st = tsdf_batch_create(params->max_batch, workspace_dev, workspace_bytes, &s->batch);
   const size_t n = params->max_sessions;
@@ -249,8 +290,8 @@ tsdf_status tsdf_server_create(const tsdf_server_params* params, void* workspace
     st = hip_status(hipHostMalloc(reinterpret_cast<void**>(&s->ctr_host), n * sizeof(void*),
                                   hipHostMallocMapped));
   if (st == TSDF_OK)
-    st = hip_status(hipHostMalloc(reinterpret_cast<void**>(&s->status_host), n * sizeof(unsigned),
-                                  hipHostMallocMapped));
+    st = hip_status(hipHostMalloc(reinterpret_cast<void**>(&s->status_host),
+                                  n * s->streams.size() * sizeof(unsigned), hipHostMallocMapped));
   if (st == TSDF_OK)
     st = hip_status(hipHostGetDevicePointer(reinterpret_cast<void**>(&s->ctr_dev), s->ctr_host, 0));
   if (st == TSDF_OK)
@@ -260,10 +301,8 @@ tsdf_status tsdf_server_create(const tsdf_server_params* params, void* workspace
     free_server(s);
     return st;
   }
-  for (size_t i = 0; i < n; ++i) {
-    s->ctr_host[i] = nullptr;
-    s->status_host[i] = 0;
-  }
+  for (size_t i = 0; i < n; ++i) s->ctr_host[i] = nullptr;
+  for (size_t i = 0; i < n * s->streams.size(); ++i) s->status_host[i] = 0;
   s->sessions.resize(n);
   s->items.reserve(params->max_batch);
   *out = s;
@@ -289,7 +328,12 @@ tsdf_status tsdf_server_open(tsdf_server* s, const tsdf_volume_params* params,
   if (st != TSDF_OK) return st;
   tsdf_volume* vol = nullptr;
   st = tsdf_create_volume(params, arena, bytes, s->stream, &vol);
+  // the other streams reach the volume only after its initialisation
+  if (st == TSDF_OK) st = hip_status(hipEventRecord(s->opened, s->stream));
+  for (size_t k = 1; k < s->streams.size() && st == TSDF_OK; ++k)
+    st = hip_status(hipStreamWaitEvent(s->streams[k], s->opened, 0));
   if (st != TSDF_OK) {
+    if (vol) (void)tsdf_destroy_volume(vol);
     (void)tsdf_region_free(s->region, arena);
     return st;
   }

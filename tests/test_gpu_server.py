@@ -298,3 +298,26 @@ def test_queue_limit_and_close_with_queued_frames():
     assert server.load()["queued"] == 0
     assert server.submit(ids[1], depths[0], cams[0], 7) == T.OK
     assert drain(server, 1) == {7: T.OK}
+
+
+def test_concurrent_launches_into_one_volume_equal_fusing_alone():
+    """One session, frames launched one per launch on four streams at once:
+    the launches fuse into the same volume concurrently and it ends as the
+    frames fused one by one."""
+    w = S.ServingWorkload(1, rate=4000.0, duration_s=0.005, seed=27, sizes=((320, 240),),
+                          log2_pools=(18, 18))
+    depths, cams = frames_of(w)
+    server = T.Server(budget_for(w), max_sessions=2, max_batch=1, max_inflight=4, max_queue=256)
+    sid = open_all(server, w)[0]
+    for j, (d, c) in enumerate(zip(depths, cams)):
+        assert server.submit(sid, d, c, j) == T.OK
+    most = 0
+    for _ in range(8):
+        server.step()
+        most = max(most, server.load()["inflight_launches"])
+    done = drain(server, len(w))
+    assert all(st == T.OK for st in done.values()) and len(w) >= 4, sorted(set(done.values()))
+    assert most >= 2, "no two launches were in flight together"
+    v, fail = server.session(sid)
+    st = assert_same_volume(v, alone(w, depths, cams)[0])
+    assert fail == T.OK and st.frames == len(w)
