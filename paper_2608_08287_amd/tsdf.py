@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import sys
 from dataclasses import dataclass
 from typing import Optional, Sequence, Tuple
 
@@ -118,6 +119,45 @@ class TsdfError(RuntimeError):
 
 
 _lib = None
+_hip = None
+
+
+def _finalise(obj) -> None:
+    """Release an object's library handle when it is garbage-collected, but
+    not during interpreter shutdown: by then the HIP runtime (or a profiler
+    hooked into it) may already be torn down, so the process leaves the memory
+    to the operating system.  Code that needs the memory back, or a clean exit
+    under a profiler, calls close() itself."""
+    if sys.is_finalizing():
+        return
+    try:
+        obj.close()
+    except Exception:
+        pass
+
+
+def hip_runtime() -> C.CDLL:
+    """The HIP runtime this process already has loaded (torch's, which
+    libtsdf.so binds to as well), never a second copy."""
+    global _hip
+    if _hip is None:
+        lib()
+        try:
+            _hip = C.CDLL("libamdhip64.so.7", mode=os.RTLD_NOLOAD | os.RTLD_LAZY)
+        except OSError as e:
+            raise RuntimeError("the HIP runtime is not loaded in this process") from e
+        _hip.hipHostGetDevicePointer.restype = C.c_int
+        _hip.hipHostGetDevicePointer.argtypes = [C.POINTER(C.c_void_p), C.c_void_p, C.c_uint]
+    return _hip
+
+
+def host_device_pointer(host_ptr: int) -> Optional[int]:
+    """Device address of pinned host memory (hipHostGetDevicePointer), or None
+    when the runtime gives it none."""
+    dp = C.c_void_p()
+    if hip_runtime().hipHostGetDevicePointer(C.byref(dp), C.c_void_p(host_ptr), 0) != 0:
+        return None
+    return dp.value or None
 
 
 def lib() -> C.CDLL:
@@ -407,10 +447,7 @@ class Volume(_VolumeCalls):
             self._h = C.c_void_p()
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        _finalise(self)
 
     @property
     def handle(self) -> C.c_void_p:
@@ -619,10 +656,7 @@ class Batch:
             self._h = C.c_void_p()
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        _finalise(self)
 
     def set_config(self, cfg: BatchConfig) -> None:
         c = BatchConfigC(cfg.tile_width, cfg.pixels_per_thread, cfg.acc_blocks, cfg.groups_per_cu)
@@ -705,10 +739,7 @@ class Region:
             self._h = C.c_void_p()
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        _finalise(self)
 
     def alloc(self, nbytes: int) -> Optional[int]:
         """Device address of a new range, or None when nothing fits."""
@@ -788,10 +819,7 @@ class Server:
             self._h = C.c_void_p()
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        _finalise(self)
 
     def open(self, voxel_size: float, trunc: float, table_capacity: int,
              pool_capacity: int) -> Optional[int]:

@@ -55,3 +55,49 @@ def test_several_gpus_are_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_host_report_names_the_cpu():
+    h = bench.host_info()
+    assert h["nproc"] == os.cpu_count() and 1 <= h["usable_cpus"] <= h["nproc"]
+    assert h["cpu_model"] is None or isinstance(h["cpu_model"], str)
+    assert 1 <= bench.cpu_threads() <= 16
+
+
+def test_medians_over_passes():
+    assert bench.med([3.0, 1.0, 2.0]) == 2.0
+    assert bench.med([5.0]) == 5.0
+
+
+def test_a_gpu_held_by_another_process_is_refused(monkeypatch):
+    """With HBM already in use before the run, nothing is built or timed and
+    the exit status is 3."""
+    import torch
+
+    monkeypatch.setattr(torch.cuda, "is_available", lambda: True)
+    monkeypatch.setattr(torch.cuda, "set_device", lambda d: None)
+    monkeypatch.setattr(bench, "check_idle",
+                        lambda torch_: {"shared": True, "hbm_in_use_gib": 9.0})
+    built = []
+    monkeypatch.setattr(bench, "trajectory_leg", lambda *a: built.append(a))
+    args = bench.argparse.Namespace(allow_shared_gpu=False)
+    assert bench.run_legs(args, ["trajectory"]) == 3
+    assert built == []
+
+
+def test_shared_threshold_is_applied(monkeypatch):
+    class Cuda:
+        @staticmethod
+        def mem_get_info():
+            return (100 << 30, 288 << 30)
+
+        @staticmethod
+        def memory_reserved():
+            return 0
+
+    class FakeTorch:
+        cuda = Cuda
+
+    monkeypatch.setenv("ROCPROF_FAKE", "1")  # skips the rocm-smi query
+    st = bench.check_idle(FakeTorch)
+    assert st["shared"] and st["hbm_in_use_gib"] == pytest.approx(188.0)

@@ -558,16 +558,10 @@ def test_frames_read_from_pinned_host_memory():
     host = torch.empty((n, H, W), dtype=torch.float32, pin_memory=True)
     for k in range(n):
         host[k].copy_(torch.from_numpy(w.depth[k]))
-    hip = ctypes.CDLL("libamdhip64.so.7")
-    hip.hipHostGetDevicePointer.restype = ctypes.c_int
-    hip.hipHostGetDevicePointer.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p,
-                                            ctypes.c_uint]
     dptr = (ctypes.c_void_p * n)()
     for k in range(n):
-        dp = ctypes.c_void_p()
-        assert hip.hipHostGetDevicePointer(ctypes.byref(dp), host[k].data_ptr(), 0) == 0
-        assert dp.value
-        dptr[k] = dp.value
+        dptr[k] = T.host_device_pointer(host[k].data_ptr())
+        assert dptr[k]
     cams = (T.CameraC * n)(*[T.camera_struct(c) for c in w.cameras])
     sp = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     L = T.lib()

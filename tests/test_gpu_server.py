@@ -96,24 +96,16 @@ def test_sessions_served_from_pinned_host_frames():
     """Frames in pinned host memory, submitted at their device addresses, are
     read by the kernels over PCIe: every session ends as when its frames are
     fused alone from device memory."""
-    import ctypes
-
     w = S.ServingWorkload(8, rate=2000.0, duration_s=0.03, seed=24, sizes=SMALL,
                           log2_pools=(15, 16))
     depths, cams = frames_of(w)
-    hip = ctypes.CDLL("libamdhip64.so.7")
-    hip.hipHostGetDevicePointer.restype = ctypes.c_int
-    hip.hipHostGetDevicePointer.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p,
-                                            ctypes.c_uint]
 
     class Mapped:  # a pinned frame known by its device address
         def __init__(self, t):
             self.host = torch.empty(t.shape, dtype=t.dtype, pin_memory=True)
             self.host.copy_(t)
-            dp = ctypes.c_void_p()
-            assert hip.hipHostGetDevicePointer(ctypes.byref(dp), self.host.data_ptr(), 0) == 0
-            assert dp.value
-            self.addr = dp.value
+            self.addr = T.host_device_pointer(self.host.data_ptr())
+            assert self.addr
 
         def numel(self):
             return self.host.numel()
@@ -162,8 +154,8 @@ def test_served_sessions_match_the_oracle():
 def test_full_serving_trace_sampled_sessions_match_the_oracle():
     """The serving bench's trace at full size: 256 sessions, Poisson arrivals at
     3000 frames/s for one second, replayed in real time through the served path
-    in the bench's configuration (up to 256 frames per launch, 2 launches in
-    flight, 32-pixel-wide tiles, one pixel per thread).  Every session counts
+    in the bench's configuration (up to 256 frames per launch, 4 launches in
+    flight on streams of their own, 32-pixel-wide tiles, one pixel per thread).  Every session counts
     its own frames, and 32 sessions drawn with a fixed seed match the oracle
     (fused on threads; the oracle's calls release the interpreter lock)."""
     import os
@@ -174,7 +166,7 @@ def test_full_serving_trace_sampled_sessions_match_the_oracle():
               for s, k in zip(w.session_of, w.frame_of)]
     cams = [w.camera(int(s), int(k)) for s, k in zip(w.session_of, w.frame_of)]
     log(f"  rendered {len(w)} frames")
-    server = T.Server(budget_for(w), max_sessions=len(w.specs), max_batch=256, max_inflight=2,
+    server = T.Server(budget_for(w), max_sessions=len(w.specs), max_batch=256, max_inflight=4,
                       max_queue=max(4096, len(w)))
     server.batch_config(T.BatchConfig(32, 1, 8, 0))
     ids = open_all(server, w)
@@ -202,6 +194,7 @@ def test_full_serving_trace_sampled_sessions_match_the_oracle():
         for i, o in zip(pick, ex.map(oracle_of, pick)):
             assert_parity(result_of(server.session(ids[i])[0]), o)
     log(f"  {len(w)} frames served; sessions {pick} match the oracle")
+    server.close()
     del server, depths
     torch.cuda.empty_cache()
 
