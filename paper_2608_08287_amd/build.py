@@ -31,13 +31,32 @@ FLAGS = ["-x", "hip", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
          "-Wall", "-Wno-unused-function", f"-I{os.path.join(ROOT, 'include')}"]
 
 
-def build(verbose: bool = False, extra=(), jobs: int = 0) -> str:
-    """Compile every translation unit in parallel, then link libtsdf.so."""
-    os.makedirs(BUILD_DIR, exist_ok=True)
+# Libraries built with one design alternative switched on, for measuring it
+# against the shipped choice (the switches are described in tsdf_device.h).
+# They load in place of libtsdf.so when TSDF_LIBRARY names them.
+VARIANTS = {
+    "first_read_coherent": ["-DTSDF_FIRST_READ_COHERENT=1"],
+    "keyset_ballot": ["-DTSDF_KEYSET_BALLOT=1"],
+}
+VARIANT_DIR = os.path.join(HERE, "variants")
+
+
+def variant_path(name: str) -> str:
+    return os.path.join(VARIANT_DIR, f"libtsdf_{name}.so")
+
+
+def build(verbose: bool = False, extra=(), jobs: int = 0, variant: str = "") -> str:
+    """Compile every translation unit in parallel, then link libtsdf.so (or,
+    with `variant`, the library of that design alternative)."""
+    extra = list(extra) + (VARIANTS[variant] if variant else [])
+    out = variant_path(variant) if variant else OUT
+    build_dir = BUILD_DIR + (f"_{variant}" if variant else "")
+    os.makedirs(build_dir, exist_ok=True)
+    os.makedirs(os.path.dirname(out), exist_ok=True)
     jobs = jobs or min(16, os.cpu_count() or 4)
 
     def compile_one(src):
-        obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
+        obj = os.path.join(build_dir, os.path.basename(src) + ".o")
         cmd = [HIPCC, *FLAGS, *extra, "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
@@ -53,13 +72,20 @@ def build(verbose: bool = False, extra=(), jobs: int = 0) -> str:
 
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(compile_one, SOURCES))
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", OUT + ".tmp"]
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", out + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(OUT + ".tmp", OUT)
-    return OUT
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv)
+    import argparse
+
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("-v", action="store_true", help="print the commands")
+    ap.add_argument("--variant", choices=sorted(VARIANTS), default="",
+                    help="build the library of one design alternative instead")
+    a = ap.parse_args()
+    print(build(verbose=a.v, variant=a.variant))

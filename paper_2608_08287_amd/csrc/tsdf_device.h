@@ -78,6 +78,23 @@ constexpr int kProbeAheadLong = 8;          // ... per later step, for tables th
 // INTERNAL instead of spinning forever.
 constexpr unsigned kMaxWaitSteps = 1u << 20;
 
+// Two design alternatives stay buildable so that they can be measured against
+// the shipped choice (both are off in the library; the build script's
+// --variant turns one on in a separate library):
+//   TSDF_FIRST_READ_COHERENT  the probe's first read of each entry is an
+//       agent-scope atomic load, as the wait's reads are, instead of a plain
+//       cacheable load;
+//   TSDF_KEYSET_BALLOT  a wave elects one lane per distinct key (ballot, then
+//       the leader's key broadcast) and only that lane inserts into the tile's
+//       LDS key set, instead of every lane inserting its own key.
+// Both give the same results as the shipped code.
+#ifndef TSDF_FIRST_READ_COHERENT
+#define TSDF_FIRST_READ_COHERENT 0
+#endif
+#ifndef TSDF_KEYSET_BALLOT
+#define TSDF_KEYSET_BALLOT 0
+#endif
+
 // ---------------------------------------------------------------------------
 // Keys and hashing
 // ---------------------------------------------------------------------------
@@ -240,8 +257,19 @@ __device__ int resolve_key(const VolumeDev& vol, unsigned long long want, bool a
 #pragma unroll
       for (int i = 0; i < kMax; ++i) {
         sl[i] = (i == 0) ? slot : ((sl[i - 1] + 1 == C) ? 0u : sl[i - 1] + 1);
-        if ((unsigned)i < n_read) en[i] = vol.table[sl[i]];
-        else en[i] = TableEntry{0ull, 0, 0u};  // not read: never a candidate
+        if ((unsigned)i < n_read) {
+#if TSDF_FIRST_READ_COHERENT
+          en[i].key = __hip_atomic_load(&vol.table[sl[i]].key, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+          en[i].block = __hip_atomic_load(&vol.table[sl[i]].block, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+          en[i].pad = 0u;
+#else
+          en[i] = vol.table[sl[i]];
+#endif
+        } else {
+          en[i] = TableEntry{0ull, 0, 0u};  // not read: never a candidate
+        }
       }
       // the first candidate in probe order (compile-time indices only, so the
       // read-ahead stays in registers)
@@ -399,6 +427,24 @@ __device__ __forceinline__ Sample walk_sample(const FrameDev& f, const WalkParam
   s.keep = s.in_range && (zcv > 0.0f) && !(sdf < -wp.trunc);
   s.val = sdf < wp.trunc ? sdf : wp.trunc;
   return s;
+}
+
+// Insert a block key into a tile's LDS key set (open addressing, linear
+// probe): its slot, found or claimed, or kSetNone when the set is full.  A
+// claimed slot is appended to the set's list of distinct keys.
+__device__ __forceinline__ unsigned set_insert(unsigned long long* s_keys, unsigned short* s_list,
+                                               unsigned* s_n, unsigned long long key) {
+  unsigned h = set_home(key);
+  for (unsigned i = 0; i < kSetCap; ++i) {
+    const unsigned long long old = atomicCAS(&s_keys[h], kEmptyKey, key);
+    if (old == kEmptyKey) {
+      s_list[atomicAdd(s_n, 1u)] = (unsigned short)h;
+      return h;
+    }
+    if (old == key) return h;
+    h = (h + 1) & (kSetCap - 1);
+  }
+  return kSetNone;
 }
 
 // Per-sample state carried from phase 1 to phase 3 in one register:
@@ -563,26 +609,23 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
       // consecutive samples of a point mostly share a block: reuse its slot
       const bool need = cand && key != prev_key;
       unsigned slot = prev_slot;
-      if (need) {
-        // every lane inserts its own key; the LDS serialises lanes of one wave
-        // that aim at the same slot, so exactly one of them claims it and the
-        // others find the key there
-        unsigned h = set_home(key);
-        slot = kSetNone;
-        for (unsigned i = 0; i < kSetCap; ++i) {
-          const unsigned long long old = atomicCAS(&s_keys[h], kEmptyKey, key);
-          if (old == kEmptyKey) {
-            s_list[atomicAdd(s_n, 1u)] = (unsigned short)h;
-            slot = h;
-            break;
-          }
-          if (old == key) {
-            slot = h;
-            break;
-          }
-          h = (h + 1) & (kSetCap - 1);
-        }
+#if TSDF_KEYSET_BALLOT
+      for (unsigned long long todo = __ballot(need); todo != 0ull;) {
+        const int leader = __builtin_ctzll(todo);
+        const unsigned long long lk = __shfl(key, leader);
+        const bool same = need && key == lk;
+        unsigned ls = kSetNone;
+        if (__lane_id() == (unsigned)leader) ls = set_insert(s_keys, s_list, s_n, key);
+        ls = __shfl(ls, leader);
+        if (same) slot = ls;
+        todo &= ~__ballot(same);
       }
+#else
+      // every lane inserts its own key; the LDS serialises lanes of one wave
+      // that aim at the same slot, so exactly one of them claims it and the
+      // others find the key there
+      if (need) slot = set_insert(s_keys, s_list, s_n, key);
+#endif
       if (cand) {
         prev_key = key;
         prev_slot = slot;

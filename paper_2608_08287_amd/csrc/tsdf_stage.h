@@ -137,24 +137,7 @@ __device__ __forceinline__ void stage_tile(const VolumeDev& vol, const WalkParam
       // consecutive kept samples of a point mostly share a block: reuse its slot
       const bool need = cand && !(have_prev && bx == pbx && by == pby && bz == pbz);
       unsigned slot = prev_slot;
-      if (need) {
-        const unsigned long long key = pack_key(bx, by, bz);
-        unsigned h = set_home(key);
-        slot = kSetNone;
-        for (unsigned i = 0; i < kSetCap; ++i) {
-          const unsigned long long old = atomicCAS(&s_keys[h], kEmptyKey, key);
-          if (old == kEmptyKey) {
-            s_list[atomicAdd(s_n, 1u)] = (unsigned short)h;
-            slot = h;
-            break;
-          }
-          if (old == key) {
-            slot = h;
-            break;
-          }
-          h = (h + 1) & (kSetCap - 1);
-        }
-      }
+      if (need) slot = set_insert(s_keys, s_list, s_n, pack_key(bx, by, bz));
       if (cand) {
         have_prev = true;
         pbx = bx;

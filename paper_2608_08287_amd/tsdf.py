@@ -18,7 +18,9 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libtsdf.so")
+# TSDF_LIBRARY may name a library built from the same sources with one design
+# alternative switched on (build.py --variant), for measuring it.
+LIB_PATH = os.environ.get("TSDF_LIBRARY") or os.path.join(_HERE, "libtsdf.so")
 
 # tsdf_status
 OK, ERR_INVALID_ARGUMENT, ERR_BUFFER_TOO_SMALL, ERR_POOL_EXHAUSTED, ERR_TABLE_FULL, \
