@@ -1161,6 +1161,14 @@ def trajectory_leg(args, torch, T, S) -> Leg:
     ptr_arr = (T.C.c_void_p * len(ptrs))(*[d.data_ptr() for d in depth])
     cam_arr = (T.CameraC * len(cams))(*cams)
     bflags = T.FUSE_BATCH(args.per_group)
+    staged = args.accumulate == "staged"
+    if staged and (colour or slot):
+        raise GateFailed("--accumulate staged takes the main design's plain volumes only")
+    if staged:
+        # every record of fpl frames with the band's 2K+1 samples per pixel
+        stage_buf = T.staging_buffer(pool, fpl * n_pix * (2 * int(round(w.trunc / w.voxel_size)) + 1))
+        stage_ptr = T.C.c_void_p(stage_buf.data_ptr())
+        stage_n = stage_buf.numel()
     cbatch = None
     if colour:
         rgba_arr = (T.C.c_void_p * len(ptrs))(*[c.data_ptr() for c in rgba])
@@ -1194,7 +1202,8 @@ def trajectory_leg(args, torch, T, S) -> Leg:
             else:
                 p = T.C.cast(T.C.byref(ptr_arr, i0 * T.C.sizeof(T.C.c_void_p)), T.C.c_void_p)
                 c = T.C.cast(T.C.byref(cam_arr, i0 * T.C.sizeof(T.CameraC)), T.C.c_void_p)
-                st = L.tsdf_fuse_frames(h, n, p, c, bflags, sp)
+                st = (L.tsdf_fuse_frames_staged(h, n, p, c, bflags, stage_ptr, stage_n, sp)
+                      if staged else L.tsdf_fuse_frames(h, n, p, c, bflags, sp))
             if st != T.OK:
                 raise RuntimeError("batched fusion failed")
         if events is not None:
@@ -1465,14 +1474,15 @@ def trajectory_leg(args, torch, T, S) -> Leg:
         mean_launch_ms = med([x["launch_ms"][:, full].mean() for x in passes])
         achieved = bytes_per_launch / (mean_launch_ms * 1e-3) / 1e9
         traffic = None
-        if os.path.exists(TRAFFIC_FILE) and args.variant == "main":
+        if os.path.exists(TRAFFIC_FILE) and args.variant == "main" and not staged:
             tr = json.load(open(TRAFFIC_FILE))
             if tr.get("kernel_sha") == kernel_sha() and tr.get("batch") == fpl and \
                     tr.get("per_group") == args.per_group:
                 traffic = tr.get("bytes_per_launch")
-        at = atomics(mean_launch_ms) if args.variant == "main" else None
+        at = atomics(mean_launch_ms) if args.variant == "main" and not staged else None
         cold = e2e = None
-        if args.variant == "main" and args.cold_volumes > 0:
+        if args.variant == "main" and args.cold_volumes > 0 and not staged:
+            # (both time the atomic path)
             cold = cold_frames()
             e2e = end_to_end()
         cpu = None if args.no_cpu_baseline else cpu_baseline()
@@ -1499,7 +1509,8 @@ def trajectory_leg(args, torch, T, S) -> Leg:
                             + (", colour images" if colour else ""),
                 "path": (f"batched: tsdf_batch_fuse, {fpl} frames of the volume per launch"
                          if colour and args.colour_path == "batch" else
-                         f"batched: tsdf_fuse_frames{'_rgb' if colour else ''}, {fpl} frames per "
+                         f"batched: tsdf_fuse_frames{'_rgb' if colour else ''}"
+                         f"{'_staged' if staged else ''}, {fpl} frames per "
                          f"launch, {args.per_group} frame(s) per workgroup"),
                 "variant": {"main": "main design", "slot": "block index = table slot",
                             "colour": "TSDF, weight and three colour sums"}[args.variant],
@@ -1536,6 +1547,8 @@ def trajectory_leg(args, torch, T, S) -> Leg:
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "kernel": ("fuse_multi_kernel<4, 1, 4, colour>"
                            if colour and args.colour_path == "batch"
+                           else f"stage_kernel<4, {args.per_group}> + stage_apply_kernel"
+                           if staged
                            else f"fuse_kernel<4, {args.per_group}, 32, fused"
                                 f"{', colour' if colour else ''}>"),
                 "algorithmic_bytes_per_launch": bytes_per_launch,
@@ -1656,6 +1669,10 @@ def main() -> int:
     ap.add_argument("--workload", default="all",
                     choices=["all", "trajectory", "multi", "serve", "stress", "lf-sweep"],
                     help="all: the trajectory headline with the multi and serve legs")
+    ap.add_argument("--accumulate", choices=["atomic", "staged"], default="atomic",
+                    help="trajectory: the headline path's accumulation: atomic adds from each "
+                         "tile (tsdf_fuse_frames) or records applied once per launch "
+                         "(tsdf_fuse_frames_staged)")
     ap.add_argument("--colour-path", choices=["frames", "batch"], default="frames",
                     help="colour variant: tsdf_fuse_frames_rgb or tsdf_batch_fuse")
     ap.add_argument("--cold-volumes", type=int, default=8,
