@@ -52,7 +52,10 @@ typedef enum tsdf_status {
   TSDF_ERR_COORD_RANGE = 5,       /* a sample's voxel lies outside the key range (sticky) */
   TSDF_ERR_INTERNAL = 6,          /* an invariant broke on the device (sticky) */
   TSDF_ERR_HIP = 7,               /* a HIP runtime call failed */
-  TSDF_ERR_BUDGET = 8             /* a region, queue or session table has no room */
+  TSDF_ERR_BUDGET = 8,            /* a region, queue or session table has no room */
+  /* not a status: keeps the type 32 bits wide, so that every non-negative
+   * code a caller hands back (tsdf_status_str) is a value of the type */
+  TSDF_STATUS_RANGE_ = 0x7FFFFFFF
 } tsdf_status;
 
 /* Sticky status bits, as returned in tsdf_stats.status_bits. */

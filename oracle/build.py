@@ -13,14 +13,25 @@ FLAGS = ["-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fno-finit
          "-fPIC", "-shared", "-Wall", "-Wextra"]
 
 
-def build(verbose: bool = False) -> str:
-    cmd = ["g++", *FLAGS, SRC, "-o", OUT + ".tmp"]
+# The sanitized build (AddressSanitizer + UndefinedBehaviorSanitizer) uses
+# ROCm's clang++, whose sanitizer runtime is the one the sanitized libtsdf.so
+# expects: one process cannot hold two different ASan runtimes.
+CLANGXX = "/opt/rocm/llvm/bin/clang++"
+SANITIZED_OUT = os.path.join(HERE, "liboracle_sanitized.so")
+SANITIZE_FLAGS = ["-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                  "-fno-sanitize-recover=undefined"]
+
+
+def build(verbose: bool = False, sanitize: bool = False) -> str:
+    out = SANITIZED_OUT if sanitize else OUT
+    cmd = ([CLANGXX, *FLAGS, *SANITIZE_FLAGS] if sanitize else ["g++", *FLAGS]) + \
+        [SRC, "-o", out + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(OUT + ".tmp", OUT)
-    return OUT
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv)
+    build(verbose="-v" in sys.argv, sanitize="--sanitize" in sys.argv)

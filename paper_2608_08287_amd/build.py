@@ -37,6 +37,12 @@ FLAGS = ["-x", "hip", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
 VARIANTS = {
     "first_read_coherent": ["-DTSDF_FIRST_READ_COHERENT=1"],
     "keyset_ballot": ["-DTSDF_KEYSET_BALLOT=1"],
+    # the host half under AddressSanitizer and UndefinedBehaviorSanitizer (the
+    # device code is built as shipped); the sanitizer runtime comes from the
+    # process that loads the library (tests/run_sanitized_cpu.py preloads it)
+    "sanitized": ["-g", "-Xarch_host", "-fno-omit-frame-pointer",
+                  "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                  "-Xarch_host", "-fno-sanitize-recover=undefined"],
 }
 VARIANT_DIR = os.path.join(HERE, "variants")
 

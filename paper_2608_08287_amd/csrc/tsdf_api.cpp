@@ -566,6 +566,7 @@ const char* tsdf_status_str(tsdf_status status) {
     case TSDF_ERR_INTERNAL: return "internal invariant violated";
     case TSDF_ERR_HIP: return "HIP runtime error";
     case TSDF_ERR_BUDGET: return "no room in the region, queue or session table";
+    case TSDF_STATUS_RANGE_: break;
   }
   return "unknown status";
 }
