@@ -124,13 +124,14 @@ _lib = None
 _hip = None
 
 
-def _finalise(obj) -> None:
+def _finalise(obj, _shutting_down=sys.is_finalizing) -> None:
     """Release an object's library handle when it is garbage-collected, but
     not during interpreter shutdown: by then the HIP runtime (or a profiler
     hooked into it) may already be torn down, so the process leaves the memory
     to the operating system.  Code that needs the memory back, or a clean exit
-    under a profiler, calls close() itself."""
-    if sys.is_finalizing():
+    under a profiler, calls close() itself.  (Bound as default arguments, this
+    and the finalisers keep working while module globals are being cleared.)"""
+    if _shutting_down():
         return
     try:
         obj.close()
@@ -448,8 +449,8 @@ class Volume(_VolumeCalls):
             lib().tsdf_destroy_volume(self._h)
             self._h = C.c_void_p()
 
-    def __del__(self):
-        _finalise(self)
+    def __del__(self, _fin=_finalise):
+        _fin(self)
 
     @property
     def handle(self) -> C.c_void_p:
@@ -657,8 +658,8 @@ class Batch:
             lib().tsdf_batch_destroy(self._h)
             self._h = C.c_void_p()
 
-    def __del__(self):
-        _finalise(self)
+    def __del__(self, _fin=_finalise):
+        _fin(self)
 
     def set_config(self, cfg: BatchConfig) -> None:
         c = BatchConfigC(cfg.tile_width, cfg.pixels_per_thread, cfg.acc_blocks, cfg.groups_per_cu)
@@ -740,8 +741,8 @@ class Region:
             lib().tsdf_region_destroy(self._h)
             self._h = C.c_void_p()
 
-    def __del__(self):
-        _finalise(self)
+    def __del__(self, _fin=_finalise):
+        _fin(self)
 
     def alloc(self, nbytes: int) -> Optional[int]:
         """Device address of a new range, or None when nothing fits."""
@@ -820,8 +821,8 @@ class Server:
             lib().tsdf_server_destroy(self._h)
             self._h = C.c_void_p()
 
-    def __del__(self):
-        _finalise(self)
+    def __del__(self, _fin=_finalise):
+        _fin(self)
 
     def open(self, voxel_size: float, trunc: float, table_capacity: int,
              pool_capacity: int) -> Optional[int]:
