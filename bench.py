@@ -1659,8 +1659,8 @@ def main() -> int:
                     help="plain-path kernel")
     ap.add_argument("--batch", type=int, default=32,
                     help="frames per launch of the batched path (at most 32)")
-    ap.add_argument("--per-group", type=int, default=2,
-                    help="frames summed per workgroup in the batched path (1, 2 or 4)")
+    ap.add_argument("--per-group", type=int, default=3,
+                    help="frames summed per workgroup in the batched path (1 to 4)")
     ap.add_argument("--profile-copy-bytes", type=int, default=0,
                     help="after the legs, copy this many bytes device to device three times "
                          "(the known-size reference for memory counters)")

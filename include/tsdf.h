@@ -237,9 +237,9 @@ tsdf_status tsdf_fuse_frame_rgb(tsdf_volume* vol, const float* depth_dev, const 
  * overlaps another's pool updates.  Each workgroup takes the same 32x8 pixel
  * tile of F consecutive frames and sums their contributions in LDS before
  * adding them to the pool, so frames of one trajectory that see the same
- * surface share pool updates.  F is set by TSDF_FUSE_BATCH(m): m = 1 -> 1,
- * m = 2 or 3 -> 2, m >= 4 -> 4, and m = 0 (the default) -> 2; F is capped at 2
- * when round(trunc/voxel_size) > 4.  The result is that of fusing the frames
+ * surface share pool updates.  F is set by TSDF_FUSE_BATCH(m): m = 1, 2 or 3
+ * -> m, m >= 4 -> 4, and m = 0 (the default) -> 3; F is capped at 2 when
+ * round(trunc/voxel_size) > 4.  The result is that of fusing the frames
  * one by one with tsdf_fuse_frame, in any order (keys and weights identical,
  * TSDF sums up to float summation order).
  *   depth_devs  host array of n_frames device-accessible pointers (height x

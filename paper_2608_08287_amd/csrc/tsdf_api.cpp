@@ -226,11 +226,11 @@ tsdf_status fuse_frames_impl(tsdf_volume* vol, uint32_t n_frames, const float* c
       return TSDF_ERR_INVALID_ARGUMENT;
   }
   const tsdf::WalkParams wp = walk_params(vol);
-  // frames summed per workgroup: the TSDF_FUSE_BATCH(m) request rounded down to
-  // 1, 2 or 4 (2 when m = 0, the measured best), capped for wide bands and, for
-  // colour volumes, at 2
+  // frames summed per workgroup: the TSDF_FUSE_BATCH(m) request, at most 4 (3
+  // when m = 0, the measured best), capped for wide bands and, for colour
+  // volumes, at 2
   const uint32_t asked = (flags & TSDF_FUSE_BATCH_MASK) >> TSDF_FUSE_BATCH_SHIFT;
-  int per_group = asked == 0 ? 2 : asked >= 4 ? 4 : asked >= 2 ? 2 : 1;
+  int per_group = asked == 0 ? 3 : asked >= 4 ? 4 : (int)asked;
   const int cap = colour ? 2 : tsdf::max_frames_per_group(wp.K);
   if (per_group > cap) per_group = cap;
   const bool remap = (flags & TSDF_FUSE_XCD_REMAP) != 0;

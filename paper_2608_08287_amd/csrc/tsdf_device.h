@@ -486,10 +486,14 @@ struct FuseArgs {
 // (frames past the batch are empty).  F > 1 sums the frames' contributions to a
 // tile before they reach the pool; NB > F puts several frames in one grid so
 // one frame's start-up overlaps another's pool updates.
-// Two frames per workgroup would take ~146 VGPRs (3 waves per SIMD); asking
-// for 4 waves per SIMD costs a few spilled dwords and measures faster.  Colour
-// workgroups take more LDS, three per CU: no cap.
-constexpr int waves_per_eu_for(int F, bool colour) { return (F == 2 && !colour) ? 4 : 1; }
+// Two to four frames per workgroup ask for 4 waves per SIMD (at most 128
+// VGPRs), the residency the LDS allows.  Left alone, three frames take 152
+// VGPRs (3 waves per SIMD) and four 202 (2 waves); at 4 waves three frames
+// spill 80 bytes per lane and four more, and both measure faster so (room
+// orbit, 32 frames per launch: 7.87 against 7.57 G points/s for three, 7.55
+// against 5.76 for four; two frames fit without spilling).  Colour workgroups
+// take more LDS, three per CU: no cap.
+constexpr int waves_per_eu_for(int F, bool colour) { return colour ? 1 : (F >= 2 && F <= 4) ? 4 : 1; }
 
 // Accumulator floats per block: sums and counts in the pool's row layout,
 // then (colour volumes) the red, green and blue sums in the colour layout.
@@ -1189,7 +1193,7 @@ hipError_t launch_fuse_kf(VolumeDev vol, const WalkParams& wp, const FrameDev* f
 }
 
 // n frames (1..kMaxBatchFrames) in one launch; frames_per_group frames summed
-// per workgroup (1, 2 or 4).  The two-pass stages are single-frame launches.
+// per workgroup (1 to 4).  The two-pass stages are single-frame launches.
 template <int K>
 hipError_t launch_fuse_k(VolumeDev vol, const WalkParams& wp, const FrameDev* frames, int n,
                          int frames_per_group, FuseMode mode, bool remap, hipStream_t s) {
@@ -1209,6 +1213,10 @@ hipError_t launch_fuse_k(VolumeDev vol, const WalkParams& wp, const FrameDev* fr
   switch (frames_per_group) {
     case 1: return launch_fuse_kf<K, 1, kMaxBatchFrames, false>(vol, wp, frames, n, mode, remap, s);
     case 2: return launch_fuse_kf<K, 2, kMaxBatchFrames, false>(vol, wp, frames, n, mode, remap, s);
+    case 3:
+      if constexpr (max_frames_for(K) >= 3)
+        return launch_fuse_kf<K, 3, kMaxBatchFrames, false>(vol, wp, frames, n, mode, remap, s);
+      return hipErrorInvalidValue;
     case 4:
       if constexpr (max_frames_for(K) >= 4)
         return launch_fuse_kf<K, 4, kMaxBatchFrames, false>(vol, wp, frames, n, mode, remap, s);

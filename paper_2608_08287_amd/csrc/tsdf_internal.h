@@ -179,7 +179,7 @@ hipError_t launch_reset_used(VolumeDev vol, hipStream_t s);
 hipError_t launch_atomic_rate(float* p, unsigned n_rows, unsigned waves, unsigned iters,
                               unsigned rows, unsigned lanes, hipStream_t s);
 // Fuse n_frames (1..kMaxBatchFrames) frames in one launch, frames_per_group of
-// them summed per workgroup (1, 2 or 4, at most max_frames_per_group(K)).
+// them summed per workgroup (1 to 4, at most max_frames_per_group(K)).
 hipError_t launch_fuse(VolumeDev vol, const WalkParams& wp, const FrameDev* frames, int n_frames,
                        int frames_per_group, FuseMode mode, bool xcd_remap, hipStream_t s);
 int max_frames_per_group(int K);

@@ -237,7 +237,7 @@ def test_stress_A_prefilled_to_095_drops_nothing(stress_full, flags):
 
 def test_stress_A_all_100_frames_batched_matches_oracle():
     """The stress bench's whole run: 100 plane frames through tsdf_fuse_frames
-    (32 per launch, 2 per workgroup) into the table pre-filled to load factor
+    (32 per launch, 3 per workgroup) into the table pre-filled to load factor
     0.95, against the oracle at every voxel (frame slices fused on threads,
     each after the same pre-fill, added by key)."""
     import os
@@ -349,7 +349,7 @@ def test_blocks_new_counts_since_the_previous_query(room):
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("band", list(SCATTER))
-@pytest.mark.parametrize("path", ["plain", "batch1", "batch2", "batch4"])
+@pytest.mark.parametrize("path", ["plain", "batch1", "batch2", "batch3", "batch4"])
 def test_scattered_tiles(band, path):
     v, tau, opts = SCATTER[band]
     depths, cams = scattered_frames(4, seed=31, **opts)
@@ -465,7 +465,7 @@ def test_atomic_rate_measurement_loses_no_update():
 # Several frames per launch (tsdf_fuse_frames)
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("cap", [0, 1, 2, 3])
+@pytest.mark.parametrize("cap", [0, 1, 2, 3, 4])
 def test_batched_room_frames(room, cap):
     w, o = room
     g = run_workload(w, flags=T.FUSE_BATCH(cap), batched=True, keep_volume=True)
@@ -505,10 +505,10 @@ def test_batched_wide_band():
     assert_parity(g, o)
 
 
-@pytest.mark.parametrize("per_group", [1, 2, 4])
+@pytest.mark.parametrize("per_group", [1, 2, 3, 4])
 def test_batched_stress_prefilled(stress_full, per_group):
     """Batched launches on the long probe read-ahead (the pool can fill the
-    table), with 1, 2 and 4 frames per workgroup."""
+    table), with 1 to 4 frames per workgroup."""
     w = S.plane_stress_workload("A", frames=[0, 1, 2, 3])
     o = O.fuse_workload(w)
     g = run_workload(w, batched=True, keep_volume=True, flags=T.FUSE_BATCH(per_group))
@@ -597,7 +597,7 @@ def test_frames_read_from_pinned_host_memory():
 @pytest.mark.parametrize("design", ["main", "slot index"])
 def test_full_trajectory_batched_matches_oracle_everywhere(design):
     """All 300 frames at 640x480 through the launch configuration the bench times
-    (tsdf_fuse_frames, 32 frames per launch, 2 per workgroup), against the oracle
+    (tsdf_fuse_frames, 32 frames per launch, 3 per workgroup), against the oracle
     at every voxel; for the main design (table 2^20, pool 2^18) and for the
     slot-derived block index (pool = table = 2^20), as the bench's variants.  With no pool overflow, a voxel's weight and TSDF sum are
     sums over frames, so disjoint slices of the trajectory fused into separate
