@@ -153,18 +153,22 @@ typedef struct tsdf_stats {
  *   alloc_list : (TSDF_VOLUME_SLOT_INDEX only) pool_capacity uint32, the pool
  *                index (= table slot) of the i-th allocated block; without the
  *                flag the i-th allocated block is pool block i
- *   voxels     : pool_capacity * 1024 float, the voxel pool.  Voxel (lx, ly, lz)
- *                of block b has in-block index loc = (lz * 8 + ly) * 8 + lx
- *                (x fastest) and lies in x-row r = loc / 8; each row is one
- *                64-byte segment holding its 8 TSDF sums then its 8 weights:
- *                  TSDF sum : voxels[b * 1024 + r * 16 + lx]
- *                  weight   : voxels[b * 1024 + r * 16 + 8 + lx]
+ *   voxels     : pool_capacity * 1024 float, the voxel pool.  A block is 64
+ *                segments of 64 bytes; voxel (lx, ly, lz) of block b lies in
+ *                segment g = ((lz / 2) * 8 + ly) * 2 + lx / 4, at place
+ *                e = (lz % 2) * 4 + lx % 4, and a segment holds its 8 TSDF sums
+ *                then its 8 weights:
+ *                  TSDF sum : voxels[b * 1024 + g * 16 + e]
+ *                  weight   : voxels[b * 1024 + g * 16 + 8 + e]
+ *                (a segment is a 4 x 1 x 2 box of voxels, so that one 64-byte
+ *                memory request updates both accumulators of 8 neighbours).
  *                Weights count contributions; TSDF values are sums (the mean is
- *                sum / weight).  tsdf_extract_blocks returns plain arrays.
+ *                sum / weight).  tsdf_extract_blocks returns plain arrays in the
+ *                canonical in-block order loc = (lz * 8 + ly) * 8 + lx.
  *   colour     : (TSDF_VOLUME_COLOUR only) pool_capacity * 1536 float: per
- *                block 64 rows of 24 floats, the row's 8 red, 8 green, 8 blue
- *                sums (colour values 0..255):
- *                  red sum : colour[b * 1536 + r * 24 + lx], green + 8, blue + 16
+ *                block 64 segments of 24 floats, the segment's 8 red, 8 green,
+ *                8 blue sums (colour values 0..255):
+ *                  red sum : colour[b * 1536 + g * 24 + e], green + 8, blue + 16
  *                Regions a volume does not use have size 0. */
 typedef struct tsdf_layout {
   uint64_t counters, table, overflow_keys, block_keys, alloc_list, voxels, colour, total_bytes;

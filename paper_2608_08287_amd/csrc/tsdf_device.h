@@ -33,14 +33,15 @@
 //                one pass when the LDS region holds them all, which is the
 //                common case, else in passes of as many as it holds.  The slots
 //                are then flushed with agent-scope float atomics, two lanes per
-//                voxel (its sum and its count, which share a 64-byte pool row),
-//                so that a wave instruction touches a few rows.  Device-scope
+//                voxel (its sum and its count, which share a 64-byte pool
+//                segment), so that a wave instruction touches a few segments.
+//                Device-scope
 //                float atomics on gfx950 are performed beyond L2, one request
 //                per touched 64-byte segment per instruction whatever its lane
-//                count, so the cost is the number of (tile, row) pairs: a voxel
-//                gets one update per tile (and per launch), not one per
-//                contribution, and the row's TSDF sums and weights share a
-//                segment (see the pool layout in tsdf_internal.h).
+//                count, so the cost is the number of (tile, segment) pairs: a
+//                voxel gets one update per tile (and per launch), not one per
+//                contribution, and the TSDF sums and weights of a segment's 8
+//                voxels share it (see the pool layout in tsdf_internal.h).
 //
 // A workgroup only ever accumulates into blocks whose indices it resolved itself,
 // so one launch needs no grid-wide barrier.  The two-pass structure of Section
@@ -60,10 +61,10 @@
 namespace tsdf {
 namespace {
 
-// The fused kernels' tile: wide tiles cover longer runs of the pool's x-rows
-// (a room orbit's image rows run roughly along them), so a 32x8 tile's
-// contributions fall into fewer 64-byte rows than a 16x16 tile's: about 6 %
-// fewer memory-side requests per contribution on a room trajectory.
+// The fused kernels' tile, 32x8 pixels.  It was chosen when a pool segment was
+// an x-row of 8 voxels, where its contributions fell into about 6 % fewer
+// segments than a 16x16 tile's on a room trajectory; with the 4x1x2 segments
+// the two touch about as many.
 constexpr int kTileW = 32;
 constexpr int kTileH = 8;
 constexpr int kThreads = kTileW * kTileH;  // 256 = 4 x wave64
@@ -495,7 +496,7 @@ struct FuseArgs {
 // take more LDS, three per CU: no cap.
 constexpr int waves_per_eu_for(int F, bool colour) { return colour ? 1 : (F >= 2 && F <= 4) ? 4 : 1; }
 
-// Accumulator floats per block: sums and counts in the pool's row layout,
+// Accumulator floats per block: sums and counts in the pool's segment layout,
 // then (colour volumes) the red, green and blue sums in the colour layout.
 constexpr unsigned acc_block_floats(bool colour) {
   return colour ? kBlockFloats + kColourFloats : kBlockFloats;
@@ -609,7 +610,7 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
       // sample's block (below).
       const bool cand = point && smp.in_range && smp.keep;
       const unsigned long long key = pack_key(smp.vx >> 3, smp.vy >> 3, smp.vz >> 3);
-      const unsigned loc = (unsigned)((((smp.vz & 7) * 8) + (smp.vy & 7)) * 8 + (smp.vx & 7));
+      const unsigned loc = voxel_index((unsigned)smp.vx & 7u, (unsigned)smp.vy & 7u, (unsigned)smp.vz & 7u);
       // consecutive samples of a point mostly share a block: reuse its slot
       const bool need = cand && key != prev_key;
       unsigned slot = prev_slot;
@@ -719,7 +720,7 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
         if (vol.probe_hist) count_probe(vol, probes);
         if (blk >= 0) {
           const unsigned loc =
-              (unsigned)((((smp.vz & 7) * 8) + (smp.vy & 7)) * 8 + (smp.vx & 7));
+              voxel_index((unsigned)smp.vx & 7u, (unsigned)smp.vy & 7u, (unsigned)smp.vz & 7u);
           float* bp = vol.voxels + (size_t)blk * kBlockFloats;
           add_f32(bp + pool_tsdf_index(loc), smp.val);
           add_f32(bp + pool_weight_index(loc), 1.0f);
@@ -858,13 +859,13 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
         }
         __syncthreads();
         // flush: two lanes per voxel slot, its sum and its count, which share
-        // a 64-byte pool row; slots are in block and voxel order, so a row's
-        // voxels are consecutive slots.
+        // a 64-byte pool segment; slots are in block and voxel order, so a
+        // segment's voxels are consecutive slots.
         if (kRowFlush) {
           // Each wave walks its quarter of the pass's slots in windows of at
-          // most 32 slots that end where a row ends, so that every touched row
-          // is one memory-side request (a row cut by a fixed window would cost
-          // two).  For kernels bound by those requests.
+          // most 32 slots that end where a segment ends, so that every touched
+          // segment is one memory-side request (a segment cut by a fixed window
+          // would cost two).  For kernels bound by those requests.
           const unsigned wv = tid / kWave, lane = lane_id();
           const unsigned half = lane & 1u, li = lane >> 1;
           unsigned pos = n_here * wv / (kThreads / kWave);
@@ -876,7 +877,7 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
             const float sm = in ? s_sum[j] : 0.0f;
             unsigned take = end - pos < 32u ? end - pos : 32u;
             if (pos + 32u < end) {
-              // the window's last row may go on past it: it opens the next window
+              // the window's last segment may go on past it: it opens the next one
               const unsigned last = (unsigned)__shfl((int)(tg >> 15), kWave - 1, kWave);
               const unsigned long long m = __ballot(in && half == 0u && (tg >> 15) == last);
               const unsigned first = (unsigned)__ffsll((long long)m) - 1u;
@@ -927,8 +928,8 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
         }
         if (kColour) {
           // colour sums: three lanes per slot (its red, green and blue sums), so
-          // a wave instruction covers 21 slots and a touched 96-byte colour row
-          // costs about two requests; a zero sum needs no update
+          // a wave instruction covers 21 slots and a touched 96-byte colour
+          // segment costs about two requests; a zero sum needs no update
           constexpr unsigned kPer = kThreads / 3u;  // slots per iteration
           const unsigned c = tid % 3u;
           for (unsigned j0 = tid / 3u; j0 < n_here; j0 += 2u * kPer) {
@@ -1032,7 +1033,7 @@ void fuse_kernel(FuseArgs<NB> args) {
     py[fi] = y;
   }
   // several frames per workgroup: the trajectory launches that reach the
-  // memory-side atomic ceiling flush in row-aligned windows
+  // memory-side atomic ceiling flush in segment-aligned windows
   fuse_tile<K, F, AB, kMode, kColour, (F >= 2), kLong>(A.vol, A.wp, frs, px, py, blockIdx.x, sh);
 }
 

@@ -59,18 +59,22 @@ __global__ __launch_bounds__(256) void reset_used_kernel(VolumeDev vol) {
   }
 }
 
-// One thread per x-row of 8 voxels: read the row's 64-byte segment, write the
-// 8 means and 8 weights in flat x-fastest order.
+// One thread per pool segment of 8 voxels (4 along x by 2 along z): read its
+// 64 bytes, write the 8 means and 8 weights at their canonical places, two runs
+// of 4 consecutive x in flat (lz * 8 + ly) * 8 + lx order.
 __global__ __launch_bounds__(256) void extract_kernel(VolumeDev vol, unsigned n_blocks,
                                                       unsigned long long* keys, float* tsdf,
                                                       float* weight) {
-  const size_t n_rows = (size_t)n_blocks * (TSDF_BLOCK_VOXELS / 8);
+  const size_t n_segs = (size_t)n_blocks * (TSDF_BLOCK_VOXELS / 8);
   const size_t stride = (size_t)gridDim.x * 256u;
   const float4* v4 = reinterpret_cast<const float4*>(vol.voxels);
-  for (size_t r = blockIdx.x * 256u + threadIdx.x; r < n_rows; r += stride) {
+  for (size_t r = blockIdx.x * 256u + threadIdx.x; r < n_segs; r += stride) {
     const size_t src = (size_t)allocated_block(vol, (unsigned)(r / 64)) * 64 + r % 64;
+    // float4 q of the segment: sums of (lz even, odd), then weights of the same
     const float4 s0 = v4[4 * src], s1 = v4[4 * src + 1], w0 = v4[4 * src + 2],
                  w1 = v4[4 * src + 3];
+    // canonical index of the segment's first voxel (lz even); lz odd is 64 on
+    const size_t base = (r / 64) * TSDF_BLOCK_VOXELS + canonical_index((unsigned)(r % 64) * 8u);
     if (tsdf) {
       float4 m0, m1;
       m0.x = w0.x > 0.f ? s0.x / w0.x : 0.f;
@@ -81,12 +85,12 @@ __global__ __launch_bounds__(256) void extract_kernel(VolumeDev vol, unsigned n_
       m1.y = w1.y > 0.f ? s1.y / w1.y : 0.f;
       m1.z = w1.z > 0.f ? s1.z / w1.z : 0.f;
       m1.w = w1.w > 0.f ? s1.w / w1.w : 0.f;
-      reinterpret_cast<float4*>(tsdf)[2 * r] = m0;
-      reinterpret_cast<float4*>(tsdf)[2 * r + 1] = m1;
+      reinterpret_cast<float4*>(tsdf + base)[0] = m0;
+      reinterpret_cast<float4*>(tsdf + base + 64)[0] = m1;
     }
     if (weight) {
-      reinterpret_cast<float4*>(weight)[2 * r] = w0;
-      reinterpret_cast<float4*>(weight)[2 * r + 1] = w1;
+      reinterpret_cast<float4*>(weight + base)[0] = w0;
+      reinterpret_cast<float4*>(weight + base + 64)[0] = w1;
     }
   }
   if (keys)
@@ -100,7 +104,8 @@ __global__ __launch_bounds__(256) void extract_colour_kernel(VolumeDev vol, unsi
   const size_t n = (size_t)n_blocks * TSDF_BLOCK_VOXELS;
   const size_t stride = (size_t)gridDim.x * 256u;
   for (size_t v = blockIdx.x * 256u + threadIdx.x; v < n; v += stride) {
-    const unsigned loc = (unsigned)(v % TSDF_BLOCK_VOXELS);
+    const unsigned c = (unsigned)(v % TSDF_BLOCK_VOXELS);  // canonical in-block index
+    const unsigned loc = voxel_index(c & 7u, (c >> 3) & 7u, c >> 6);
     const size_t blk = allocated_block(vol, (unsigned)(v / TSDF_BLOCK_VOXELS));
     const float w = vol.voxels[blk * kBlockFloats + pool_weight_index(loc)];
     const float* cp = vol.colour + blk * kColourFloats;
@@ -217,11 +222,11 @@ __device__ void stage_sum_runs(const StageDev& stg, unsigned blk, unsigned n_run
 // The work items of a launch, taken by waves from a queue (one device atomic
 // per eight items).  Item (block, k) of a block with n records (parts = ceil(n /
 // kStageItemRecords) items, appended by the tile kernel) sums the block's runs
-// k, k + parts, ... per voxel in LDS and adds the sums to the block's pool rows
-// with device atomics: a row's 8 sums and 8 weights by 16 lanes of one
-// instruction, one memory-side request per touched row.  Items of one block,
-// the tile kernel's direct additions and the items of an earlier launch may
-// all update a row at once: every update is an atomic add.
+// k, k + parts, ... per voxel in LDS and adds the sums to the block's pool
+// segments with device atomics: a segment's 8 sums and 8 weights by 16 lanes of
+// one instruction, one memory-side request per touched segment.  Items of one
+// block, the tile kernel's direct additions and the items of an earlier launch
+// may all update a segment at once: every update is an atomic add.
 constexpr unsigned kApplyWaves = kThreads / kWave;
 
 __global__ __launch_bounds__(kThreads) void stage_apply_kernel(VolumeDev vol, StageDev stg) {
@@ -247,7 +252,7 @@ __global__ __launch_bounds__(kThreads) void stage_apply_kernel(VolumeDev vol, St
     float* const bp = vol.voxels + (size_t)blk * kBlockFloats;
 #pragma unroll
     for (unsigned q = 0; q < 16; ++q) {
-      const unsigned row = q * 4u + (lane >> 4), e = lane & 15u;  // e < 8: sums, else weights
+      const unsigned row = q * 4u + (lane >> 4), e = lane & 15u;  // segment; e < 8: sums, else weights
       const unsigned loc = row * 8u + (e & 7u);
       const unsigned c = cnt[loc];
       if (c) add_f32(bp + row * 16u + e, e < 8u ? sum[loc] : (float)c);

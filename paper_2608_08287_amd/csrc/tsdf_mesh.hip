@@ -146,7 +146,7 @@ __global__ __launch_bounds__(256) void mesh_kernel(VolumeDev vol, float v, float
     const int nb = s_nb[(x >> 3) | ((y >> 3) << 1) | ((z >> 3) << 2)];
     float f = __builtin_nanf("");
     if (nb >= 0) {
-      const unsigned loc = (unsigned)((((z & 7) * 8) + (y & 7)) * 8 + (x & 7));
+      const unsigned loc = voxel_index((unsigned)x & 7u, (unsigned)y & 7u, (unsigned)z & 7u);
       const float* bp = vol.voxels + (size_t)nb * kBlockFloats;
       const float w = bp[pool_weight_index(loc)];
       if (w > 0.0f) f = bp[pool_tsdf_index(loc)] / w;

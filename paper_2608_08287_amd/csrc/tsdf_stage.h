@@ -32,9 +32,9 @@
 //
 // stage_apply_kernel (tsdf_kernels.hip) then takes the launch's work items: an
 // item sums its share of a block's runs per voxel in LDS and adds the sums to
-// the block's pool rows, one memory-side request per touched row.  One device
-// atomic per (tile, block) replaces one per (tile, pool row), a pool row takes
-// one request per item (one per launch for most blocks) instead of one from
+// the block's pool segments, one memory-side request per touched segment.  One
+// device atomic per (tile, block) replaces one per (tile, pool segment), a
+// segment takes one request per item (one per launch for most blocks) instead of one from
 // every tile and frame, and the tile needs no per-voxel slots (no masks,
 // prefix sums or passes): the apply kernel sums per voxel for the whole launch.
 #pragma once
@@ -133,7 +133,7 @@ __device__ __forceinline__ void stage_tile(const VolumeDev& vol, const WalkParam
       if (z_ok && !smp.in_range) ++n_oor;
       const bool cand = point && smp.keep;  // keep implies in range
       const int bx = smp.vx >> 3, by = smp.vy >> 3, bz = smp.vz >> 3;
-      const unsigned loc = (unsigned)((((smp.vz & 7) * 8) + (smp.vy & 7)) * 8 + (smp.vx & 7));
+      const unsigned loc = voxel_index((unsigned)smp.vx & 7u, (unsigned)smp.vy & 7u, (unsigned)smp.vz & 7u);
       // consecutive kept samples of a point mostly share a block: reuse its slot
       const bool need = cand && !(have_prev && bx == pbx && by == pby && bz == pbz);
       unsigned slot = prev_slot;
@@ -340,7 +340,7 @@ __device__ __forceinline__ void stage_tile(const VolumeDev& vol, const WalkParam
       my_missing += missing ? 1u : 0u;
       if (vol.probe_hist) count_probe(vol, probes);
       if (blk >= 0) {
-        const unsigned loc = (unsigned)((((smp.vz & 7) * 8) + (smp.vy & 7)) * 8 + (smp.vx & 7));
+        const unsigned loc = voxel_index((unsigned)smp.vx & 7u, (unsigned)smp.vy & 7u, (unsigned)smp.vz & 7u);
         float* bp = vol.voxels + (size_t)blk * kBlockFloats;
         add_f32(bp + pool_tsdf_index(loc), smp.val);
         add_f32(bp + pool_weight_index(loc), 1.0f);

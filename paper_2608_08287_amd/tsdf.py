@@ -295,6 +295,19 @@ def layout(p: VolumeParams) -> LayoutC:
     return out
 
 
+def pool_voxel_order() -> np.ndarray:
+    """(512,) the canonical in-block index (lz * 8 + ly) * 8 + lx of each voxel
+    of a pool block, in the pool's order (the layout region ``voxels``: 64
+    segments of 8 voxels, segment ((lz // 2) * 8 + ly) * 2 + lx // 4 holding
+    voxel (lz % 2) * 4 + lx % 4 of its 4 x 1 x 2 box)."""
+    v = np.arange(512)
+    seg, w = v >> 3, v & 7
+    lx = (seg & 1) * 4 + (w & 3)
+    ly = (seg >> 1) & 7
+    lz = (seg >> 4) * 2 + (w >> 2)
+    return (lz * 8 + ly) * 8 + lx
+
+
 def staging_bytes(pool_capacity: int, records: int) -> int:
     """Bytes of staging memory for tsdf_fuse_frames_staged holding `records`
     records per launch (0 if invalid)."""
@@ -588,17 +601,19 @@ class Volume(_VolumeCalls):
         return t.view(torch.int64).view(L.table_capacity, 2)
 
     def pool_view(self) -> torch.Tensor:
-        """(P, 64, 2, 8) float32 view of the voxel pool: [block, x-row, (sum | weight), x]."""
+        """(P, 64, 2, 8) float32 view of the voxel pool: [block, segment, (sum |
+        weight), voxel of the segment]; pool_voxel_order() maps the flattened
+        (segment, voxel) index to the canonical in-block index."""
         L = self.layout
         return self.arena[L.voxels:L.voxels + 4096 * L.pool_capacity].view(torch.float32).view(
             L.pool_capacity, 64, 2, 8)
 
     def tsdf_sum_view(self) -> torch.Tensor:
-        """(P, 64, 8) strided view of the TSDF sums (x-row major within a block)."""
+        """(P, 64, 8) strided view of the TSDF sums, in the pool's voxel order."""
         return self.pool_view()[:, :, 0, :]
 
     def weight_view(self) -> torch.Tensor:
-        """(P, 64, 8) strided view of the weights (x-row major within a block)."""
+        """(P, 64, 8) strided view of the weights, in the pool's voxel order."""
         return self.pool_view()[:, :, 1, :]
 
     def block_keys_view(self) -> torch.Tensor:
@@ -614,7 +629,8 @@ class Volume(_VolumeCalls):
         return self.arena[L.alloc_list:L.alloc_list + 4 * L.pool_capacity].view(torch.int32)
 
     def colour_view(self) -> torch.Tensor:
-        """(P, 64, 3, 8) float32 colour sums: [block, x-row, (r | g | b), x]."""
+        """(P, 64, 3, 8) float32 colour sums: [block, segment, (r | g | b), voxel
+        of the segment], in the pool's voxel order."""
         L = self.layout
         if not (L.flags & VOLUME_COLOUR):
             raise ValueError("not a colour volume")

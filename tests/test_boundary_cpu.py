@@ -6,6 +6,7 @@ import re
 import subprocess
 
 import pytest
+import numpy as np
 
 from paper_2608_08287_amd import tsdf as T
 
@@ -223,3 +224,21 @@ def test_staging_bytes_and_refusals_without_a_gpu():
         assert T.staging_bytes(pool, rec) == 0, (pool, rec)
     assert L.tsdf_fuse_frames_staged(None, 0, None, None, 0, C.c_void_p(256), 1 << 30,
                                      None) == T.ERR_INVALID_ARGUMENT
+
+
+def test_pool_voxel_order_is_the_documented_layout():
+    """pool_voxel_order() is the header's layout: a permutation of the 512
+    canonical in-block indices, each 8 consecutive pool places a 4 x 1 x 2 box
+    at g = ((lz // 2) * 8 + ly) * 2 + lx // 4, place (lz % 2) * 4 + lx % 4."""
+    order = T.pool_voxel_order()
+    assert sorted(order.tolist()) == list(range(512))
+    for lz in range(8):
+        for ly in range(8):
+            for lx in range(8):
+                g = ((lz // 2) * 8 + ly) * 2 + lx // 4
+                e = (lz % 2) * 4 + lx % 4
+                assert order[g * 8 + e] == (lz * 8 + ly) * 8 + lx
+    boxes = order.reshape(64, 8)
+    for box in boxes:
+        x, y, z = box % 8, (box // 8) % 8, box // 64
+        assert np.ptp(x) == 3 and np.ptp(y) == 0 and np.ptp(z) == 1

@@ -62,8 +62,9 @@ def field_pair(fn, blocks, weight_fn=None, v=V32, tau=TAU32):
         sums[i], wts[i] = f, w
         o.set_block(int(k), f.astype(np.float64), w)
     pool = g.pool_view()
-    pool[:P, :, 0, :] = torch.from_numpy(sums.reshape(P, 64, 8)).cuda()
-    pool[:P, :, 1, :] = torch.from_numpy(wts.reshape(P, 64, 8)).cuda()
+    order = T.pool_voxel_order()  # pool voxel -> canonical in-block index
+    pool[:P, :, 0, :] = torch.from_numpy(sums[:, order].reshape(P, 64, 8)).cuda()
+    pool[:P, :, 1, :] = torch.from_numpy(wts[:, order].reshape(P, 64, 8)).cuda()
     torch.cuda.synchronize()
     return g, o
 

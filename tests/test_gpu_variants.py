@@ -147,8 +147,11 @@ def gpu_colour_sums(vol: T.Volume, n_blocks: int, slot: bool):
     keys = vol.block_keys_view()[:n_blocks].cpu().numpy().view(np.uint64)
     pool = vol.alloc_list_view()[:n_blocks].cpu().numpy() if slot else np.arange(n_blocks)
     cv = vol.colour_view()[torch.from_numpy(pool.astype(np.int64)).cuda()].cpu().numpy()
-    # (B, 64 rows, 3, 8 x) -> (B, 3, 512) with loc = row * 8 + x
-    sums = cv.transpose(0, 2, 1, 3).reshape(n_blocks, 3, 512).astype(np.float64)
+    # (B, 64 segments, 3, 8) -> (B, 3, 512) in the pool's voxel order, then
+    # placed at the canonical in-block indices
+    dev = cv.transpose(0, 2, 1, 3).reshape(n_blocks, 3, 512).astype(np.float64)
+    sums = np.empty_like(dev)
+    sums[:, :, T.pool_voxel_order()] = dev
     order = np.argsort(keys)
     return keys[order], sums[order]
 
