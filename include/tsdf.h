@@ -155,9 +155,9 @@ typedef struct tsdf_stats {
  *                flag the i-th allocated block is pool block i
  *   voxels     : pool_capacity * 1024 float, the voxel pool.  A block is 64
  *                segments of 64 bytes; voxel (lx, ly, lz) of block b lies in
- *                segment g = ((lz / 2) * 8 + ly) * 2 + lx / 4, at place
- *                e = (lz % 2) * 4 + lx % 4, and a segment holds its 8 TSDF sums
- *                then its 8 weights:
+ *                segment g = ((ly % 4) * 2 + (lz / 2) % 2) * 8 + (lz / 4) * 4 +
+ *                (ly / 4) * 2 + lx / 4, at place e = (lz % 2) * 4 + lx % 4, and
+ *                a segment holds its 8 TSDF sums then its 8 weights:
  *                  TSDF sum : voxels[b * 1024 + g * 16 + e]
  *                  weight   : voxels[b * 1024 + g * 16 + 8 + e]
  *                (a segment is a 4 x 1 x 2 box of voxels, so that one 64-byte

@@ -298,13 +298,14 @@ def layout(p: VolumeParams) -> LayoutC:
 def pool_voxel_order() -> np.ndarray:
     """(512,) the canonical in-block index (lz * 8 + ly) * 8 + lx of each voxel
     of a pool block, in the pool's order (the layout region ``voxels``: 64
-    segments of 8 voxels, segment ((lz // 2) * 8 + ly) * 2 + lx // 4 holding
-    voxel (lz % 2) * 4 + lx % 4 of its 4 x 1 x 2 box)."""
+    segments of 8 voxels, each a 4 x 1 x 2 box; segment
+    g = ((ly % 4) * 2 + (lz // 2) % 2) * 8 + (lz // 4) * 4 + (ly // 4) * 2 + lx // 4
+    holds voxel (lz % 2) * 4 + lx % 4 of its box)."""
     v = np.arange(512)
-    seg, w = v >> 3, v & 7
-    lx = (seg & 1) * 4 + (w & 3)
-    ly = (seg >> 1) & 7
-    lz = (seg >> 4) * 2 + (w >> 2)
+    word, inw, w = v >> 6, (v >> 3) & 7, v & 7
+    ly = (word >> 1) + ((inw >> 1) & 1) * 4
+    lz = ((word & 1) + (inw >> 2) * 2) * 2 + (w >> 2)
+    lx = (inw & 1) * 4 + (w & 3)
     return (lz * 8 + ly) * 8 + lx
 
 

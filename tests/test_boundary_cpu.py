@@ -229,13 +229,14 @@ def test_staging_bytes_and_refusals_without_a_gpu():
 def test_pool_voxel_order_is_the_documented_layout():
     """pool_voxel_order() is the header's layout: a permutation of the 512
     canonical in-block indices, each 8 consecutive pool places a 4 x 1 x 2 box
-    at g = ((lz // 2) * 8 + ly) * 2 + lx // 4, place (lz % 2) * 4 + lx % 4."""
+    at g = ((ly % 4) * 2 + (lz // 2) % 2) * 8 + (lz // 4) * 4 + (ly // 4) * 2 + lx // 4,
+    place (lz % 2) * 4 + lx % 4."""
     order = T.pool_voxel_order()
     assert sorted(order.tolist()) == list(range(512))
     for lz in range(8):
         for ly in range(8):
             for lx in range(8):
-                g = ((lz // 2) * 8 + ly) * 2 + lx // 4
+                g = ((ly % 4) * 2 + (lz // 2) % 2) * 8 + (lz // 4) * 4 + (ly // 4) * 2 + lx // 4
                 e = (lz % 2) * 4 + lx % 4
                 assert order[g * 8 + e] == (lz * 8 + ly) * 8 + lx
     boxes = order.reshape(64, 8)
