@@ -660,6 +660,10 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
       st[fi][s] = (pair && !spilled) ? word : 0u;
     }
   }
+  // Phase 1's counts are reported only at the end of the tile; computed there,
+  // they would keep every sample's inputs to them alive through phases 2 and 3
+  // (with three frames per workgroup, spilled).  The empty asm fixes them here.
+  asm volatile("" : "+v"(n_pts), "+v"(n_pairs), "+v"(n_oor));
   __syncthreads();
 
   // ---- phase 2: resolve each distinct key of the tile once ----------------

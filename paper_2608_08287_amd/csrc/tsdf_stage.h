@@ -165,6 +165,8 @@ __device__ __forceinline__ void stage_tile(const VolumeDev& vol, const WalkParam
       val[fi][s] = smp.val;
     }
   }
+  // phase 1's counts, fixed here rather than at the end of the tile (see fuse_tile)
+  asm volatile("" : "+v"(n_pts), "+v"(n_pairs), "+v"(n_oor));
   __syncthreads();
 
   // ---- phase 2: resolve each distinct key of the tile once; count pairs ----
