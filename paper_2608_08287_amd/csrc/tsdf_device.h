@@ -78,6 +78,9 @@ constexpr int kProbeAheadLong = 8;          // ... per later step, for tables th
 // handful of steps.  A wait this long means the invariant broke: report it as
 // INTERNAL instead of spinning forever.
 constexpr unsigned kMaxWaitSteps = 1u << 20;
+constexpr int kFramePad = 3;  // spare frame descriptors after a launch's frames
+// frame descriptors of a launch of up to NB frames (one-frame launches need no spares)
+constexpr int frame_slots(int NB) { return NB > 1 ? NB + kFramePad : NB; }
 
 // Two design alternatives stay buildable so that they can be measured against
 // the shipped choice (both are off in the library; the build script's
@@ -477,7 +480,9 @@ template <int NB>
 struct FuseArgs {
   VolumeDev vol;
   WalkParams wp;
-  FrameDev f[NB];
+  // NB frames and (NB > 1) kFramePad copies of the first past them, so that
+  // the last group of F <= kFramePad + 1 frames reads inside the array
+  FrameDev f[frame_slots(NB)];
   unsigned n_frames, tiles_x, n_tiles;
   int remap;
 };
@@ -1025,15 +1030,15 @@ void fuse_kernel(FuseArgs<NB> args) {
   const unsigned tile = tile_of_group(blockIdx.x % n_tiles, n_tiles, A.remap != 0);
   const unsigned x = (tile % tiles_x) * kTileW + (threadIdx.x % kTileW);
   const unsigned y = (tile / tiles_x) * kTileH + (threadIdx.x / kTileW);
-  FrameDev frs[F];
+  // the group's frames, read where they are used from the argument segment
+  // rather than copied (a copy of three frames would hold 66 scalar registers
+  // for the whole tile); a frame past the batch gets a pixel column past any
+  // width, so it has no point and adds nothing
+  const FrameDev(&frs)[F] = *reinterpret_cast<const FrameDev(*)[F]>(&A.f[group * F]);
   unsigned px[F], py[F];
 #pragma unroll
   for (int fi = 0; fi < F; ++fi) {
-    const unsigned idx = group * F + fi;
-    const bool in_batch = idx < A.n_frames;
-    frs[fi] = A.f[in_batch ? idx : 0u];
-    if (!in_batch) frs[fi].width = frs[fi].height = 0;  // past the batch: empty
-    px[fi] = x;
+    px[fi] = group * F + fi < A.n_frames ? x : ~0u;
     py[fi] = y;
   }
   // several frames per workgroup: the trajectory launches that reach the
@@ -1140,7 +1145,7 @@ hipError_t launch_fuse_kf(VolumeDev vol, const WalkParams& wp, const FrameDev* f
   args.vol = vol;
   args.wp = wp;
   unsigned w = 0, h = 0;
-  for (int i = 0; i < NB; ++i) {
+  for (int i = 0; i < frame_slots(NB); ++i) {
     args.f[i] = frames[i < n ? i : 0];
     if (i < n) {
       w = frames[i].width > w ? frames[i].width : w;
