@@ -550,16 +550,46 @@ struct alignas(16) TileShared {
   static_assert(kCap >= 512, "a pass holds at least one block's voxels");
 };
 
+// A tile's frames, copied into registers (from a work list): read in place.
+template <int F>
+struct HeldFrames {
+  const FrameDev (&f)[F];
+  __device__ const FrameDev& operator[](int i) const { return f[i]; }
+  __device__ HeldFrames reread() const { return *this; }
+};
+
+// A tile's frames in the launch's argument segment, frames first, first + 1,
+// ...  With kReload, reread() hides the index from the optimiser, so what is
+// read through its result is loaded again (scalar loads that hit the constant
+// cache) where it is used, instead of being kept in scalar registers from the
+// first read on: several frames' constants held through phases 1 and 2 spill
+// to vector lanes.  One frame's fit, and reloading them in every pass of
+// phase 3 only adds latency.
+template <bool kReload>
+struct ArgFrames {
+  ConstPtr<FrameDev> f;
+  unsigned first;
+  __device__ const FrameDev& operator[](int i) const {
+    return *(const FrameDev*)&f[first + (unsigned)i];
+  }
+  __device__ ArgFrames reread() const {
+    unsigned g = first;
+    if (kReload) asm volatile("" : "+s"(g));
+    return {f, g};
+  }
+};
+
 // One tile of F pixel slots per thread: the three phases.  Slot fi of the
-// calling thread is pixel (px[fi], py[fi]) of frame frs[fi]; the slots may be
+// calling thread is pixel (px[fi], py[fi]) of frame frs[fi] (a HeldFrames or
+// an ArgFrames; phase 3 reads its frames through frs.reread()); the slots may be
 // the same pixel of F frames of one trajectory or F pixels of one frame.
 // Frames with width 0 are empty.  Every thread of the workgroup must call it;
 // it begins with a workgroup barrier, so a persistent workgroup may call it
 // tile after tile.
 template <int K, int F, int AB, FuseMode kMode, bool kColour = false, bool kRowFlush = true,
-          bool kLong = false>
+          bool kLong = false, class Frames>
 __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams& wp,
-                                          const FrameDev (&frs)[F], const unsigned (&px)[F],
+                                          const Frames& frs, const unsigned (&px)[F],
                                           const unsigned (&py)[F], unsigned shard,
                                           TileShared<AB, kColour>& sh) {
   constexpr int NS = 2 * K + 1;
@@ -713,9 +743,10 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
     // kSetCap distinct blocks): resolve each one directly (same protocol, same
     // result) and add it straight to the pool.  Rare; kept out of line of the
     // unrolled fast path by looping over the bits of a mask.
+    const Frames fr3 = frs.reread();
 #pragma unroll
     for (int fi = 0; fi < F; ++fi) {
-      const FrameDev& fr = frs[fi];
+      const FrameDev& fr = fr3[fi];
       const float a = ((float)px[fi] - fr.cx) * fr.ifx;
       const float b = ((float)py[fi] - fr.cy) * fr.ify;
       for (unsigned m = ovf[fi]; m != 0u; m &= m - 1u) {
@@ -837,9 +868,10 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
           }
         }
         __syncthreads();
+        const Frames frp = frs.reread();  // loaded again for each pass
 #pragma unroll
         for (int fi = 0; fi < F; ++fi) {
-          const FrameDev& fr = frs[fi];
+          const FrameDev& fr = frp[fi];
           const float a = ((float)px[fi] - fr.cx) * fr.ifx;
           const float b = ((float)py[fi] - fr.cy) * fr.ify;
 #pragma unroll
@@ -1034,7 +1066,7 @@ void fuse_kernel(FuseArgs<NB> args) {
   // rather than copied (a copy of three frames would hold 66 scalar registers
   // for the whole tile); a frame past the batch gets a pixel column past any
   // width, so it has no point and adds nothing
-  const FrameDev(&frs)[F] = *reinterpret_cast<const FrameDev(*)[F]>(&A.f[group * F]);
+  const ArgFrames<(F > 1)> frs{(ConstPtr<FrameDev>)(const FrameDev*)A.f, group * F};
   unsigned px[F], py[F];
 #pragma unroll
   for (int fi = 0; fi < F; ++fi) {
@@ -1099,8 +1131,8 @@ void fuse_multi_kernel(BatchWork w, unsigned tw_log2) {
       py[p] = y0 + p * rows;
     }
     // latency-bound (its workloads sit below the atomic ceiling): fixed windows
-    fuse_tile<K, PPT, AB, FuseMode::kFused, kColour, false>(it.vol, it.wp, frs, px, py, blockIdx.x,
-                                                            sh);
+    fuse_tile<K, PPT, AB, FuseMode::kFused, kColour, false>(it.vol, it.wp, HeldFrames<PPT>{frs},
+                                                            px, py, blockIdx.x, sh);
   }
 }
 
