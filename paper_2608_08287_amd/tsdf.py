@@ -36,8 +36,9 @@ PROBE_HIST_BINS = 16
 
 
 def FUSE_BATCH(m: int) -> int:
-    """Flag for ``fuse_frames``: frames summed per workgroup (m = 1 -> 1, 2 or 3
-    -> 2, 4..15 -> 4; 0, the default, -> 2)."""
+    """Flag for ``fuse_frames``: frames summed per workgroup (m = 1 to 4 -> m,
+    5..15 -> 4; 0, the default, -> 3; at most 2 for bands wider than 9
+    samples and for colour volumes)."""
     return (m & 0xF) << 16
 BLOCK_VOXELS = 512
 EMPTY_KEY = 0xFFFFFFFFFFFFFFFF
