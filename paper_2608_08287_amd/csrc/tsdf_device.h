@@ -492,14 +492,17 @@ struct FuseArgs {
 // (frames past the batch are empty).  F > 1 sums the frames' contributions to a
 // tile before they reach the pool; NB > F puts several frames in one grid so
 // one frame's start-up overlaps another's pool updates.
-// Two to four frames per workgroup ask for 4 waves per SIMD (at most 128
-// VGPRs), the residency the LDS allows.  Left alone, three frames take 152
-// VGPRs (3 waves per SIMD) and four 202 (2 waves); at 4 waves three frames
-// spill 80 bytes per lane and four more, and both measure faster so (room
-// orbit, 32 frames per launch: 7.87 against 7.57 G points/s for three, 7.55
-// against 5.76 for four; two frames fit without spilling).  Colour workgroups
-// take more LDS, three per CU: no cap.
-constexpr int waves_per_eu_for(int F, bool colour) { return colour ? 1 : (F >= 2 && F <= 4) ? 4 : 1; }
+// Two or three frames per workgroup ask for 4 waves per SIMD (at most 128
+// VGPRs), the residency the LDS allows.  Three frames need 129 VGPRs and so
+// spill 8 bytes per lane; capped while they still spilled 80, they already
+// measured faster than at 3 waves per SIMD without spills (room orbit, 32
+// frames per launch: 7.87 against 7.57 G points/s).  Four frames need 168
+// VGPRs and run at 3 waves per SIMD without spilling: 7.66 against 8.65 G
+// points/s for three frames at 4 waves (at 4 waves four frames spill 152
+// bytes per lane).  Colour workgroups take more LDS, three per CU: no cap.
+constexpr int waves_per_eu_for(int F, bool colour) {
+  return colour ? 1 : F == 4 ? 3 : (F == 2 || F == 3) ? 4 : 1;
+}
 
 // Accumulator floats per block: sums and counts in the pool's segment layout,
 // then (colour volumes) the red, green and blue sums in the colour layout.
@@ -1092,7 +1095,7 @@ void fuse_kernel(FuseArgs<NB> args) {
 // constant address space (ConstPtr).
 
 // Four workgroups of a plain volume fit a CU's LDS, so registers are capped to
-// match: 128 VGPRs (two pixels per thread need ~146, and spill a few dwords).
+// match: 128 VGPRs (two pixels per thread fit without spilling).
 // Colour workgroups take more LDS, three per CU: no cap.
 constexpr int multi_waves_per_eu(bool colour) { return colour ? 1 : 4; }
 
