@@ -435,10 +435,14 @@ __device__ __forceinline__ Sample walk_sample(const FrameDev& f, const WalkParam
 
 // Insert a block key into a tile's LDS key set (open addressing, linear
 // probe): its slot, found or claimed, or kSetNone when the set is full.  A
-// claimed slot is appended to the set's list of distinct keys.
+// claimed slot is appended to the set's list of distinct keys.  The probe
+// stays a loop: it is inlined once per band sample of every frame of a tile,
+// and unrolled copies of it (rarely run past the first step) pushed the
+// three-frame kernel's code past what the instruction cache holds.
 __device__ __forceinline__ unsigned set_insert(unsigned long long* s_keys, unsigned short* s_list,
                                                unsigned* s_n, unsigned long long key) {
   unsigned h = set_home(key);
+#pragma unroll 1
   for (unsigned i = 0; i < kSetCap; ++i) {
     const unsigned long long old = atomicCAS(&s_keys[h], kEmptyKey, key);
     if (old == kEmptyKey) {
@@ -493,10 +497,10 @@ struct FuseArgs {
 // tile before they reach the pool; NB > F puts several frames in one grid so
 // one frame's start-up overlaps another's pool updates.
 // Two or three frames per workgroup ask for 4 waves per SIMD (at most 128
-// VGPRs), the residency the LDS allows.  Three frames need 129 VGPRs and so
-// spill 8 bytes per lane; capped while they still spilled 80, they already
+// VGPRs), the residency the LDS allows: three frames fit in 126 without
+// spilling; capped while they still spilled 80 bytes per lane, they already
 // measured faster than at 3 waves per SIMD without spills (room orbit, 32
-// frames per launch: 7.87 against 7.57 G points/s).  Four frames need 168
+// frames per launch: 7.87 against 7.57 G points/s).  Four frames need 158
 // VGPRs and run at 3 waves per SIMD without spilling: 7.66 against 8.65 G
 // points/s for three frames at 4 waves (at 4 waves four frames spill 152
 // bytes per lane).  Colour workgroups take more LDS, three per CU: no cap.
@@ -685,6 +689,7 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
 #pragma unroll
         for (int j = 0; j < s; ++j) dup |= st[fi][j] == word;
       } else if (cand) {
+#pragma unroll 1  // rare (a tile of more than kSetCap blocks): kept small
         for (unsigned m = ovf[fi]; m != 0u; m &= m - 1u) {
           const Sample o = walk_sample(fr, wp, df, a, b, __builtin_ctz(m) - K);
           dup |= o.vx == smp.vx && o.vy == smp.vy && o.vz == smp.vz;
@@ -752,6 +757,7 @@ __device__ __forceinline__ void fuse_tile(const VolumeDev& vol, const WalkParams
       const FrameDev& fr = fr3[fi];
       const float a = ((float)px[fi] - fr.cx) * fr.ifx;
       const float b = ((float)py[fi] - fr.cy) * fr.ify;
+#pragma unroll 1
       for (unsigned m = ovf[fi]; m != 0u; m &= m - 1u) {
         const int s = __builtin_ctz(m);
         const Sample smp = walk_sample(fr, wp, d[fi], a, b, s - K);
