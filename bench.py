@@ -1164,6 +1164,9 @@ def trajectory_leg(args, torch, T, S) -> Leg:
     staged = args.accumulate == "staged"
     if staged and (colour or slot):
         raise GateFailed("--accumulate staged takes the main design's plain volumes only")
+    # frames per workgroup as the library takes them: colour volumes and the
+    # staged path sum at most two
+    pg = min(args.per_group, 2) if colour or staged else args.per_group
     if staged:
         # every record of fpl frames with the band's 2K+1 samples per pixel
         stage_buf = T.staging_buffer(pool, fpl * n_pix * (2 * int(round(w.trunc / w.voxel_size)) + 1))
@@ -1291,7 +1294,7 @@ def trajectory_leg(args, torch, T, S) -> Leg:
         if os.path.exists(TRAFFIC_FILE):
             tr = json.load(open(TRAFFIC_FILE))
             if tr.get("kernel_sha") == kernel_sha() and tr.get("batch") == fpl and \
-                    tr.get("per_group") == args.per_group:
+                    tr.get("per_group") == pg:
                 req = tr.get("atomic_requests_per_dispatch")
         return {
             "unit": "G requests/s", "ceiling": ceiling["flush_pattern"],
@@ -1477,7 +1480,7 @@ def trajectory_leg(args, torch, T, S) -> Leg:
         if os.path.exists(TRAFFIC_FILE) and args.variant == "main" and not staged:
             tr = json.load(open(TRAFFIC_FILE))
             if tr.get("kernel_sha") == kernel_sha() and tr.get("batch") == fpl and \
-                    tr.get("per_group") == args.per_group:
+                    tr.get("per_group") == pg:
                 traffic = tr.get("bytes_per_launch")
         at = atomics(mean_launch_ms) if args.variant == "main" and not staged else None
         cold = e2e = None
@@ -1511,7 +1514,7 @@ def trajectory_leg(args, torch, T, S) -> Leg:
                          if colour and args.colour_path == "batch" else
                          f"batched: tsdf_fuse_frames{'_rgb' if colour else ''}"
                          f"{'_staged' if staged else ''}, {fpl} frames per "
-                         f"launch, {args.per_group} frame(s) per workgroup"),
+                         f"launch, {pg} frame(s) per workgroup"),
                 "variant": {"main": "main design", "slot": "block index = table slot",
                             "colour": "TSDF, weight and three colour sums"}[args.variant],
                 "frames_per_step": len(ptrs), "points_per_step": points_per_step,
@@ -1531,7 +1534,7 @@ def trajectory_leg(args, torch, T, S) -> Leg:
             },
             "batched": {
                 "value": value, "unit": "points/s", "frames_per_launch": fpl,
-                "frames_per_workgroup": args.per_group,
+                "frames_per_workgroup": pg,
                 "mean_launch_ms": mean_launch_ms,
                 "p50_launch_ms": med([np.percentile(x["launch_ms"][:, full], 50) for x in passes]),
                 "p99_launch_ms": med([np.percentile(x["launch_ms"][:, full], 99) for x in passes]),
@@ -1547,9 +1550,9 @@ def trajectory_leg(args, torch, T, S) -> Leg:
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "kernel": ("fuse_multi_kernel<4, 1, 4, colour>"
                            if colour and args.colour_path == "batch"
-                           else f"stage_kernel<4, {args.per_group}> + stage_apply_kernel"
+                           else f"stage_kernel<4, {pg}> + stage_apply_kernel"
                            if staged
-                           else f"fuse_kernel<4, {args.per_group}, 32, fused"
+                           else f"fuse_kernel<4, {pg}, 32, fused"
                                 f"{', colour' if colour else ''}>"),
                 "algorithmic_bytes_per_launch": bytes_per_launch,
                 "mean_launch_ms": mean_launch_ms,
