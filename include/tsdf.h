@@ -268,8 +268,8 @@ tsdf_status tsdf_fuse_frames(tsdf_volume* vol, uint32_t n_frames, const float* c
  * caller's staging memory, and lists each of its (tile, block) runs in that
  * block's run table (one device atomic per tile and block).  An apply kernel
  * then sums each block's records per voxel, one work item per 1024 records of
- * a block, and adds the sums to its pool rows with one memory-side request per
- * touched row and item.  Runs that do not fit a block's table of 128, or a
+ * a block, and adds the sums to its pool segments with one memory-side
+ * request per touched 64-byte segment and item.  Runs that do not fit a block's table of 128, or a
  * launch's records beyond the staging memory, go to the pool directly with
  * device atomics, so any size is correct; the size only decides how much is
  * staged.  The staging memory holds two sets used by alternate launches, and

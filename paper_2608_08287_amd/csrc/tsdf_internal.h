@@ -174,7 +174,8 @@ struct BatchWork {
 // counts the block's runs and records).  A block is cut into one work item per
 // kStageItemRecords records; the apply kernel takes items from a queue, sums
 // an item's share of the block's runs per voxel in LDS and adds the sums to
-// the block's pool rows with device atomics, one request per touched row.
+// the block's pool segments with device atomics, one request per touched
+// segment.
 //
 // A record is one contribution in 32 bits: its voxel's in-block index (bits
 // 0..8) and its truncated distance in signed 23-bit fixed point of the
