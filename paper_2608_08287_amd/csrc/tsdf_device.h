@@ -501,9 +501,11 @@ struct FuseArgs {
 // spilling; capped while they still spilled 80 bytes per lane, they already
 // measured faster than at 3 waves per SIMD without spills (room orbit, 32
 // frames per launch: 7.87 against 7.57 G points/s).  Four frames need 158
-// VGPRs and run at 3 waves per SIMD without spilling: 7.66 against 8.65 G
-// points/s for three frames at 4 waves (at 4 waves four frames spill 152
-// bytes per lane).  Colour workgroups take more LDS, three per CU: no cap.
+// VGPRs and run at 3 waves per SIMD without spilling: 7.83 against 8.87 G
+// points/s for three frames at 4 waves (capped at 4 waves, an earlier build
+// of four frames spilled 152 bytes per lane; their 94 KB of code also
+// overflows the instruction cache).  Colour workgroups take more LDS, three
+// per CU: no cap.
 constexpr int waves_per_eu_for(int F, bool colour) {
   return colour ? 1 : F == 4 ? 3 : (F == 2 || F == 3) ? 4 : 1;
 }
